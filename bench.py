@@ -1,0 +1,225 @@
+#!/usr/bin/env python3
+"""Benchmark: adaptive Hook-Compress connected components on one MI355X.
+
+A step is one full solve (cc_labels through the C ABI) of the R-MAT scale-24
+graph (n = 2^24, edge factor 16, a/b/c/d = .57/.19/.19/.05, ids permuted,
+symmetrised: m = 2^29 int32 entries) with the edge list already resident in
+HBM.  Prints one JSON line:
+
+  value        edges/s = m / (wall time of one solve), averaged over the timed steps
+  roofline     the Atomic-Hook kernels (the dominant kernel): algorithmic bytes
+               (8 B per edge entry, each read once) / their summed duration,
+               measured with HIP events on the solve's stream, vs 8 TB/s
+  cpu_baseline the CPU oracle (sequential union-find, 1 thread) on the first
+               2^27 entries of the same edge list, in edges/s
+  batch        10,000 ER graphs in one cc_labels_batch call vs one cc_labels per graph
+
+Progress goes to stderr.  Options: --gpus N (only 1 is supported: the
+library runs on one GPU), --steps K, --warmup W, --workload NAME,
+--skip-cpu, --skip-batch.
+"""
+import argparse
+import hashlib
+import json
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+HBM_PEAK_GBS = 8000.0
+METRIC = "edges/s (|E|/solve time) + % HBM roofline; batched graphs/s and p99 latency"
+
+
+def log(*a):
+    print(*a, file=sys.stderr, flush=True)
+
+
+def digest(labels_np):
+    import numpy as np
+    return hashlib.sha256(np.ascontiguousarray(labels_np, dtype="<i4").tobytes()).hexdigest()
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=20)
+    ap.add_argument("--warmup", type=int, default=3)
+    ap.add_argument("--workload", default="rmat24", choices=["rmat24", "er16", "grid4k"])
+    ap.add_argument("--hook", default="atomic", choices=["atomic", "plain"])
+    ap.add_argument("--filter", default="auto", choices=["auto", "off", "giant"])
+    ap.add_argument("--segments", type=int, default=0)
+    ap.add_argument("--ept", type=int, default=0)
+    ap.add_argument("--block", type=int, default=0)
+    ap.add_argument("--profile-steps", type=int, default=3)
+    ap.add_argument("--skip-cpu", action="store_true")
+    ap.add_argument("--skip-batch", action="store_true")
+    args = ap.parse_args()
+
+    if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
+        print("bench.py: this solver runs on one GPU; --gpus %d is not supported "
+              "(multi-GPU sharding is a design note only)" % args.gpus, file=sys.stderr)
+        sys.exit(2)
+
+    import numpy as np
+    import torch
+
+    import graphgen
+    import paper_1612_01178_amd as cc
+
+    dev = torch.device("cuda:0")
+    cc.load()
+    opts = cc.Options(hook=args.hook, filter=args.filter, segments=args.segments,
+                      edges_per_thread=args.ept, block=args.block)
+
+    log("generating", args.workload)
+    t = time.time()
+    u_np, v_np, n = graphgen.workload(args.workload)
+    m = len(u_np)
+    log("generated n=%d m=%d in %.1fs" % (n, m, time.time() - t))
+    u = torch.from_numpy(u_np).to(dev)
+    v = torch.from_numpy(v_np).to(dev)
+    out = torch.empty(n, dtype=torch.int32, device=dev)
+    torch.cuda.synchronize()
+
+    for i in range(args.warmup):
+        cc.labels(u, v, n, out=out, options=opts)
+    torch.cuda.synchronize()
+    log("warmup done")
+    t0 = time.perf_counter()
+    for i in range(args.steps):
+        cc.labels(u, v, n, out=out, options=opts)
+    torch.cuda.synchronize()
+    t1 = time.perf_counter()
+    ms = (t1 - t0) * 1000.0 / max(args.steps, 1)
+    log("timed %d steps: %.3f ms/solve" % (args.steps, ms))
+
+    lab = out.cpu().numpy()
+    golden = json.load(open(os.path.join(ROOT, "tests", "golden", "oracle_digests.json")))
+    rec = golden.get(args.workload, {})
+    parity = bool(rec) and digest(lab) == rec.get("sha256")
+    comps = int(np.count_nonzero(lab == np.arange(n)))
+
+    # Per-kernel durations from HIP events recorded around every launch on
+    # the solve's stream (separate, profiled solves).
+    popts = cc.Options(**{**opts.__dict__, "profile": True})
+    hook_ms = comp_ms = other_ms = 0.0
+    st = None
+    for i in range(args.profile_steps):
+        _, st = cc.labels(u, v, n, out=out, options=popts, return_stats=True)
+        hook_ms += st["hook_ms"]
+        comp_ms += st["compress_ms"]
+        other_ms += st["other_ms"]
+    k = max(args.profile_steps, 1)
+    hook_ms, comp_ms, other_ms = hook_ms / k, comp_ms / k, other_ms / k
+    if args.hook == "atomic":
+        alg_bytes = 8.0 * m  # each int32 (u, v) entry read once across the Atomic-Hook launches
+        kernel = "k_ahook (all Atomic-Hook launches of one solve)"
+    else:
+        alg_bytes = 8.0 * m  # first Hook pass over the input entries
+        kernel = "k_hook_plain + k_compact (all edge passes of one solve)"
+    achieved = alg_bytes / (hook_ms * 1e-3) / 1e9 if hook_ms > 0 else 0.0
+    solve_bytes = 8.0 * m + 8.0 * n
+    log("profiled: hook %.3f ms, compress %.3f ms, other %.3f ms; stats %s"
+        % (hook_ms, comp_ms, other_ms, st))
+
+    result = {
+        "metric": METRIC,
+        "value": m / (ms * 1e-3),
+        "unit": "edges/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": ms,
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "int32",
+        "data": "synthetic (seeded generator, no dataset)",
+        "config": {"workload": args.workload, "n": n, "m_entries": m,
+                   "hook": args.hook, "filter": args.filter,
+                   "segments": st["segments"] if st else None,
+                   "filter_used": st["filter_used"] if st else None,
+                   "parallelism": "single GPU"},
+        "parity_vs_oracle_digest": parity,
+        "components": comps,
+        "roofline": {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS,
+                     "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": None,
+                     "kernel": kernel, "kernel_ms": round(hook_ms, 4),
+                     "alg_bytes_per_solve": alg_bytes},
+        "solve_roofline": {"alg_bytes": solve_bytes,
+                           "achieved_GBs": round(solve_bytes / (ms * 1e-3) / 1e9, 1),
+                           "frac": round(solve_bytes / (ms * 1e-3) / 1e9 / HBM_PEAK_GBS, 4)},
+        "phase_ms": {"hook": round(hook_ms, 4), "compress": round(comp_ms, 4),
+                     "other": round(other_ms, 4)},
+    }
+
+    if not args.skip_cpu:
+        import oracle
+        sample = min(m, 1 << 27)
+        log("cpu oracle on %d entries" % sample)
+        uu = np.ascontiguousarray(u_np[:sample])
+        vv = np.ascontiguousarray(v_np[:sample])
+        t = time.perf_counter()
+        oracle.labels(uu, vv, n)
+        dt = time.perf_counter() - t
+        result["cpu_baseline"] = {"value": sample / dt, "unit": "edges/s", "cores": 1,
+                                  "kind": "oracle",
+                                  "sample": "first %d of the %d entries of the same edge list, "
+                                            "all n=%d vertices; %.1f s" % (sample, m, n, dt),
+                                  "host_cpus": os.cpu_count()}
+        del uu, vv
+    del u_np, v_np
+
+    if not args.skip_batch:
+        result["batch"] = bench_batch(cc, torch, dev)
+
+    print(json.dumps(result), flush=True)
+
+
+def bench_batch(cc, torch, dev, num_graphs=10000, reps=5):
+    import numpy as np
+
+    import graphgen
+    log("generating batch of %d graphs" % num_graphs)
+    u_np, v_np, vo, eo = graphgen.batch_er(num_graphs, seed=1004)
+    u = torch.from_numpy(u_np).to(dev)
+    v = torch.from_numpy(v_np).to(dev)
+    out = torch.empty(int(vo[-1]), dtype=torch.int32, device=dev)
+    for _ in range(2):
+        cc.labels_batch(u, v, vo, eo, out=out)
+    torch.cuda.synchronize()
+    t = time.perf_counter()
+    for _ in range(reps):
+        cc.labels_batch(u, v, vo, eo, out=out)
+    torch.cuda.synchronize()
+    dt = (time.perf_counter() - t) / reps
+    lab = out.cpu().numpy()
+    golden = json.load(open(os.path.join(ROOT, "tests", "golden", "oracle_digests.json")))
+    parity = digest(lab) == golden["batch10k"]["sha256"]
+    # baseline: one synchronous cc_labels call per graph on the same resident data
+    lib = cc.load()
+    base_u, base_v, base_o = u.data_ptr(), v.data_ptr(), out.data_ptr()
+    torch.cuda.synchronize()
+    t = time.perf_counter()
+    for g in range(num_graphs):
+        e0 = int(eo[g])
+        rc = lib.cc_labels(int(vo[g + 1] - vo[g]), base_u + 4 * e0, base_v + 4 * e0,
+                           int(eo[g + 1] - e0), base_o + 4 * int(vo[g]))
+        if rc != 0:
+            raise RuntimeError(cc.last_error())
+    torch.cuda.synchronize()
+    dt_loop = time.perf_counter() - t
+    loop_parity = digest(out.cpu().numpy()) == golden["batch10k"]["sha256"]
+    m = int(eo[-1])
+    log("batch: %.3f ms per batch call, loop %.1f ms" % (dt * 1e3, dt_loop * 1e3))
+    return {"workload": "batch10k", "graphs": num_graphs, "n_total": int(vo[-1]), "m_total": m,
+            "graphs_per_s": num_graphs / dt, "edges_per_s": m / dt, "ms_per_batch": dt * 1e3,
+            "loop_graphs_per_s": num_graphs / dt_loop, "speedup_vs_loop": dt_loop / dt,
+            "parity_vs_oracle_digest": bool(parity and loop_parity),
+            "hbm_frac": round((8.0 * m + 4.0 * int(vo[-1])) / dt / 1e9 / HBM_PEAK_GBS, 4)}
+
+
+if __name__ == "__main__":
+    main()

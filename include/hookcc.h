@@ -1,0 +1,199 @@
+/*
+ * hookcc -- adaptive, work-efficient Hook-Compress connected components on
+ * AMD Instinct MI355X (gfx950).  C ABI of libhookcc.so.
+ *
+ * The operation (Section 2 of the paper, definition of connected components):
+ * for an undirected graph G = (V, E) with V = {0, ..., n-1}, give every vertex
+ * the id of a representative vertex of its component.  The representative is
+ * the SMALLEST vertex id of the component: every parent pointer the hooking
+ * kernels write goes from a larger id to a smaller one (the global
+ * high-to-low rule of Fig. 2 and Fig. 3), so each component tree's root is
+ * its minimum, and after the final Multi-Jump every vertex points at it.
+ * The result is therefore unique and exact: label[v] = min{ w : w ~ v }.
+ *
+ * Method (Section 3): the component-tree array pi (pi[v] = v initially) is
+ * built by Atomic-Hook over edge-list segments, each followed by a full
+ * Multi-Jump Compress (Fig. 3, Fig. 4), with s = max(1, round(m / n))
+ * segments by default (the average-degree heuristic of Section 3.B, with m
+ * the number of edge entries passed).  The atomic-free Hook of Fig. 2 is the
+ * alternative hook variant; its "repeat until Hook performs no change" loop
+ * (Fig. 1) runs with the convergence test and the shrinking frontier of
+ * still-active edges kept on the device.
+ *
+ * Conventions for every entry point:
+ *  - Array pointers marked [device] are device (HBM) memory of the current
+ *    HIP device, e.g. torch.Tensor.data_ptr() of a ROCm tensor.  The library
+ *    does not probe pointer kinds.  Pointers marked [host] are host memory.
+ *  - Vertex ids and labels are int32; edge counts and offsets are int64.
+ *  - Edges are given as two parallel arrays (structure of arrays): entry i is
+ *    the pair (edges_u[i], edges_v[i]).  Self-loops, repeated pairs and both
+ *    orientations of a pair are allowed and mean the same undirected edge.
+ *  - Input arrays are never written.  The caller owns every array it passes;
+ *    the library keeps no pointer after a call returns, apart from its own
+ *    cached workspace (freed by cc_release).
+ *  - Errors are returned as status codes (no exceptions cross the ABI);
+ *    cc_last_error() gives a message for the calling thread's last failure.
+ *  - On any non-zero status the contents of out_label are unspecified.
+ *  - Concurrent calls from different host threads are allowed; the library's
+ *    workspace cache is guarded by a mutex and keyed by stream.
+ */
+#ifndef HOOKCC_H
+#define HOOKCC_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+/* ------------------------------------------------------------------ status */
+#define CC_OK 0
+#define CC_ERR_ARG (-1)        /* null pointer with a non-zero length, n < 0, m < 0,
+                                  bad offsets, or an unknown option value        */
+#define CC_ERR_RANGE (-2)      /* an edge endpoint outside [0, n) (detected on the
+                                  device during the first pass over the edges)    */
+#define CC_ERR_NOMEM (-3)      /* workspace too small or device allocation failed */
+#define CC_ERR_HIP (-4)        /* a HIP runtime error (message in cc_last_error)  */
+#define CC_ERR_NOCONVERGE (-5) /* the atomic-free Hook hit opts->max_rounds       */
+
+/* ---------------------------------------------------------------- options */
+#define CC_HOOK_ATOMIC 0 /* Atomic-Hook (Fig. 3, CAS on roots) + segmentation (Fig. 4) */
+#define CC_HOOK_PLAIN 1  /* atomic-free Hook (Fig. 2) rounds until no change (Fig. 1),
+                            convergence test and active-edge frontier on the device   */
+
+#define CC_FILTER_OFF 0  /* Atomic-Hook only: hook every edge entry                   */
+#define CC_FILTER_GIANT 1 /* Atomic-Hook only: after the first segment(s), sample the
+                            labels, and when one component holds a large share of the
+                            samples, keep a bitmap of its vertices and skip every later
+                            edge whose two ends are both in it (exact: trees only
+                            merge, so such an edge is already satisfied)               */
+#define CC_FILTER_AUTO 2 /* library chooses (the default)                             */
+
+typedef struct cc_options {
+    int32_t hook;             /* CC_HOOK_ATOMIC (default) or CC_HOOK_PLAIN               */
+    int32_t segments;         /* Atomic-Hook: number of edge segments s; 0 = default
+                                 max(1, round(m / n)); clamped to [1, ceil(m / 4)]     */
+    int32_t filter;           /* CC_FILTER_* (Atomic-Hook only); default CC_FILTER_AUTO  */
+    int32_t filter_after;     /* segments hooked before the giant-component sample
+                                 (0 = default 1)                                        */
+    int32_t block;            /* threads per workgroup for the edge kernels: 64..1024,
+                                 multiple of 64; 0 = default 256                        */
+    int32_t edges_per_thread; /* edge entries per thread in the edge kernels: 4, 8 or 16;
+                                 0 = default                                            */
+    int32_t max_rounds;       /* atomic-free Hook: round cap (0 = n + 1, which is never
+                                 reached: every active round removes at least one root) */
+    int32_t rounds_per_check; /* atomic-free Hook: rounds launched between two host reads
+                                 of the device convergence word (0 = default 4)          */
+    int32_t profile;          /* 1 = time every kernel with HIP events on the call's stream
+                                 and report the phase times in cc_stats (adds a few
+                                 microseconds per launch); 0 = off                      */
+    int32_t reserved[7];      /* must be zero                                           */
+} cc_options;
+
+/* Fills *opts with the defaults (all fields zero = library choice). */
+void cc_options_init(cc_options* opts);
+
+/* Per-call statistics (optional output of cc_labels_ex). */
+typedef struct cc_stats {
+    int32_t hook;          /* variant that ran                                         */
+    int32_t segments;      /* Atomic-Hook: segments used                               */
+    int32_t filter_used;   /* 1 if the giant-component filter was active              */
+    int32_t rounds;        /* atomic-free Hook: Hook rounds run until no change        */
+    int64_t active_edges;  /* atomic-free Hook: edges still active after round 1       */
+    int32_t giant_label;   /* filter: label of the sampled giant component (or -1)     */
+    int32_t host_syncs;    /* host synchronisations made inside the call               */
+    int32_t hook_launches; /* edge-pass kernels launched (Atomic-Hook / Hook / compaction) */
+    int32_t compress_launches; /* Multi-Jump kernels launched                          */
+    float hook_ms;         /* opts->profile: summed durations of the edge-pass kernels   */
+    float compress_ms;     /* opts->profile: summed durations of the Multi-Jump kernels  */
+    float other_ms;        /* opts->profile: init, sample and bitmap kernels             */
+    int64_t reserved[4];
+} cc_stats;
+
+/* ------------------------------------------------------------- single graph */
+
+/* Min-id component labels of one graph; synchronous.
+ *   n          number of vertices (>= 0)
+ *   edges_u    [device] int32[m], endpoint 0 of each entry, in [0, n)
+ *   edges_v    [device] int32[m], endpoint 1 of each entry, in [0, n)
+ *   m          number of edge entries (>= 0)
+ *   out_label  [device] int32[n]; receives label[v] = min id of v's component
+ * Runs on the null stream with default options and returns after the labels
+ * are complete.  n == 0 returns CC_OK; m == 0 gives label[v] = v.
+ * Returns CC_OK, CC_ERR_ARG, CC_ERR_RANGE, CC_ERR_NOMEM or CC_ERR_HIP. */
+int32_t cc_labels(int32_t n, const int32_t* edges_u, const int32_t* edges_v, int64_t m,
+                  int32_t* out_label);
+
+/* As cc_labels, with options, caller workspace, stream and statistics.
+ *   opts             [host] options, or NULL for the defaults
+ *   workspace        [device] scratch of workspace_bytes bytes (256-byte aligned),
+ *                    or NULL to use the library's cached pool for this stream
+ *   workspace_bytes  size of workspace; must be >= cc_workspace_bytes(n, m, opts)
+ *   stream           hipStream_t to run on (NULL = null stream)
+ *   stats            [host] optional statistics output, or NULL
+ * The call returns after the labels are complete on `stream` (it ends with
+ * one stream synchronisation; the atomic-free Hook also reads the device
+ * convergence word once every opts->rounds_per_check rounds). */
+int32_t cc_labels_ex(int32_t n, const int32_t* edges_u, const int32_t* edges_v, int64_t m,
+                     int32_t* out_label, const cc_options* opts, void* workspace,
+                     size_t workspace_bytes, void* stream, cc_stats* stats);
+
+/* Device scratch bytes cc_labels_ex needs for (n, m, opts); 0 on bad input. */
+size_t cc_workspace_bytes(int32_t n, int64_t m, const cc_options* opts);
+
+/* ------------------------------------------------------------------ batches */
+
+/* Min-id labels of many independent graphs packed back to back; synchronous.
+ *   num_graphs  B >= 0
+ *   vtx_off     [host] int64[B+1]; graph g owns vertices [vtx_off[g], vtx_off[g+1]);
+ *               vtx_off[0] == 0, non-decreasing, each graph < 2^31 vertices
+ *   edge_off    [host] int64[B+1]; graph g owns entries [edge_off[g], edge_off[g+1]);
+ *               edge_off[0] == 0, non-decreasing
+ *   edges_u/v   [device] int32[edge_off[B]]; LOCAL endpoint ids in [0, n_g)
+ *   out_label   [device] int32[vtx_off[B]]; out_label[vtx_off[g] + x] receives the
+ *               local label (min local id of x's component within graph g)
+ * Graphs of at most CC_BATCH_LDS_MAX_N vertices are solved by one persistent
+ * launch whose workgroups take graphs from a device work queue, largest first,
+ * and keep each graph's tree array in LDS; larger graphs are solved in device
+ * memory.  Returns after every label is complete (null stream).
+ * Returns CC_OK, CC_ERR_ARG, CC_ERR_RANGE, CC_ERR_NOMEM or CC_ERR_HIP. */
+#define CC_BATCH_LDS_MAX_N 65536
+int32_t cc_labels_batch(int32_t num_graphs, const int64_t* vtx_off, const int64_t* edge_off,
+                        const int32_t* edges_u, const int32_t* edges_v, int32_t* out_label);
+
+/* As cc_labels_batch on `stream` (hipStream_t, NULL = null stream), using the
+ * library's workspace pool; `stats` may be NULL. */
+int32_t cc_labels_batch_ex(int32_t num_graphs, const int64_t* vtx_off, const int64_t* edge_off,
+                           const int32_t* edges_u, const int32_t* edges_v, int32_t* out_label,
+                           void* stream, cc_stats* stats);
+
+/* -------------------------------------------------------------- measurement */
+
+/* Memory-ceiling probe (measurement only, no labels).  Streams the m entries
+ * of edges_u/edges_v ([device], 16-byte aligned) with the tiling of the hook
+ * kernels and, for mode 1, also gathers table[u] and table[v] from the
+ * [device] int32[n] array `table`, or, for mode 2, tests bits u and v of the
+ * [device] n-bit bitmap `table` (uint32 words).  Entries with an endpoint
+ * outside [0, n) are skipped by modes 1 and 2.  Asynchronous on `stream`.
+ * Returns CC_OK, CC_ERR_ARG or CC_ERR_HIP. */
+int32_t cc_probe(int32_t mode, const int32_t* edges_u, const int32_t* edges_v, int64_t m,
+                 const void* table, int32_t n, void* stream);
+
+/* ------------------------------------------------------------------ library */
+
+/* Message for the calling thread's last non-zero status ("" if none). */
+const char* cc_last_error(void);
+
+/* Frees the library's cached device workspace (all streams).  Must not run
+ * concurrently with another call. */
+void cc_release(void);
+
+/* Library version string. */
+const char* cc_version(void);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* HOOKCC_H */

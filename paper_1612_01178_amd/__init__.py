@@ -1,0 +1,245 @@
+"""Adaptive, work-efficient Hook-Compress connected components on MI355X.
+
+Thin Python binding of ``libhookcc.so`` (C ABI in ``include/hookcc.h``):
+argument marshalling only.  Every step of a solve runs in the library's HIP
+kernels; PyTorch only provides device memory and streams.  There is no CPU
+fallback: if the library has not been built, every call raises.
+
+    import paper_1612_01178_amd as cc
+    lab = cc.labels(u, v, n)                       # u, v: int32 CUDA tensors
+    lab = cc.labels(u, v, n, options=cc.Options(hook="plain"))
+    lab = cc.labels_batch(u, v, vtx_off, edge_off) # host int64 offsets
+
+Labels are exact: label[x] is the smallest vertex id of x's component.
+"""
+from __future__ import annotations
+
+import ctypes
+import dataclasses
+import os
+import threading
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "libhookcc.so")
+
+CC_OK = 0
+CC_ERR_ARG = -1
+CC_ERR_RANGE = -2
+CC_ERR_NOMEM = -3
+CC_ERR_HIP = -4
+CC_ERR_NOCONVERGE = -5
+CC_BATCH_LDS_MAX_N = 65536
+
+_HOOKS = {"atomic": 0, "plain": 1}
+_FILTERS = {"off": 0, "giant": 1, "auto": 2}
+
+# Every symbol include/hookcc.h declares.
+EXPORTS = ("cc_options_init", "cc_labels", "cc_labels_ex", "cc_workspace_bytes",
+           "cc_labels_batch", "cc_labels_batch_ex", "cc_probe", "cc_last_error",
+           "cc_release", "cc_version")
+
+
+class CCError(RuntimeError):
+    def __init__(self, code: int, message: str):
+        super().__init__("hookcc status %d: %s" % (code, message))
+        self.code = code
+
+
+class _COptions(ctypes.Structure):
+    _fields_ = [("hook", ctypes.c_int32), ("segments", ctypes.c_int32),
+                ("filter", ctypes.c_int32), ("filter_after", ctypes.c_int32),
+                ("block", ctypes.c_int32), ("edges_per_thread", ctypes.c_int32),
+                ("max_rounds", ctypes.c_int32), ("rounds_per_check", ctypes.c_int32),
+                ("profile", ctypes.c_int32), ("reserved", ctypes.c_int32 * 7)]
+
+
+class _CStats(ctypes.Structure):
+    _fields_ = [("hook", ctypes.c_int32), ("segments", ctypes.c_int32),
+                ("filter_used", ctypes.c_int32), ("rounds", ctypes.c_int32),
+                ("active_edges", ctypes.c_int64), ("giant_label", ctypes.c_int32),
+                ("host_syncs", ctypes.c_int32), ("hook_launches", ctypes.c_int32),
+                ("compress_launches", ctypes.c_int32), ("hook_ms", ctypes.c_float),
+                ("compress_ms", ctypes.c_float), ("other_ms", ctypes.c_float),
+                ("reserved", ctypes.c_int64 * 4)]
+
+
+@dataclasses.dataclass
+class Options:
+    """Solver options (0 / "auto" = library default).  See cc_options in hookcc.h."""
+    hook: str = "atomic"
+    segments: int = 0
+    filter: str = "auto"
+    filter_after: int = 0
+    block: int = 0
+    edges_per_thread: int = 0
+    max_rounds: int = 0
+    rounds_per_check: int = 0
+    profile: bool = False
+
+    def _c(self) -> _COptions:
+        o = _COptions()
+        o.hook = _HOOKS[self.hook]
+        o.segments = self.segments
+        o.filter = _FILTERS[self.filter]
+        o.filter_after = self.filter_after
+        o.block = self.block
+        o.edges_per_thread = self.edges_per_thread
+        o.max_rounds = self.max_rounds
+        o.rounds_per_check = self.rounds_per_check
+        o.profile = 1 if self.profile else 0
+        return o
+
+
+_lib = None
+_lock = threading.Lock()
+_vp = ctypes.c_void_p
+_i32 = ctypes.c_int32
+_i64 = ctypes.c_int64
+
+
+def load():
+    """The loaded libhookcc.so; raises if it has not been built."""
+    global _lib
+    with _lock:
+        if _lib is None:
+            if not os.path.exists(LIB_PATH):
+                raise RuntimeError("libhookcc.so is not built (run __graft_entry__.build() or "
+                                   "python paper_1612_01178_amd/build.py); there is no fallback")
+            lib = ctypes.CDLL(LIB_PATH)
+            lib.cc_options_init.argtypes = [ctypes.POINTER(_COptions)]
+            lib.cc_options_init.restype = None
+            lib.cc_labels.argtypes = [_i32, _vp, _vp, _i64, _vp]
+            lib.cc_labels.restype = _i32
+            lib.cc_labels_ex.argtypes = [_i32, _vp, _vp, _i64, _vp, ctypes.POINTER(_COptions),
+                                         _vp, ctypes.c_size_t, _vp, ctypes.POINTER(_CStats)]
+            lib.cc_labels_ex.restype = _i32
+            lib.cc_workspace_bytes.argtypes = [_i32, _i64, ctypes.POINTER(_COptions)]
+            lib.cc_workspace_bytes.restype = ctypes.c_size_t
+            lib.cc_labels_batch.argtypes = [_i32, _vp, _vp, _vp, _vp, _vp]
+            lib.cc_labels_batch.restype = _i32
+            lib.cc_labels_batch_ex.argtypes = [_i32, _vp, _vp, _vp, _vp, _vp, _vp,
+                                               ctypes.POINTER(_CStats)]
+            lib.cc_labels_batch_ex.restype = _i32
+            lib.cc_probe.argtypes = [_i32, _vp, _vp, _i64, _vp, _i32, _vp]
+            lib.cc_probe.restype = _i32
+            lib.cc_last_error.argtypes = []
+            lib.cc_last_error.restype = ctypes.c_char_p
+            lib.cc_release.argtypes = []
+            lib.cc_release.restype = None
+            lib.cc_version.argtypes = []
+            lib.cc_version.restype = ctypes.c_char_p
+            _lib = lib
+    return _lib
+
+
+def last_error() -> str:
+    return load().cc_last_error().decode()
+
+
+def version() -> str:
+    return load().cc_version().decode()
+
+
+def release() -> None:
+    load().cc_release()
+
+
+def _check(rc: int) -> None:
+    if rc != CC_OK:
+        raise CCError(rc, last_error())
+
+
+def _stream_handle(stream):
+    import torch
+    if stream is None:
+        stream = torch.cuda.current_stream()
+    return ctypes.c_void_p(int(stream.cuda_stream))
+
+
+def _edge_tensor(x, name):
+    import torch
+    if not isinstance(x, torch.Tensor) or x.dtype != torch.int32 or x.device.type != "cuda":
+        raise TypeError("%s must be an int32 CUDA tensor" % name)
+    if x.dim() != 1 or not x.is_contiguous():
+        raise ValueError("%s must be 1-D and contiguous" % name)
+    return x
+
+
+def labels(u, v, n: int, *, out=None, options: Options | None = None, stream=None,
+           workspace=None, return_stats: bool = False):
+    """Min-id component labels (int32 CUDA tensor of length n) of the graph
+    with edge entries (u[i], v[i]).  Synchronous on ``stream`` (default: the
+    current torch stream)."""
+    import torch
+    u = _edge_tensor(u, "u")
+    v = _edge_tensor(v, "v")
+    if u.numel() != v.numel():
+        raise ValueError("u and v differ in length")
+    if out is None:
+        out = torch.empty(max(int(n), 0), dtype=torch.int32, device=u.device)
+    else:
+        out = _edge_tensor(out, "out")
+        if out.numel() < n:
+            raise ValueError("out is shorter than n")
+    opts = (options or Options())._c()
+    st = _CStats()
+    ws_ptr, ws_bytes = None, 0
+    if workspace is not None:
+        ws_ptr, ws_bytes = workspace.data_ptr(), workspace.numel() * workspace.element_size()
+    with torch.cuda.device(u.device):
+        rc = load().cc_labels_ex(int(n), u.data_ptr(), v.data_ptr(), u.numel(), out.data_ptr(),
+                                 ctypes.byref(opts), ws_ptr, ws_bytes, _stream_handle(stream),
+                                 ctypes.byref(st))
+    _check(rc)
+    if return_stats:
+        return out, {f: getattr(st, f) for f, _ in _CStats._fields_ if f != "reserved"}
+    return out
+
+
+def labels_raw(n: int, u_ptr: int, v_ptr: int, m: int, out_ptr: int) -> int:
+    """cc_labels on raw device pointers (null stream); returns the status."""
+    return int(load().cc_labels(int(n), u_ptr, v_ptr, int(m), out_ptr))
+
+
+def workspace_bytes(n: int, m: int, options: Options | None = None) -> int:
+    opts = (options or Options())._c()
+    return int(load().cc_workspace_bytes(int(n), int(m), ctypes.byref(opts)))
+
+
+def labels_batch(u, v, vtx_off, edge_off, *, out=None, stream=None, return_stats: bool = False):
+    """Per-graph local min-id labels of graphs packed back to back.
+
+    ``u``/``v`` are int32 CUDA tensors of local ids; ``vtx_off``/``edge_off``
+    are host int64 arrays of length B+1.  Returns an int32 CUDA tensor of
+    length vtx_off[-1]."""
+    import numpy as np
+    import torch
+    u = _edge_tensor(u, "u")
+    v = _edge_tensor(v, "v")
+    vo = np.ascontiguousarray(np.asarray(vtx_off, dtype=np.int64))
+    eo = np.ascontiguousarray(np.asarray(edge_off, dtype=np.int64))
+    if vo.ndim != 1 or eo.shape != vo.shape or len(vo) < 1:
+        raise ValueError("vtx_off and edge_off must be 1-D of equal length B+1")
+    if eo[-1] != u.numel() or u.numel() != v.numel():
+        raise ValueError("edge_off[-1] must equal len(u) == len(v)")
+    total = int(vo[-1])
+    if out is None:
+        out = torch.empty(total, dtype=torch.int32, device=u.device)
+    st = _CStats()
+    with torch.cuda.device(u.device):
+        rc = load().cc_labels_batch_ex(len(vo) - 1, vo.ctypes.data, eo.ctypes.data, u.data_ptr(),
+                                       v.data_ptr(), out.data_ptr(), _stream_handle(stream),
+                                       ctypes.byref(st))
+    _check(rc)
+    if return_stats:
+        return out, {f: getattr(st, f) for f, _ in _CStats._fields_ if f != "reserved"}
+    return out
+
+
+def probe(mode: int, u, v, table=None, n: int = 0, stream=None) -> None:
+    """Asynchronous memory-ceiling probe (see cc_probe in hookcc.h)."""
+    u = _edge_tensor(u, "u")
+    v = _edge_tensor(v, "v")
+    tp = table.data_ptr() if table is not None else None
+    _check(load().cc_probe(int(mode), u.data_ptr(), v.data_ptr(), u.numel(), tp, int(n),
+                           _stream_handle(stream)))

@@ -1,0 +1,60 @@
+// Internal definitions shared by the HIP kernels and the host engine of
+// libhookcc.  Not part of the public ABI (include/hookcc.h is).
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <cstdint>
+
+namespace hookcc {
+
+// Device control block, the first 256 bytes of every workspace.
+// Written and read only by the kernels, except that the host zeroes it at the
+// start of a solve (through the init kernel) and reads it once at the end.
+struct Ctrl {
+    int32_t status;       // bit 0: an endpoint outside [0, n); bit 1: frontier overflow
+    int32_t giant;        // sampled giant-component label (-1 = none)
+    int32_t filter_on;    // 1 when the giant-component bitmap is valid and worth using
+    int32_t rounds;       // atomic-free Hook: rounds that found an active edge
+    uint32_t count[2];    // atomic-free Hook: frontier sizes, ping-pong by round parity
+    uint32_t nofilter;    // giant sample: 1 when no component is large enough to filter
+    int32_t queue_head;   // batched solve: next position of the graph work queue
+    int64_t active_round1;  // atomic-free Hook: frontier size after round 1
+    int32_t pad[54];
+};
+static_assert(sizeof(Ctrl) == 256, "control block is one 256-byte line");
+
+constexpr int32_t kStatusRange = 1;
+constexpr int32_t kStatusOverflow = 2;
+
+// Graph descriptor used by the batched kernels (one per graph, in device
+// memory).  Endpoints are local ids in [0, n); labels are local.
+struct GraphDesc {
+    const int32_t* u;
+    const int32_t* v;
+    int32_t* out;
+    int64_t m;
+    int32_t n;
+    int32_t segments;
+};
+static_assert(sizeof(GraphDesc) == 40, "descriptor layout");
+
+// Relaxed atomic accesses of the tree array.  The races on pi are part of the
+// method (concurrent hooks and jumps, Section 3): every value a load can
+// return is some ancestor of the vertex, which is all the algorithm needs, and
+// the atomic forms keep the compiler from caching, merging or dropping the
+// accesses inside the climbing loops.  Agent scope: the kernels of one solve
+// run on every CU of the device.
+__device__ __forceinline__ int32_t ld_rlx(const int32_t* p) {
+    return __hip_atomic_load(p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+__device__ __forceinline__ void st_rlx(int32_t* p, int32_t x) {
+    __hip_atomic_store(p, x, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+__device__ __forceinline__ int32_t cas_rlx(int32_t* p, int32_t expected, int32_t desired) {
+    __hip_atomic_compare_exchange_strong(p, &expected, desired, __ATOMIC_RELAXED,
+                                         __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    return expected;  // the value found (== the old expected on success)
+}
+
+}  // namespace hookcc

@@ -1,0 +1,61 @@
+// Host-side launchers of the HIP kernels (internal to libhookcc).
+#pragma once
+
+#include "common.hpp"
+
+namespace hookcc {
+
+// pi[v] = v for v < n; resets the control block.  (Fig. 4, first step.)
+hipError_t launch_init(int32_t* pi, int32_t n, Ctrl* ctrl, hipStream_t s);
+
+// Atomic-Hook (Fig. 3) of entries [begin, end).  When `bits` is non-null the
+// giant-component filter is applied (only if ctrl->filter_on is set).
+hipError_t launch_ahook(const int32_t* u, const int32_t* v, int64_t begin, int64_t end,
+                        int32_t* pi, int32_t n, Ctrl* ctrl, const uint32_t* bits, int block,
+                        int ept, hipStream_t s);
+
+// Multi-Jump (Fig. 3) over all n vertices.  When `gate` is non-null the
+// kernel does nothing if *gate == 0.
+hipError_t launch_mj(int32_t* pi, int32_t n, const uint32_t* gate, hipStream_t s);
+
+// Giant-component sample: label of the component that holds the most of
+// `samples` edge endpoints drawn across entries [0, m); sets ctrl->giant and
+// ctrl->filter_on.  Requires pi to be a forest of stars (after Multi-Jump).
+hipError_t launch_sample_giant(const int32_t* u, int64_t m, const int32_t* pi, int32_t n,
+                               Ctrl* ctrl, int samples, hipStream_t s);
+
+// bits[v] = (pi[v] == pi[ctrl->giant]) for v < n (stars required); no-op
+// unless ctrl->filter_on.
+hipError_t launch_bitmap(const int32_t* pi, int32_t n, Ctrl* ctrl, uint32_t* bits, hipStream_t s);
+
+// Atomic-free Hook (Fig. 2) of round `round` (1-based).  Round 1 reads the
+// input entries [0, m) and checks ranges; later rounds read the frontier of
+// root pairs written by the previous round's compaction (size in ctrl->count).
+hipError_t launch_hook_plain(int round, const int32_t* u, const int32_t* v, int64_t m,
+                             const int2* frontier, int32_t* pi, int32_t n, Ctrl* ctrl, int block,
+                             int ept, int grid_cap, hipStream_t s);
+
+// Frontier compaction after the Compress of round `round`: keeps the entries
+// whose endpoints still have different roots, written as root pairs to
+// `dst` (capacity cap), size accumulated in ctrl->count[round & 1].
+hipError_t launch_compact(int round, const int32_t* u, const int32_t* v, int64_t m,
+                          const int2* src, int2* dst, int64_t cap, const int32_t* pi, int32_t n,
+                          Ctrl* ctrl, int block, int ept, int grid_cap, hipStream_t s);
+
+// Streaming and gather probes used to measure the memory ceilings.
+hipError_t launch_probe_stream(const int32_t* u, const int32_t* v, int64_t m, uint32_t* sink,
+                               hipStream_t s);
+hipError_t launch_probe_gather(const int32_t* u, const int32_t* v, int64_t m, const int32_t* table,
+                               int32_t n, uint32_t* sink, hipStream_t s);
+hipError_t launch_probe_bitgather(const int32_t* u, const int32_t* v, int64_t m,
+                                  const uint32_t* bits, int32_t n, uint32_t* sink, hipStream_t s);
+
+// Batched solve: one workgroup per graph, tree array in LDS, graphs taken
+// from a device work queue in the order of `order`.
+hipError_t launch_batch_lds(const GraphDesc* descs, const int32_t* order, int32_t count,
+                            int32_t max_n, int32_t* queue_head, int32_t* status, int grid,
+                            hipStream_t s);
+
+int device_cu_count();
+
+}  // namespace hookcc

@@ -1,0 +1,122 @@
+// Batched solve of many small graphs in one persistent launch (CDNA4).
+//
+// One workgroup (1024 threads, 16 waves) per CU takes graphs from a device
+// work queue (an atomic counter over a host-sorted order, largest first) and
+// solves each one entirely in LDS: the graph's tree array pi lives in LDS as
+// 16-bit local ids (n <= 65536 -> at most 128 KiB of the 160 KiB LDS), the
+// edge entries are streamed once from HBM, and the labels are written once.
+// Per graph the schedule is the paper's adaptive one (Fig. 4): for each of
+// the graph's s edge segments, Atomic-Hook the segment, then Multi-Jump all
+// its vertices, with a workgroup barrier between phases.
+#include "kernels.hpp"
+
+namespace hookcc {
+
+// 16-bit compare-and-swap in LDS, built on the 32-bit CAS of the containing
+// word: succeeds iff slot `idx` holds `expected`; returns the value found.
+// The other half-word may change concurrently; the loop then retries with
+// the fresh word, so only a change of this half-word can make it fail.
+__device__ __forceinline__ uint32_t lds_cas16(uint16_t* spi, uint32_t idx, uint32_t expected,
+                                              uint32_t desired) {
+    uint32_t* w = reinterpret_cast<uint32_t*>(spi) + (idx >> 1);
+    const uint32_t sh = (idx & 1) * 16;
+    uint32_t old = __hip_atomic_load(w, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
+    while (true) {
+        const uint32_t cur = (old >> sh) & 0xffffu;
+        if (cur != expected) return cur;
+        const uint32_t nw = (old & ~(0xffffu << sh)) | (desired << sh);
+        const uint32_t prev = atomicCAS(w, old, nw);
+        if (prev == old) return expected;
+        old = prev;
+    }
+}
+
+__device__ __forceinline__ uint32_t lds_ld16(const uint16_t* spi, uint32_t idx) {
+    return *reinterpret_cast<const volatile uint16_t*>(spi + idx);
+}
+__device__ __forceinline__ void lds_st16(uint16_t* spi, uint32_t idx, uint32_t x) {
+    *reinterpret_cast<volatile uint16_t*>(spi + idx) = (uint16_t)x;
+}
+
+// Atomic-Hook in LDS (Fig. 3, top), same steps as the device-memory kernel.
+__device__ __forceinline__ void lds_atomic_hook(uint16_t* spi, uint32_t pu, uint32_t pv) {
+    while (pu != pv) {
+        const uint32_t H = pu > pv ? pu : pv;
+        const uint32_t L = pu > pv ? pv : pu;
+        const uint32_t found = lds_cas16(spi, H, H, L);
+        if (found == H) return;
+        pu = lds_ld16(spi, found);
+        pv = lds_ld16(spi, L);
+    }
+}
+
+__global__ __launch_bounds__(1024) void k_batch_lds(const GraphDesc* __restrict__ descs,
+                                                    const int32_t* __restrict__ order,
+                                                    int32_t count, int32_t* queue_head,
+                                                    int32_t* status) {
+    extern __shared__ uint16_t spi[];
+    __shared__ int32_t next;
+    const uint32_t tid = threadIdx.x;
+    const uint32_t nthr = blockDim.x;
+    while (true) {
+        if (tid == 0) next = atomicAdd(queue_head, 1);
+        __syncthreads();
+        const int32_t idx = next;
+        __syncthreads();  // everyone has read `next` before thread 0 may overwrite it
+        if (idx >= count) break;
+        const GraphDesc d = descs[order[idx]];
+        const uint32_t n = (uint32_t)d.n;
+        for (uint32_t x = tid; x < n; x += nthr) lds_st16(spi, x, x);
+        __syncthreads();
+        bool bad = false;
+        const int32_t s = d.segments > 0 ? d.segments : 1;
+        for (int32_t seg = 0; seg < s; ++seg) {
+            const int64_t b0 = d.m * seg / s, b1 = d.m * (seg + 1) / s;
+            for (int64_t e = b0 + tid; e < b1; e += nthr) {
+                const int32_t a = __builtin_nontemporal_load(d.u + e);
+                const int32_t b = __builtin_nontemporal_load(d.v + e);
+                if ((uint32_t)a >= n || (uint32_t)b >= n) {
+                    bad = true;
+                    continue;
+                }
+                if (a == b) continue;
+                lds_atomic_hook(spi, lds_ld16(spi, a), lds_ld16(spi, b));
+            }
+            __syncthreads();
+            // Multi-Jump (Fig. 3, bottom) over the graph's vertices, low ids first.
+            for (uint32_t x = tid; x < n; x += nthr) {
+                uint32_t p = lds_ld16(spi, x);
+                if (p == x) continue;
+                uint32_t g = lds_ld16(spi, p);
+                while (g != p) {
+                    lds_st16(spi, x, g);
+                    p = g;
+                    g = lds_ld16(spi, p);
+                }
+            }
+            __syncthreads();
+        }
+        if (bad) atomicOr(status, kStatusRange);
+        for (uint32_t x = tid; x < n; x += nthr) d.out[x] = (int32_t)lds_ld16(spi, x);
+        __syncthreads();
+    }
+}
+
+hipError_t launch_batch_lds(const GraphDesc* descs, const int32_t* order, int32_t count,
+                            int32_t max_n, int32_t* queue_head, int32_t* status, int grid,
+                            hipStream_t s) {
+    if (count <= 0) return hipSuccess;
+    if (max_n < 1 || max_n > 65536) return hipErrorInvalidValue;
+    const size_t lds = (((size_t)max_n + 1) / 2) * 4;  // whole 32-bit words
+    static bool attr_set = false;
+    if (!attr_set) {
+        hipError_t e = hipFuncSetAttribute(reinterpret_cast<const void*>(&k_batch_lds),
+                                           hipFuncAttributeMaxDynamicSharedMemorySize, 65536 * 2);
+        if (e != hipSuccess) return e;
+        attr_set = true;
+    }
+    k_batch_lds<<<grid, 1024, lds, s>>>(descs, order, count, queue_head, status);
+    return hipGetLastError();
+}
+
+}  // namespace hookcc

@@ -1,0 +1,597 @@
+// Core kernels of the adaptive Hook-Compress solver for CDNA4 (gfx950).
+//
+//   k_init        pi[v] = v                                   (Fig. 4, first step)
+//   k_ahook       Atomic-Hook over an edge segment            (Fig. 3, top)
+//   k_mj          Multi-Jump: a whole Compress in one launch  (Fig. 3, bottom)
+//   k_sample      giant-component label from sampled endpoints
+//   k_bitmap      bitmap of the giant component's vertices
+//   k_hook_plain  atomic-free Hook                            (Fig. 2)
+//   k_compact     frontier compaction of still-active edges
+//
+// Nothing here is a dense contraction, so there is no MFMA: the kernels are
+// bound by the coalesced int32 edge stream from HBM and by random 4-byte
+// gathers of the tree array pi (L2 / Infinity Cache).  Edge entries are read
+// with 16-byte non-temporal vector loads so the stream does not evict pi from
+// the caches; tree accesses are relaxed agent-scope atomics (see common.hpp).
+#include "kernels.hpp"
+
+namespace hookcc {
+
+typedef int32_t v4i __attribute__((ext_vector_type(4)));
+typedef uint32_t v2u __attribute__((ext_vector_type(2)));
+
+// ----------------------------------------------------------------------------- helpers
+// Number of set bits of `mask` in lanes below this one (wave64 lane prefix).
+__device__ __forceinline__ uint32_t lane_prefix(uint64_t mask) {
+    return __builtin_amdgcn_mbcnt_hi((uint32_t)(mask >> 32),
+                                     __builtin_amdgcn_mbcnt_lo((uint32_t)mask, 0u));
+}
+
+// Loads EPT entries of one edge array for this thread: EPT/4 groups of 4
+// consecutive entries, group k at e0 + k * stride.  Slots outside [.., end)
+// read as vertex 0 and are reported in `valid`.
+template <int EPT, bool VEC>
+__device__ __forceinline__ void load_edges(const int32_t* __restrict__ p, int64_t e0, int64_t stride,
+                                           int64_t end, int32_t (&x)[EPT]) {
+#pragma unroll
+    for (int k = 0; k < EPT / 4; ++k) {
+        const int64_t e = e0 + k * stride;
+        if (VEC && e + 3 < end) {
+            v4i q = __builtin_nontemporal_load(reinterpret_cast<const v4i*>(p + e));
+            x[4 * k + 0] = q.x;
+            x[4 * k + 1] = q.y;
+            x[4 * k + 2] = q.z;
+            x[4 * k + 3] = q.w;
+        } else {
+#pragma unroll
+            for (int j = 0; j < 4; ++j)
+                x[4 * k + j] = (e + j < end) ? __builtin_nontemporal_load(p + e + j) : 0;
+        }
+    }
+}
+
+// Atomic-Hook of one edge whose endpoints' current parents are (pu, pv)
+// (Fig. 3, top; Section 3.A).  While the two parents differ, the larger one,
+// H, is hooked under the smaller one, L, by a compare-and-swap that succeeds
+// only if H is still a root (pi[H] == H), so no existing link is ever
+// overwritten.  When the CAS fails, H already has a parent; the pair to join
+// becomes (parent of the value found at pi[H], parent of L), one level up.
+// Every value written is smaller than the slot's index, so no cycle can form,
+// and the loop ends because max(pu, pv) strictly decreases.
+__device__ __forceinline__ void atomic_hook(int32_t* pi, int32_t pu, int32_t pv) {
+    while (pu != pv) {
+        const int32_t H = pu > pv ? pu : pv;
+        const int32_t L = pu > pv ? pv : pu;
+        const int32_t found = cas_rlx(pi + H, H, L);
+        if (found == H) return;
+        pu = ld_rlx(pi + found);
+        pv = ld_rlx(pi + L);
+    }
+}
+
+// ----------------------------------------------------------------------------- K-INIT
+template <bool VEC>
+__global__ __launch_bounds__(256) void k_init(int32_t* __restrict__ pi, int32_t n, Ctrl* ctrl) {
+    const int64_t base = ((int64_t)blockIdx.x * blockDim.x + threadIdx.x) * 4;
+    if (VEC && base + 3 < n) {
+        v4i q = {(int32_t)base, (int32_t)base + 1, (int32_t)base + 2, (int32_t)base + 3};
+        *reinterpret_cast<v4i*>(pi + base) = q;
+    } else {
+#pragma unroll
+        for (int j = 0; j < 4; ++j)
+            if (base + j < n) pi[base + j] = (int32_t)(base + j);
+    }
+    if (blockIdx.x == 0 && threadIdx.x < sizeof(Ctrl) / 4) {
+        // status, giant (-1), filter_on, rounds, counts, ... all zero
+        reinterpret_cast<int32_t*>(ctrl)[threadIdx.x] = (threadIdx.x == 1) ? -1 : 0;
+    }
+}
+
+hipError_t launch_init(int32_t* pi, int32_t n, Ctrl* ctrl, hipStream_t s) {
+    const int64_t groups = ((int64_t)n + 3) / 4;
+    const int grid = (int)((groups + 255) / 256 > 0 ? (groups + 255) / 256 : 1);
+    if (((uintptr_t)pi & 15) == 0)
+        k_init<true><<<grid, 256, 0, s>>>(pi, n, ctrl);
+    else
+        k_init<false><<<grid, 256, 0, s>>>(pi, n, ctrl);
+    return hipGetLastError();
+}
+
+// ----------------------------------------------------------------------------- K-AHOOK
+// Each thread takes EPT entries of [begin, end): EPT/4 groups of 4 consecutive
+// entries, consecutive lanes on consecutive groups (fully coalesced 16-byte
+// loads).  All 2*EPT parent gathers are issued before any climbing so that
+// their latencies overlap.  Endpoints outside [0, n) raise the range bit of
+// the status word and are skipped.
+//
+// FILTER: when ctrl->filter_on, bit v of `bits` says v's tree contained the
+// giant component's sampled root g when the bitmap was built; trees only
+// merge, so v stays joined to g.  An entry with both bits set is already
+// satisfied and is skipped; an endpoint with its bit set starts its climb at
+// g instead of gathering pi (any vertex of the endpoint's tree is a valid
+// start for Atomic-Hook, since only tree membership matters).
+template <int EPT, bool VEC, bool FILTER>
+__global__ __launch_bounds__(1024) void k_ahook(const int32_t* __restrict__ eu,
+                                                const int32_t* __restrict__ ev, int64_t begin,
+                                                int64_t end, int32_t* pi, int32_t n, Ctrl* ctrl,
+                                                const uint32_t* __restrict__ bits) {
+    const int64_t stride = (int64_t)blockDim.x * 4;
+    const int64_t e0 = begin + (int64_t)blockIdx.x * blockDim.x * EPT + (int64_t)threadIdx.x * 4;
+    int32_t a[EPT], b[EPT];
+    load_edges<EPT, VEC>(eu, e0, stride, end, a);
+    load_edges<EPT, VEC>(ev, e0, stride, end, b);
+
+    uint32_t act = 0;
+    bool bad = false;
+#pragma unroll
+    for (int j = 0; j < EPT; ++j) {
+        const bool in = (uint32_t)a[j] < (uint32_t)n && (uint32_t)b[j] < (uint32_t)n;
+        bad |= !in;
+        if (in && a[j] != b[j]) act |= 1u << j;
+    }
+    if (bad) atomicOr(&ctrl->status, kStatusRange);
+
+    int32_t pa[EPT], pb[EPT];
+    if (FILTER && ctrl->filter_on) {
+        const int32_t g = ctrl->giant;
+#pragma unroll
+        for (int j = 0; j < EPT; ++j) {
+            if (act >> j & 1) {
+                const uint32_t ba = bits[(uint32_t)a[j] >> 5] >> (a[j] & 31) & 1;
+                const uint32_t bb = bits[(uint32_t)b[j] >> 5] >> (b[j] & 31) & 1;
+                if (ba & bb) {
+                    act &= ~(1u << j);
+                } else {
+                    pa[j] = ba ? g : ld_rlx(pi + a[j]);
+                    pb[j] = bb ? g : ld_rlx(pi + b[j]);
+                }
+            }
+        }
+    } else {
+#pragma unroll
+        for (int j = 0; j < EPT; ++j) {
+            if (act >> j & 1) {
+                pa[j] = ld_rlx(pi + a[j]);
+                pb[j] = ld_rlx(pi + b[j]);
+            }
+        }
+    }
+#pragma unroll
+    for (int j = 0; j < EPT; ++j)
+        if (act >> j & 1) atomic_hook(pi, pa[j], pb[j]);
+}
+
+template <int EPT, bool FILTER>
+static void ahook_dispatch(bool vec, int grid, int block, hipStream_t s, const int32_t* u,
+                           const int32_t* v, int64_t begin, int64_t end, int32_t* pi, int32_t n,
+                           Ctrl* ctrl, const uint32_t* bits) {
+    if (vec)
+        k_ahook<EPT, true, FILTER><<<grid, block, 0, s>>>(u, v, begin, end, pi, n, ctrl, bits);
+    else
+        k_ahook<EPT, false, FILTER><<<grid, block, 0, s>>>(u, v, begin, end, pi, n, ctrl, bits);
+}
+
+static bool aligned16(const void* p) { return ((uintptr_t)p & 15) == 0; }
+
+hipError_t launch_ahook(const int32_t* u, const int32_t* v, int64_t begin, int64_t end,
+                        int32_t* pi, int32_t n, Ctrl* ctrl, const uint32_t* bits, int block,
+                        int ept, hipStream_t s) {
+    if (end <= begin) return hipSuccess;
+    const int64_t tile = (int64_t)block * ept;
+    const int64_t grid64 = (end - begin + tile - 1) / tile;
+    if (grid64 > 0x7fffffff) return hipErrorInvalidValue;
+    const int grid = (int)grid64;
+    const bool vec = aligned16(u + begin) && aligned16(v + begin);
+    const bool f = bits != nullptr;
+    switch (ept) {
+        case 4:
+            f ? ahook_dispatch<4, true>(vec, grid, block, s, u, v, begin, end, pi, n, ctrl, bits)
+              : ahook_dispatch<4, false>(vec, grid, block, s, u, v, begin, end, pi, n, ctrl, bits);
+            break;
+        case 8:
+            f ? ahook_dispatch<8, true>(vec, grid, block, s, u, v, begin, end, pi, n, ctrl, bits)
+              : ahook_dispatch<8, false>(vec, grid, block, s, u, v, begin, end, pi, n, ctrl, bits);
+            break;
+        case 16:
+            f ? ahook_dispatch<16, true>(vec, grid, block, s, u, v, begin, end, pi, n, ctrl, bits)
+              : ahook_dispatch<16, false>(vec, grid, block, s, u, v, begin, end, pi, n, ctrl, bits);
+            break;
+        default:
+            return hipErrorInvalidValue;
+    }
+    return hipGetLastError();
+}
+
+// ----------------------------------------------------------------------------- K-MJ
+// Multi-Jump (Fig. 3, bottom): for every vertex, while its grandparent
+// differs from its parent, replace the parent by the grandparent.  The new
+// parent is stored on every step, not once at the end, so that other threads
+// climbing through this vertex see the shortened path at once (the first of
+// the two optimisations of Section 3.A).  Workgroups cover the vertex range in
+// increasing id order, so the low ids near the roots are flattened first (the
+// second optimisation; the hardware dispatches workgroups in index order).
+// Each thread handles 4 consecutive vertices from one 16-byte load; roots are
+// skipped at once; the 4 grandparent gathers are issued together.
+//
+// During a Multi-Jump no root changes (only non-roots are written, and only
+// with ancestors), so "grandparent == parent" holds exactly when the parent is
+// a root: on exit every vertex points at its tree's root, i.e. at the minimum
+// id of its tree.
+template <bool VEC>
+__global__ __launch_bounds__(256) void k_mj(int32_t* pi, int32_t n, const uint32_t* gate) {
+    if (gate != nullptr && *gate == 0) return;
+    const int64_t base = ((int64_t)blockIdx.x * blockDim.x + threadIdx.x) * 4;
+    int32_t p[4];
+    if (VEC && base + 3 < n) {
+        v4i q = *reinterpret_cast<const v4i*>(pi + base);
+        p[0] = q.x;
+        p[1] = q.y;
+        p[2] = q.z;
+        p[3] = q.w;
+    } else {
+#pragma unroll
+        for (int j = 0; j < 4; ++j) p[j] = (base + j < n) ? ld_rlx(pi + base + j) : (int32_t)(base + j);
+    }
+    int32_t gp[4];
+#pragma unroll
+    for (int j = 0; j < 4; ++j) gp[j] = (p[j] != base + j) ? ld_rlx(pi + p[j]) : p[j];
+#pragma unroll
+    for (int j = 0; j < 4; ++j) {
+        int32_t q = p[j], g = gp[j];
+        while (g != q) {
+            st_rlx(pi + base + j, g);
+            q = g;
+            g = ld_rlx(pi + q);
+        }
+    }
+}
+
+hipError_t launch_mj(int32_t* pi, int32_t n, const uint32_t* gate, hipStream_t s) {
+    if (n <= 0) return hipSuccess;
+    const int64_t groups = ((int64_t)n + 3) / 4;
+    const int grid = (int)((groups + 255) / 256);
+    if (((uintptr_t)pi & 15) == 0)
+        k_mj<true><<<grid, 256, 0, s>>>(pi, n, gate);
+    else
+        k_mj<false><<<grid, 256, 0, s>>>(pi, n, gate);
+    return hipGetLastError();
+}
+
+// ----------------------------------------------------------------------------- giant sample
+// One workgroup.  Sample i reads edge entry floor(i * m / S) (evenly spread
+// over the list), takes the root of its first endpoint (pi is a forest of
+// stars, so that is pi[u]), and counts roots in an LDS hash table
+// (open addressing, 2*S slots).  The most frequent root is the giant label;
+// the filter is switched on when it holds at least 1/8 of the samples.
+constexpr int kSampleMax = 2048;
+
+__global__ __launch_bounds__(1024) void k_sample(const int32_t* __restrict__ eu, int64_t m,
+                                                 const int32_t* pi, int32_t n, Ctrl* ctrl, int S) {
+    __shared__ int32_t keys[2 * kSampleMax];
+    __shared__ int32_t cnts[2 * kSampleMax];
+    __shared__ int32_t best_cnt[16];
+    __shared__ int32_t best_key[16];
+    constexpr int kSlots = 2 * kSampleMax;
+    for (int i = threadIdx.x; i < kSlots; i += blockDim.x) {
+        keys[i] = -1;
+        cnts[i] = 0;
+    }
+    __syncthreads();
+    for (int i = threadIdx.x; i < S; i += blockDim.x) {
+        const int64_t e = (int64_t)i * m / S;
+        const int32_t x = eu[e];
+        if ((uint32_t)x >= (uint32_t)n) continue;
+        const int32_t r = ld_rlx(pi + x);
+        uint32_t slot = ((uint32_t)r * 2654435761u) & (kSlots - 1);
+        for (int probe = 0; probe < kSlots; ++probe) {
+            const int32_t k = atomicCAS(&keys[slot], -1, r);
+            if (k == -1 || k == r) {
+                atomicAdd(&cnts[slot], 1);
+                break;
+            }
+            slot = (slot + 1) & (kSlots - 1);
+        }
+    }
+    __syncthreads();
+    int bc = -1, bk = -1;
+    for (int i = threadIdx.x; i < kSlots; i += blockDim.x) {
+        if (cnts[i] > bc) {
+            bc = cnts[i];
+            bk = keys[i];
+        }
+    }
+    // wave reduction (max count)
+    for (int off = 32; off > 0; off >>= 1) {
+        const int oc = __shfl_xor(bc, off);
+        const int ok = __shfl_xor(bk, off);
+        if (oc > bc) {
+            bc = oc;
+            bk = ok;
+        }
+    }
+    const int wave = threadIdx.x >> 6;
+    if ((threadIdx.x & 63) == 0) {
+        best_cnt[wave] = bc;
+        best_key[wave] = bk;
+    }
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        const int waves = (blockDim.x + 63) >> 6;
+        int c = best_cnt[0], k = best_key[0];
+        for (int w = 1; w < waves; ++w)
+            if (best_cnt[w] > c) {
+                c = best_cnt[w];
+                k = best_key[w];
+            }
+        const bool on = k >= 0 && c * 8 >= S;
+        ctrl->giant = on ? k : -1;
+        ctrl->filter_on = on ? 1 : 0;
+        ctrl->nofilter = on ? 0u : 1u;
+    }
+}
+
+hipError_t launch_sample_giant(const int32_t* u, int64_t m, const int32_t* pi, int32_t n,
+                               Ctrl* ctrl, int samples, hipStream_t s) {
+    if (samples > kSampleMax) samples = kSampleMax;
+    if (samples < 1 || m <= 0) return hipSuccess;
+    k_sample<<<1, 1024, 0, s>>>(u, m, pi, n, ctrl, samples);
+    return hipGetLastError();
+}
+
+// ----------------------------------------------------------------------------- bitmap
+// Each wave covers 256 consecutive vertices in 4 coalesced steps of 64; a
+// ballot turns each step's predicate into 64 bits (2 words); lanes 0..7 store
+// the wave's 8 words.  The giant's current root is re-read first (it may have
+// been hooked under a smaller root since the sample), and stored back.
+__global__ __launch_bounds__(256) void k_bitmap(const int32_t* pi, int32_t n, Ctrl* ctrl,
+                                                uint32_t* __restrict__ bits) {
+    if (!ctrl->filter_on) return;
+    const int32_t g = ld_rlx(pi + ctrl->giant);
+    const int lane = threadIdx.x & 63;
+    const int64_t wave_base = ((int64_t)blockIdx.x * (blockDim.x >> 6) + (threadIdx.x >> 6)) * 256;
+    uint64_t m4[4];
+#pragma unroll
+    for (int k = 0; k < 4; ++k) {
+        const int64_t x = wave_base + 64 * k + lane;
+        const bool in = x < n && ld_rlx(pi + x) == g;
+        m4[k] = __ballot(in);
+    }
+    if (lane < 8) {
+        const int64_t w = wave_base / 32 + lane;
+        if (w * 32 < n) {
+            const uint64_t mk = m4[lane >> 1];
+            bits[w] = (lane & 1) ? (uint32_t)(mk >> 32) : (uint32_t)mk;
+        }
+    }
+    if (blockIdx.x == 0 && threadIdx.x == 0) ctrl->giant = g;
+}
+
+hipError_t launch_bitmap(const int32_t* pi, int32_t n, Ctrl* ctrl, uint32_t* bits, hipStream_t s) {
+    if (n <= 0) return hipSuccess;
+    const int64_t waves = ((int64_t)n + 255) / 256;
+    const int grid = (int)((waves + 3) / 4);
+    k_bitmap<<<grid, 256, 0, s>>>(pi, n, ctrl, bits);
+    return hipGetLastError();
+}
+
+// ----------------------------------------------------------------------------- atomic-free Hook
+// Fig. 2 Hook: H = max(pi[u], pi[v]), L = min(...), plain store pi[H] = L.
+// Concurrent stores to one slot race and all but one are lost; the round
+// loop (Fig. 1) repeats until no entry is active, and every store writes a
+// smaller id than the slot's index, so no cycle forms.  Round 1 reads the
+// input lists (range-checked); later rounds read the frontier of root pairs
+// left by the previous compaction.  Block 0 also clears the count the
+// following compaction accumulates into, and records the round.
+template <int EPT, bool VEC, bool FIRST>
+__global__ __launch_bounds__(1024) void k_hook_plain(int round, const int32_t* __restrict__ eu,
+                                                     const int32_t* __restrict__ ev, int64_t m,
+                                                     const int2* __restrict__ fr, int32_t* pi,
+                                                     int32_t n, Ctrl* ctrl) {
+    // Later rounds: the frontier size, never more than the capacity `m`.
+    int64_t total = m;
+    if (!FIRST) total = min((int64_t)ctrl->count[(round - 1) & 1], m);
+    if (blockIdx.x == 0 && threadIdx.x == 0) {
+        ctrl->count[round & 1] = 0;
+        if (total > 0) ctrl->rounds = round;
+        if (round == 2) ctrl->active_round1 = total;
+    }
+    if (total == 0) return;
+    const int64_t tile = (int64_t)blockDim.x * EPT;
+    for (int64_t t0 = (int64_t)blockIdx.x * tile; t0 < total; t0 += (int64_t)gridDim.x * tile) {
+        int32_t a[EPT], b[EPT];
+        const int64_t e0 = t0 + (int64_t)threadIdx.x * 4;
+        if (FIRST) {
+            load_edges<EPT, VEC>(eu, e0, (int64_t)blockDim.x * 4, total, a);
+            load_edges<EPT, VEC>(ev, e0, (int64_t)blockDim.x * 4, total, b);
+        } else {
+#pragma unroll
+            for (int j = 0; j < EPT; ++j) {
+                const int64_t e = t0 + (int64_t)(j / 4) * blockDim.x * 4 + threadIdx.x * 4 + (j & 3);
+                int2 q = e < total ? fr[e] : int2{0, 0};
+                a[j] = q.x;
+                b[j] = q.y;
+            }
+        }
+        uint32_t act = 0;
+        bool bad = false;
+#pragma unroll
+        for (int j = 0; j < EPT; ++j) {
+            const bool in = (uint32_t)a[j] < (uint32_t)n && (uint32_t)b[j] < (uint32_t)n;
+            bad |= !in;
+            if (in && a[j] != b[j]) act |= 1u << j;
+        }
+        if (FIRST && bad) atomicOr(&ctrl->status, kStatusRange);
+        int32_t pa[EPT], pb[EPT];
+#pragma unroll
+        for (int j = 0; j < EPT; ++j) {
+            if (act >> j & 1) {
+                pa[j] = ld_rlx(pi + a[j]);
+                pb[j] = ld_rlx(pi + b[j]);
+            }
+        }
+#pragma unroll
+        for (int j = 0; j < EPT; ++j) {
+            if ((act >> j & 1) && pa[j] != pb[j]) {
+                const int32_t H = pa[j] > pb[j] ? pa[j] : pb[j];
+                const int32_t L = pa[j] > pb[j] ? pb[j] : pa[j];
+                st_rlx(pi + H, L);
+            }
+        }
+    }
+}
+
+// ----------------------------------------------------------------------------- K-COMPACT
+// After the Compress of a round, an entry is still active iff its endpoints'
+// roots differ (pi is a forest of stars).  Trees only merge, so an inactive
+// entry never becomes active again and can be dropped for good.  Survivors are
+// written as root pairs.  Per wave, one 64-bit ballot per slot j gives each
+// lane its output position (mbcnt lane prefix plus the counts of earlier
+// slots); the wave totals are scanned in LDS, the workgroup reserves its
+// output range with one atomicAdd, and the survivors, staged in LDS in that
+// order, are written out as one contiguous run.
+template <int EPT, bool VEC, bool FIRST>
+__global__ __launch_bounds__(256) void k_compact(int round, const int32_t* __restrict__ eu,
+                                                 const int32_t* __restrict__ ev, int64_t m,
+                                                 const int2* __restrict__ src, int2* __restrict__ dst,
+                                                 int64_t cap, const int32_t* pi, int32_t n,
+                                                 Ctrl* ctrl) {
+    __shared__ int2 stage[256 * EPT];
+    __shared__ uint32_t wave_tot[4];
+    __shared__ uint32_t wave_off[4];
+    __shared__ uint32_t base_sh;
+    int64_t total = m;
+    if (!FIRST) total = min((int64_t)ctrl->count[(round - 1) & 1], m);
+    if (total == 0) return;
+    const int lane = threadIdx.x & 63;
+    const int wave = threadIdx.x >> 6;
+    const int64_t tile = (int64_t)blockDim.x * EPT;
+    for (int64_t t0 = (int64_t)blockIdx.x * tile; t0 < total; t0 += (int64_t)gridDim.x * tile) {
+        int32_t a[EPT], b[EPT];
+        const int64_t e0 = t0 + (int64_t)threadIdx.x * 4;
+        if (FIRST) {
+            load_edges<EPT, VEC>(eu, e0, (int64_t)blockDim.x * 4, total, a);
+            load_edges<EPT, VEC>(ev, e0, (int64_t)blockDim.x * 4, total, b);
+        } else {
+#pragma unroll
+            for (int j = 0; j < EPT; ++j) {
+                const int64_t e = t0 + (int64_t)(j / 4) * blockDim.x * 4 + threadIdx.x * 4 + (j & 3);
+                int2 q = e < total ? src[e] : int2{0, 0};
+                a[j] = q.x;
+                b[j] = q.y;
+            }
+        }
+        int32_t ra[EPT], rb[EPT];
+#pragma unroll
+        for (int j = 0; j < EPT; ++j) {
+            const bool in = (uint32_t)a[j] < (uint32_t)n && (uint32_t)b[j] < (uint32_t)n && a[j] != b[j];
+            ra[j] = in ? ld_rlx(pi + a[j]) : 0;
+            rb[j] = in ? ld_rlx(pi + b[j]) : 0;
+        }
+        uint32_t pos[EPT];
+        uint32_t run = 0;
+#pragma unroll
+        for (int j = 0; j < EPT; ++j) {
+            const uint64_t mk = __ballot(ra[j] != rb[j]);
+            pos[j] = run + lane_prefix(mk);
+            run += (uint32_t)__popcll(mk);
+        }
+        if (lane == 0) wave_tot[wave] = run;
+        __syncthreads();
+        if (threadIdx.x == 0) {
+            uint32_t acc = 0;
+            const int waves = blockDim.x >> 6;
+            for (int w = 0; w < waves; ++w) {
+                wave_off[w] = acc;
+                acc += wave_tot[w];
+            }
+            base_sh = acc ? (uint32_t)atomicAdd(&ctrl->count[round & 1], acc) : 0u;
+            wave_tot[0] = acc;  // block total (read after the barrier)
+        }
+        __syncthreads();
+        const uint32_t woff = wave_off[wave];
+#pragma unroll
+        for (int j = 0; j < EPT; ++j)
+            if (ra[j] != rb[j]) stage[woff + pos[j]] = int2{ra[j], rb[j]};
+        __syncthreads();
+        const uint32_t cnt = wave_tot[0];
+        const int64_t base = base_sh;
+        if (base + cnt > cap) {
+            if (threadIdx.x == 0) atomicOr(&ctrl->status, kStatusOverflow);
+        } else {
+            for (uint32_t i = threadIdx.x; i < cnt; i += blockDim.x) dst[base + i] = stage[i];
+        }
+        __syncthreads();
+    }
+}
+
+hipError_t launch_hook_plain(int round, const int32_t* u, const int32_t* v, int64_t m,
+                             const int2* frontier, int32_t* pi, int32_t n, Ctrl* ctrl, int block,
+                             int ept, int grid_cap, hipStream_t s) {
+    const int64_t tile = (int64_t)block * ept;
+    int64_t grid64 = (m + tile - 1) / tile;
+    if (grid64 < 1) grid64 = 1;
+    if (grid64 > grid_cap) grid64 = grid_cap;
+    const int grid = (int)grid64;
+    const bool vec = aligned16(u) && aligned16(v);
+#define HP(EPT)                                                                                  \
+    do {                                                                                         \
+        if (round == 1) {                                                                        \
+            if (vec)                                                                             \
+                k_hook_plain<EPT, true, true><<<grid, block, 0, s>>>(round, u, v, m, frontier, pi, n, ctrl); \
+            else                                                                                 \
+                k_hook_plain<EPT, false, true><<<grid, block, 0, s>>>(round, u, v, m, frontier, pi, n, ctrl); \
+        } else {                                                                                 \
+            k_hook_plain<EPT, true, false><<<grid, block, 0, s>>>(round, u, v, m, frontier, pi, n, ctrl); \
+        }                                                                                        \
+    } while (0)
+    switch (ept) {
+        case 4: HP(4); break;
+        case 8: HP(8); break;
+        case 16: HP(16); break;
+        default: return hipErrorInvalidValue;
+    }
+#undef HP
+    return hipGetLastError();
+}
+
+hipError_t launch_compact(int round, const int32_t* u, const int32_t* v, int64_t m,
+                          const int2* src, int2* dst, int64_t cap, const int32_t* pi, int32_t n,
+                          Ctrl* ctrl, int block, int ept, int grid_cap, hipStream_t s) {
+    (void)block;  // the compaction tile is fixed at 256 threads (LDS staging size)
+    const int64_t tile = 256 * (int64_t)ept;
+    int64_t grid64 = (m + tile - 1) / tile;
+    if (grid64 < 1) grid64 = 1;
+    if (grid64 > grid_cap) grid64 = grid_cap;
+    const int grid = (int)grid64;
+    const bool vec = aligned16(u) && aligned16(v);
+#define CP(EPT)                                                                                  \
+    do {                                                                                         \
+        if (round == 1) {                                                                        \
+            if (vec)                                                                             \
+                k_compact<EPT, true, true><<<grid, 256, 0, s>>>(round, u, v, m, src, dst, cap, pi, n, ctrl); \
+            else                                                                                 \
+                k_compact<EPT, false, true><<<grid, 256, 0, s>>>(round, u, v, m, src, dst, cap, pi, n, ctrl); \
+        } else {                                                                                 \
+            k_compact<EPT, true, false><<<grid, 256, 0, s>>>(round, u, v, m, src, dst, cap, pi, n, ctrl); \
+        }                                                                                        \
+    } while (0)
+    switch (ept) {
+        case 4: CP(4); break;
+        case 8: CP(8); break;
+        case 16: CP(16); break;
+        default: return hipErrorInvalidValue;
+    }
+#undef CP
+    return hipGetLastError();
+}
+
+int device_cu_count() {
+    int dev = 0, cus = 0;
+    if (hipGetDevice(&dev) != hipSuccess) return 256;
+    if (hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess ||
+        cus <= 0)
+        return 256;
+    return cus;
+}
+
+}  // namespace hookcc

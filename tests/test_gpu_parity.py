@@ -1,0 +1,331 @@
+"""GPU parity: the HIP library (through the C ABI) against the CPU oracle.
+
+Labels are integers with a unique correct answer (the smallest id of each
+component), so every comparison is bit-exact.  Small and medium cases are
+compared element by element with the oracle run live; the full-size
+workloads are compared through the SHA-256 digests of the oracle's labels
+stored in tests/golden/oracle_digests.json (written by make_golden.py, which
+calls only the oracle).
+"""
+import hashlib
+import itertools
+import json
+import os
+import sys
+
+import numpy as np
+import pytest
+
+import graphgen
+import oracle
+from tests import pins
+from tests.golden.cases import hand_cases
+
+torch = pytest.importorskip("torch")
+import paper_1612_01178_amd as cc  # noqa: E402
+
+pytestmark = pytest.mark.gpu
+
+GOLDEN = os.path.join(os.path.dirname(os.path.abspath(__file__)), "golden", "oracle_digests.json")
+
+VARIANTS = {
+    "default": cc.Options(),
+    "plain": cc.Options(hook="plain"),
+    "s1": cc.Options(segments=1, filter="off"),
+    "s7_b64_e4": cc.Options(segments=7, filter="off", edges_per_thread=4, block=64),
+    "s5_giant_b1024_e16": cc.Options(segments=5, filter="giant", filter_after=1,
+                                     edges_per_thread=16, block=1024),
+    "s9_giant_after3": cc.Options(segments=9, filter="giant", filter_after=3,
+                                  edges_per_thread=8, block=512),
+    "plain_b128_e16_k1": cc.Options(hook="plain", edges_per_thread=16, block=128,
+                                    rounds_per_check=1),
+    "plain_e4_k7": cc.Options(hook="plain", edges_per_thread=4, rounds_per_check=7),
+}
+
+
+def say(*a):
+    print(*a, flush=True)
+    sys.stdout.flush()
+
+
+@pytest.fixture(scope="module")
+def dev():
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    cc.load()
+    return torch.device("cuda:0")
+
+
+def to_dev(x, dev):
+    return torch.from_numpy(np.ascontiguousarray(x, dtype=np.int32)).to(dev)
+
+
+def solve(u, v, n, dev, options=None, offset=0):
+    """GPU labels as numpy.  ``offset`` shifts the edge arrays inside a larger
+    allocation so that their base is not 16-byte aligned."""
+    if offset:
+        U = torch.zeros(len(u) + offset, dtype=torch.int32, device=dev)
+        V = torch.zeros(len(v) + offset, dtype=torch.int32, device=dev)
+        U[offset:] = to_dev(u, dev)
+        V[offset:] = to_dev(v, dev)
+        du, dv = U[offset:], V[offset:]
+    else:
+        du, dv = to_dev(u, dev), to_dev(v, dev)
+    return cc.labels(du, dv, n, options=options).cpu().numpy()
+
+
+def digest(labels):
+    return hashlib.sha256(np.ascontiguousarray(labels, dtype="<i4").tobytes()).hexdigest()
+
+
+# ----------------------------------------------------------------------------- small, exact
+@pytest.mark.parametrize("variant", sorted(VARIANTS))
+def test_hand_fixtures(dev, variant):
+    for name, n, u, v, want in hand_cases():
+        say("hand case", name, variant)
+        got = solve(u, v, n, dev, VARIANTS[variant])
+        assert np.array_equal(got, want), (name, got, want)
+
+
+def test_exhaustive_tiny_graphs_single_calls(dev):
+    rng = np.random.default_rng(5)
+    n = 5
+    pairs = list(itertools.combinations(range(n), 2))
+    masks = rng.choice(1 << len(pairs), 96, replace=False)
+    for i, mask in enumerate(masks):
+        chosen = [pairs[k] for k in range(len(pairs)) if mask >> k & 1]
+        u = np.array([a for a, _ in chosen], np.int32)
+        v = np.array([b for _, b in chosen], np.int32)
+        if i % 2:
+            u, v = v, u
+        want = pins.closure_labels(u, v, n)
+        for name in ("default", "plain", "s7_b64_e4"):
+            assert np.array_equal(solve(u, v, n, dev, VARIANTS[name]), want), (chosen, name)
+
+
+@pytest.mark.parametrize("variant", sorted(VARIANTS))
+def test_random_graphs_against_oracle(dev, variant):
+    """Sizes span several tiles with ragged tails; densities from forests to
+    dense; both aligned and unaligned edge arrays."""
+    rng = np.random.default_rng(11)
+    for trial in range(14):
+        n = int(rng.choice([1, 2, 3, 17, 100, 1000, 4099, 65537, 200003]))
+        deg = float(rng.choice([0.3, 1.0, 2.0, 5.0, 16.0]))
+        m = int(deg * n) + int(rng.integers(0, 7))
+        u, v = graphgen.uniform_pairs(m, n, seed=1000 + trial, stream=3)
+        off = int(rng.choice([0, 0, 1, 3]))
+        say("random", variant, "trial", trial, "n", n, "m", m, "offset", off)
+        got = solve(u, v, n, dev, VARIANTS[variant], offset=off)
+        want = oracle.labels(u, v, n)
+        assert np.array_equal(got, want), (variant, trial, n, m, int(np.sum(got != want)))
+
+
+@pytest.mark.parametrize("variant", ["default", "plain", "s5_giant_b1024_e16", "s1"])
+def test_adversarial_shapes(dev, variant):
+    opt = VARIANTS[variant]
+    n = 100003
+    ids = np.arange(n, dtype=np.int32)
+    cases = {
+        "path_up": (ids[:-1], ids[1:]),
+        "path_down": (ids[1:][::-1].copy(), ids[:-1][::-1].copy()),
+        "star_top": (np.full(n - 1, n - 1, np.int32), ids[:-1]),
+        "star_zero": (ids[1:], np.zeros(n - 1, np.int32)),
+        "matching": (ids[1::2], ids[0::2][:len(ids[1::2])]),
+        "mirror": (ids, ids[::-1].copy()),
+        "self_loops": (ids, ids),
+        "no_edges": (np.zeros(0, np.int32), np.zeros(0, np.int32)),
+    }
+    for name, (u, v) in cases.items():
+        say("shape", name, variant)
+        got = solve(u, v, n, dev, opt)
+        assert np.array_equal(got, oracle.labels(u, v, n)), name
+    # complete graph on 300 vertices (every ordered pair)
+    a, b = np.meshgrid(np.arange(300, dtype=np.int32), np.arange(300, dtype=np.int32))
+    got = solve(a.ravel(), b.ravel(), 300, dev, opt)
+    assert np.array_equal(got, np.zeros(300, np.int32))
+    # long chains of a lattice: rows only, columns only
+    W, H = 700, 300
+    u, v, nn = graphgen.grid(W, H, 0, 10, seed=2)
+    horiz = (v - u) == 1
+    got = solve(u[horiz], v[horiz], nn, dev, opt)
+    assert np.array_equal(got, (np.arange(nn) // W * W).astype(np.int32))
+    got = solve(u[~horiz][::-1].copy(), v[~horiz][::-1].copy(), nn, dev, opt)
+    assert np.array_equal(got, (np.arange(nn) % W).astype(np.int32))
+
+
+def test_generator_families_against_oracle(dev):
+    fams = {
+        "er_planted": graphgen.er_planted(n=1 << 14, m_er=1 << 17, cliques=64, seed=17)[:3],
+        "rmat_sym": graphgen.rmat(16, 16, seed=18, symmetrize=True),
+        "rmat_plain": graphgen.rmat(15, 8, seed=19, permute=False),
+        "grid_perc": graphgen.grid(512, 384, 3, 10, seed=20),
+        "grid_sparse": graphgen.grid(400, 400, 6, 10, seed=21),
+    }
+    for name, (u, v, n) in fams.items():
+        want = oracle.labels(u, v, n)
+        for variant, opt in VARIANTS.items():
+            say("family", name, variant)
+            got = solve(u, v, n, dev, opt)
+            assert np.array_equal(got, want), (name, variant)
+
+
+# ----------------------------------------------------------------------------- metamorphic
+def test_metamorphic_invariance(dev):
+    u, v, n = graphgen.rmat(15, 12, seed=23, symmetrize=False)
+    want = oracle.labels(u, v, n)
+    rng = np.random.default_rng(3)
+    perm = rng.permutation(len(u))
+    variants = {
+        "shuffled": (u[perm], v[perm]),
+        "swapped": (v, u),
+        "duplicated": (np.concatenate([u, u[:5000]]), np.concatenate([v, v[:5000]])),
+        "self_loops_added": (np.concatenate([u, np.arange(n, dtype=np.int32)]),
+                             np.concatenate([v, np.arange(n, dtype=np.int32)])),
+    }
+    for name, (uu, vv) in variants.items():
+        for opt in ("default", "plain", "s9_giant_after3"):
+            say("metamorphic", name, opt)
+            assert np.array_equal(solve(uu, vv, n, dev, VARIANTS[opt]), want), (name, opt)
+
+
+def test_repeated_solves_are_identical(dev):
+    """The races in Hook / Multi-Jump change the intermediate trees, never the labels."""
+    u, v, n, _ = graphgen.er_planted(seed=1001)
+    want = oracle.labels(u, v, n)
+    du, dv = to_dev(u, dev), to_dev(v, dev)
+    for opt in ("default", "plain", "s5_giant_b1024_e16"):
+        for rep in range(15):
+            got = cc.labels(du, dv, n, options=VARIANTS[opt]).cpu().numpy()
+            assert np.array_equal(got, want), (opt, rep)
+
+
+# ----------------------------------------------------------------------------- errors
+def test_range_errors_are_reported(dev):
+    for opt in ("default", "plain", "s5_giant_b1024_e16"):
+        for bad in (10, -1, 1 << 30):
+            u = np.array([0, 1, 2, bad, 3], np.int32)
+            v = np.array([1, 2, 3, 4, 0], np.int32)
+            with pytest.raises(cc.CCError) as ei:
+                solve(u, v, 10, dev, VARIANTS[opt])
+            assert ei.value.code == cc.CC_ERR_RANGE
+    # the library stays usable afterwards
+    assert np.array_equal(solve(np.array([1], np.int32), np.array([0], np.int32), 3, dev),
+                          np.array([0, 0, 2], np.int32))
+
+
+def test_round_cap_and_workspace_errors(dev):
+    n = 5000
+    u = np.full(n - 1, n - 1, np.int32)   # star on the top id: hooks collide on one slot
+    v = np.arange(n - 1, dtype=np.int32)
+    with pytest.raises(cc.CCError) as ei:
+        solve(u, v, n, dev, cc.Options(hook="plain", max_rounds=1, rounds_per_check=1))
+    assert ei.value.code == cc.CC_ERR_NOCONVERGE
+    opt = cc.Options(hook="plain")
+    need = cc.workspace_bytes(n, len(u), opt)
+    small = torch.empty(need // 2, dtype=torch.uint8, device=dev)
+    with pytest.raises(cc.CCError) as ei:
+        cc.labels(to_dev(u, dev), to_dev(v, dev), n, options=opt, workspace=small)
+    assert ei.value.code == cc.CC_ERR_NOMEM
+    ws = torch.empty(need + 256, dtype=torch.uint8, device=dev)
+    got = cc.labels(to_dev(u, dev), to_dev(v, dev), n, options=opt, workspace=ws)
+    assert np.array_equal(got.cpu().numpy(), np.zeros(n, np.int32))
+
+
+def test_stats_are_reported(dev):
+    u, v, n = graphgen.rmat(16, 16, seed=31, symmetrize=True)
+    du, dv = to_dev(u, dev), to_dev(v, dev)
+    lab, st = cc.labels(du, dv, n, options=cc.Options(filter="giant", profile=True),
+                        return_stats=True)
+    assert st["segments"] == 32 and st["filter_used"] == 1 and st["host_syncs"] == 1
+    assert st["hook_ms"] > 0 and st["compress_ms"] > 0
+    assert np.array_equal(lab.cpu().numpy(), oracle.labels(u, v, n))
+    lab, st = cc.labels(du, dv, n, options=cc.Options(hook="plain"), return_stats=True)
+    assert st["rounds"] >= 1 and st["active_edges"] >= 0
+
+
+# ----------------------------------------------------------------------------- batches
+def test_batch_exhaustive_tiny_graphs(dev):
+    graphs = []
+    for n in range(1, 6):
+        pairs = list(itertools.combinations(range(n), 2))
+        for mask in range(1 << len(pairs)):
+            chosen = [pairs[k] for k in range(len(pairs)) if mask >> k & 1]
+            graphs.append((n, chosen))
+    vo = np.zeros(len(graphs) + 1, np.int64)
+    eo = np.zeros(len(graphs) + 1, np.int64)
+    us, vs, want = [], [], []
+    for g, (n, chosen) in enumerate(graphs):
+        vo[g + 1] = vo[g] + n
+        eo[g + 1] = eo[g] + len(chosen)
+        uu = np.array([b for _, b in chosen], np.int32)
+        vv = np.array([a for a, _ in chosen], np.int32)
+        us.append(uu)
+        vs.append(vv)
+        want.append(pins.closure_labels(uu, vv, n))
+    u = np.concatenate(us).astype(np.int32)
+    v = np.concatenate(vs).astype(np.int32)
+    got = cc.labels_batch(to_dev(u, dev), to_dev(v, dev), vo, eo).cpu().numpy()
+    assert np.array_equal(got, np.concatenate(want))
+
+
+def test_batch_mixed_sizes_against_oracle(dev):
+    rng = np.random.default_rng(8)
+    sizes = [0, 1, 2, 300, 65536, 65537, 150000, 7, 40000, 0, 1000]
+    us, vs = [], []
+    vo, eo = [0], [0]
+    for i, n in enumerate(sizes):
+        m = 0 if n == 0 else int(rng.integers(0, 3 * n + 2))
+        if i == 4:
+            m = 0  # a large graph with no edges
+        uu, vv = graphgen.uniform_pairs(m, max(n, 1), seed=50 + i, stream=0)
+        us.append(uu)
+        vs.append(vv)
+        vo.append(vo[-1] + n)
+        eo.append(eo[-1] + m)
+    u, v = np.concatenate(us), np.concatenate(vs)
+    vo, eo = np.array(vo, np.int64), np.array(eo, np.int64)
+    want = oracle.labels_batch(u, v, vo, eo)
+    got, st = cc.labels_batch(to_dev(u, dev), to_dev(v, dev), vo, eo, return_stats=True)
+    assert np.array_equal(got.cpu().numpy(), want)
+
+
+def test_batch_range_error(dev):
+    u = np.array([0, 1, 5], np.int32)
+    v = np.array([1, 2, 0], np.int32)
+    vo = np.array([0, 3, 8], np.int64)
+    eo = np.array([0, 2, 3], np.int64)
+    with pytest.raises(cc.CCError) as ei:
+        cc.labels_batch(to_dev(u, dev), to_dev(v, dev), vo, eo)
+    assert ei.value.code == cc.CC_ERR_RANGE
+
+
+# ----------------------------------------------------------------------------- full size
+def _golden():
+    with open(GOLDEN) as f:
+        return json.load(f)
+
+
+@pytest.mark.parametrize("name", ["er16", "grid4k", "rmat24"])
+def test_full_size_workloads_match_oracle_digest(dev, name):
+    rec = _golden()[name]
+    say("generating", name)
+    u, v, n = graphgen.workload(name)
+    assert (n, len(u)) == (rec["n"], rec["m"])
+    du, dv = to_dev(u, dev), to_dev(v, dev)
+    del u, v
+    for opt in ("default", "plain", "s1"):
+        if name == "rmat24" and opt == "s1":
+            opt = "s9_giant_after3"
+        say("full size", name, opt)
+        lab = cc.labels(du, dv, n, options=VARIANTS[opt]).cpu().numpy()
+        assert int(np.count_nonzero(lab == np.arange(n))) == rec["components"], (name, opt)
+        assert digest(lab) == rec["sha256"], (name, opt)
+
+
+def test_full_size_batch_matches_oracle_digest(dev):
+    rec = _golden()["batch10k"]
+    u, v, vo, eo = graphgen.batch_er(10000, seed=1004)
+    assert (int(vo[-1]), len(u)) == (rec["n"], rec["m"])
+    say("full size batch10k")
+    lab = cc.labels_batch(to_dev(u, dev), to_dev(v, dev), vo, eo).cpu().numpy()
+    assert digest(lab) == rec["sha256"]

@@ -155,6 +155,8 @@ def main():
                      "other": round(other_ms, 4)},
     }
 
+    result["ceilings"] = probe_ceilings(cc, torch, u, v, n, m)
+
     if not args.skip_cpu:
         import oracle
         sample = min(m, 1 << 27)
@@ -176,6 +178,31 @@ def main():
         result["batch"] = bench_batch(cc, torch, dev)
 
     print(json.dumps(result), flush=True)
+
+
+def probe_ceilings(cc, torch, u, v, n, m, reps=5):
+    """Memory ceilings on the same resident edge list: the edge stream alone,
+    stream + 2 random int32 gathers of an n-entry table, stream + 2 bit
+    lookups of an n-bit bitmap (cc_probe), timed with torch events on the
+    stream the probes run on."""
+    table = torch.arange(n, dtype=torch.int32, device=u.device)
+    bits = torch.zeros((n + 31) // 32, dtype=torch.int32, device=u.device)
+    out = {}
+    for mode, name, tab in ((0, "stream", None), (1, "stream+gather", table),
+                            (2, "stream+bitmap", bits)):
+        cc.probe(mode, u, v, tab, n)
+        torch.cuda.synchronize()
+        s0, s1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        s0.record()
+        for _ in range(reps):
+            cc.probe(mode, u, v, tab, n)
+        s1.record()
+        torch.cuda.synchronize()
+        ms = s0.elapsed_time(s1) / reps
+        out[name] = {"ms": round(ms, 4), "edge_GBs": round(8.0 * m / (ms * 1e-3) / 1e9, 1),
+                     "entries_per_s": m / (ms * 1e-3)}
+    log("ceilings", out)
+    return out
 
 
 def bench_batch(cc, torch, dev, num_graphs=10000, reps=5):

@@ -88,8 +88,18 @@ typedef struct cc_options {
     int32_t profile;          /* 1 = time every kernel with HIP events on the call's stream
                                  and report the phase times in cc_stats (adds a few
                                  microseconds per launch); 0 = off                      */
-    int32_t reserved[7];      /* must be zero                                           */
+    int32_t host_loop;        /* atomic-free Hook only, for ablations of the paper's
+                                 baseline (Fig. 1 as written, convergence read by the host
+                                 after every launch): CC_HOST_LOOP_OFF (default: device-side
+                                 convergence and compaction), CC_HOST_LOOP_JUMP (Compress as
+                                 repeated single-level Jump launches, Fig. 2) or
+                                 CC_HOST_LOOP_MULTIJUMP (Compress as one Multi-Jump)    */
+    int32_t reserved[6];      /* must be zero                                           */
 } cc_options;
+
+#define CC_HOST_LOOP_OFF 0
+#define CC_HOST_LOOP_JUMP 1
+#define CC_HOST_LOOP_MULTIJUMP 2
 
 /* Fills *opts with the defaults (all fields zero = library choice). */
 void cc_options_init(cc_options* opts);
@@ -167,6 +177,91 @@ int32_t cc_labels_batch(int32_t num_graphs, const int64_t* vtx_off, const int64_
 int32_t cc_labels_batch_ex(int32_t num_graphs, const int64_t* vtx_off, const int64_t* edge_off,
                            const int32_t* edges_u, const int32_t* edges_v, int32_t* out_label,
                            void* stream, cc_stats* stats);
+
+/* One graph of a graph list: its own device arrays, local ids in [0, n). */
+typedef struct cc_graph {
+    const int32_t* edges_u; /* [device] int32[m]                                          */
+    const int32_t* edges_v; /* [device] int32[m]                                          */
+    int32_t* out_label;     /* [device] int32[n]; receives local min-id labels            */
+    int64_t m;              /* edge entries (>= 0)                                        */
+    int32_t n;              /* vertices (>= 0)                                            */
+    int32_t reserved;       /* must be zero                                               */
+} cc_graph;
+
+/* Labels of `count` independent graphs described by `graphs` ([host] array of
+ * descriptors holding device pointers); synchronous on `stream` (NULL = null
+ * stream).  Same solvers as cc_labels_batch: graphs of at most
+ * CC_BATCH_LDS_MAX_N vertices share one persistent LDS launch, larger ones
+ * are each solved in device memory on the same stream, and the call ends
+ * with a single synchronisation.  Descriptors may point anywhere (the
+ * graphs need not be packed).  Returns CC_OK, CC_ERR_ARG, CC_ERR_RANGE,
+ * CC_ERR_NOMEM or CC_ERR_HIP. */
+int32_t cc_labels_list(int32_t count, const cc_graph* graphs, void* stream, cc_stats* stats);
+
+/* ------------------------------------------------------------------ serving */
+
+/* A continuous-batching request server.  Requests (one graph each) are
+ * admitted in arrival order while they fit a device arena of
+ * cfg->device_bytes (footprint: 8m bytes of edges if CC_REQ_HOST_EDGES, 4n
+ * bytes of labels if CC_REQ_HOST_LABELS, 256-byte granules; requests whose
+ * arrays are already on the device take no arena space).  Each of
+ * cfg->workers host threads owns one HIP stream and, whenever it is free,
+ * solves every admitted waiting request as one wave (the cc_labels_list
+ * solvers), so requests that arrive while other waves run join the next
+ * wave and waves overlap on the device.  Times are seconds on the clock of
+ * cc_server_clock(). */
+#define CC_REQ_HOST_EDGES 1  /* edges_u/edges_v are [host]: copied in at admission   */
+#define CC_REQ_HOST_LABELS 2 /* out_label is [host]: labels copied back when done     */
+
+typedef struct cc_server cc_server;
+
+typedef struct cc_server_config {
+    int64_t device_bytes;    /* arena size; 0 = a quarter of the free device memory     */
+    int32_t workers;         /* worker threads / streams, 1..16; 0 = 2                  */
+    int32_t max_batch;       /* most requests in one wave; 0 = 1024                      */
+    int64_t max_batch_edges; /* most edge entries in one wave (a larger single request
+                                still runs alone); 0 = 2^28                              */
+    int32_t reserved[8];     /* must be zero                                             */
+} cc_server_config;
+
+typedef struct cc_request_info {
+    int32_t status;          /* CC_OK or the request's error code                        */
+    int32_t batch_size;      /* requests in the wave that solved it                      */
+    double t_submit;         /* cc_server_submit called                                  */
+    double t_admit;          /* arena space granted                                      */
+    double t_launch;         /* its wave started                                         */
+    double t_device_done;    /* labels complete in device memory                         */
+    double t_host_done;      /* labels copied back (== t_device_done without
+                                CC_REQ_HOST_LABELS, up to the wave's final sync)         */
+} cc_request_info;
+
+/* Creates a server on the current device.  Returns CC_OK, CC_ERR_ARG,
+ * CC_ERR_NOMEM or CC_ERR_HIP; *out is NULL on failure. */
+int32_t cc_server_create(const cc_server_config* cfg, cc_server** out);
+
+/* Queues one request.  Pointers follow `flags` ([host] or [device]) and must
+ * stay valid until the request is finished (cc_server_wait / poll).  A request
+ * larger than the arena finishes with CC_ERR_NOMEM.  *ticket identifies it. */
+int32_t cc_server_submit(cc_server* server, int32_t n, const int32_t* edges_u,
+                         const int32_t* edges_v, int64_t m, int32_t* out_label, int32_t flags,
+                         int64_t* ticket);
+
+/* Blocks until the request is finished, fills *info (may be NULL) and forgets
+ * the ticket.  Returns the request's status. */
+int32_t cc_server_wait(cc_server* server, int64_t ticket, cc_request_info* info);
+
+/* As cc_server_wait without blocking: returns 1 (and keeps the ticket) while
+ * the request is still queued or running. */
+int32_t cc_server_poll(cc_server* server, int64_t ticket, cc_request_info* info);
+
+/* Requests waiting for admission and arena bytes in use (either may be NULL). */
+int32_t cc_server_stats(cc_server* server, int64_t* pending, int64_t* arena_used);
+
+/* Finishes every queued request, stops the workers and frees the arena. */
+int32_t cc_server_destroy(cc_server* server);
+
+/* The server's clock, in seconds. */
+double cc_server_clock(void);
 
 /* -------------------------------------------------------------- measurement */
 

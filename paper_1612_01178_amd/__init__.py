@@ -32,11 +32,16 @@ CC_BATCH_LDS_MAX_N = 65536
 
 _HOOKS = {"atomic": 0, "plain": 1}
 _FILTERS = {"off": 0, "giant": 1, "auto": 2}
+_HOST_LOOPS = {"off": 0, "jump": 1, "multijump": 2}
 
 # Every symbol include/hookcc.h declares.
 EXPORTS = ("cc_options_init", "cc_labels", "cc_labels_ex", "cc_workspace_bytes",
-           "cc_labels_batch", "cc_labels_batch_ex", "cc_probe", "cc_last_error",
-           "cc_release", "cc_version")
+           "cc_labels_batch", "cc_labels_batch_ex", "cc_labels_list", "cc_probe",
+           "cc_last_error", "cc_release", "cc_version", "cc_server_create",
+           "cc_server_submit", "cc_server_wait", "cc_server_poll", "cc_server_stats",
+           "cc_server_destroy", "cc_server_clock")
+CC_REQ_HOST_EDGES = 1
+CC_REQ_HOST_LABELS = 2
 
 
 class CCError(RuntimeError):
@@ -50,7 +55,8 @@ class _COptions(ctypes.Structure):
                 ("filter", ctypes.c_int32), ("filter_after", ctypes.c_int32),
                 ("block", ctypes.c_int32), ("edges_per_thread", ctypes.c_int32),
                 ("max_rounds", ctypes.c_int32), ("rounds_per_check", ctypes.c_int32),
-                ("profile", ctypes.c_int32), ("reserved", ctypes.c_int32 * 7)]
+                ("profile", ctypes.c_int32), ("host_loop", ctypes.c_int32),
+                ("reserved", ctypes.c_int32 * 6)]
 
 
 class _CStats(ctypes.Structure):
@@ -61,6 +67,25 @@ class _CStats(ctypes.Structure):
                 ("compress_launches", ctypes.c_int32), ("hook_ms", ctypes.c_float),
                 ("compress_ms", ctypes.c_float), ("other_ms", ctypes.c_float),
                 ("reserved", ctypes.c_int64 * 4)]
+
+
+class _CGraph(ctypes.Structure):
+    _fields_ = [("edges_u", ctypes.c_void_p), ("edges_v", ctypes.c_void_p),
+                ("out_label", ctypes.c_void_p), ("m", ctypes.c_int64), ("n", ctypes.c_int32),
+                ("reserved", ctypes.c_int32)]
+
+
+class _CServerConfig(ctypes.Structure):
+    _fields_ = [("device_bytes", ctypes.c_int64), ("workers", ctypes.c_int32),
+                ("max_batch", ctypes.c_int32), ("max_batch_edges", ctypes.c_int64),
+                ("reserved", ctypes.c_int32 * 8)]
+
+
+class _CRequestInfo(ctypes.Structure):
+    _fields_ = [("status", ctypes.c_int32), ("batch_size", ctypes.c_int32),
+                ("t_submit", ctypes.c_double), ("t_admit", ctypes.c_double),
+                ("t_launch", ctypes.c_double), ("t_device_done", ctypes.c_double),
+                ("t_host_done", ctypes.c_double)]
 
 
 @dataclasses.dataclass
@@ -75,6 +100,7 @@ class Options:
     max_rounds: int = 0
     rounds_per_check: int = 0
     profile: bool = False
+    host_loop: str = "off"
 
     def _c(self) -> _COptions:
         o = _COptions()
@@ -87,6 +113,7 @@ class Options:
         o.max_rounds = self.max_rounds
         o.rounds_per_check = self.rounds_per_check
         o.profile = 1 if self.profile else 0
+        o.host_loop = _HOST_LOOPS[self.host_loop]
         return o
 
 
@@ -120,6 +147,25 @@ def load():
             lib.cc_labels_batch_ex.argtypes = [_i32, _vp, _vp, _vp, _vp, _vp, _vp,
                                                ctypes.POINTER(_CStats)]
             lib.cc_labels_batch_ex.restype = _i32
+            lib.cc_labels_list.argtypes = [_i32, ctypes.POINTER(_CGraph), _vp,
+                                           ctypes.POINTER(_CStats)]
+            lib.cc_labels_list.restype = _i32
+            lib.cc_server_create.argtypes = [ctypes.POINTER(_CServerConfig),
+                                             ctypes.POINTER(ctypes.c_void_p)]
+            lib.cc_server_create.restype = _i32
+            lib.cc_server_submit.argtypes = [_vp, _i32, _vp, _vp, _i64, _vp, _i32,
+                                             ctypes.POINTER(_i64)]
+            lib.cc_server_submit.restype = _i32
+            lib.cc_server_wait.argtypes = [_vp, _i64, ctypes.POINTER(_CRequestInfo)]
+            lib.cc_server_wait.restype = _i32
+            lib.cc_server_poll.argtypes = [_vp, _i64, ctypes.POINTER(_CRequestInfo)]
+            lib.cc_server_poll.restype = _i32
+            lib.cc_server_stats.argtypes = [_vp, ctypes.POINTER(_i64), ctypes.POINTER(_i64)]
+            lib.cc_server_stats.restype = _i32
+            lib.cc_server_destroy.argtypes = [_vp]
+            lib.cc_server_destroy.restype = _i32
+            lib.cc_server_clock.argtypes = []
+            lib.cc_server_clock.restype = ctypes.c_double
             lib.cc_probe.argtypes = [_i32, _vp, _vp, _i64, _vp, _i32, _vp]
             lib.cc_probe.restype = _i32
             lib.cc_last_error.argtypes = []
@@ -236,6 +282,39 @@ def labels_batch(u, v, vtx_off, edge_off, *, out=None, stream=None, return_stats
     return out
 
 
+def labels_list(graphs, *, stream=None, return_stats: bool = False):
+    """Labels of independent graphs, each given as (u, v, n) or (u, v, n, out)
+    with its own int32 CUDA tensors.  Returns the list of label tensors."""
+    import torch
+    descs = (_CGraph * max(len(graphs), 1))()
+    outs = []
+    dev = None
+    for i, g in enumerate(graphs):
+        u, v, n = g[0], g[1], int(g[2])
+        u = _edge_tensor(u, "u")
+        v = _edge_tensor(v, "v")
+        if u.numel() != v.numel():
+            raise ValueError("u and v differ in length")
+        out = g[3] if len(g) > 3 else torch.empty(max(n, 0), dtype=torch.int32, device=u.device)
+        outs.append(out)
+        dev = u.device
+        descs[i].edges_u = u.data_ptr() if u.numel() else None
+        descs[i].edges_v = v.data_ptr() if v.numel() else None
+        descs[i].out_label = out.data_ptr() if n > 0 else None
+        descs[i].m = u.numel()
+        descs[i].n = n
+        descs[i].reserved = 0
+    st = _CStats()
+    if dev is None:
+        return ([], {}) if return_stats else []
+    with torch.cuda.device(dev):
+        rc = load().cc_labels_list(len(graphs), descs, _stream_handle(stream), ctypes.byref(st))
+    _check(rc)
+    if return_stats:
+        return outs, {f: getattr(st, f) for f, _ in _CStats._fields_ if f != "reserved"}
+    return outs
+
+
 def probe(mode: int, u, v, table=None, n: int = 0, stream=None) -> None:
     """Asynchronous memory-ceiling probe (see cc_probe in hookcc.h)."""
     u = _edge_tensor(u, "u")
@@ -243,3 +322,91 @@ def probe(mode: int, u, v, table=None, n: int = 0, stream=None) -> None:
     tp = table.data_ptr() if table is not None else None
     _check(load().cc_probe(int(mode), u.data_ptr(), v.data_ptr(), u.numel(), tp, int(n),
                            _stream_handle(stream)))
+
+
+class Server:
+    """Continuous-batching request server (cc_server_* in hookcc.h).
+
+    ``submit`` takes either int32 CUDA tensors (device-resident request) or
+    numpy int32 arrays (host request: edges copied in at admission, labels
+    copied back).  The arrays are kept alive here until ``wait``."""
+
+    def __init__(self, device_bytes: int = 0, workers: int = 0, max_batch: int = 0,
+                 max_batch_edges: int = 0):
+        cfg = _CServerConfig()
+        cfg.device_bytes = device_bytes
+        cfg.workers = workers
+        cfg.max_batch = max_batch
+        cfg.max_batch_edges = max_batch_edges
+        h = ctypes.c_void_p()
+        _check(load().cc_server_create(ctypes.byref(cfg), ctypes.byref(h)))
+        self._h = h
+        self._keep = {}
+
+    @staticmethod
+    def clock() -> float:
+        return float(load().cc_server_clock())
+
+    def submit(self, u, v, n: int, out=None) -> int:
+        import numpy as np
+        import torch
+        if isinstance(u, torch.Tensor):
+            u = _edge_tensor(u, "u")
+            v = _edge_tensor(v, "v")
+            if out is None:
+                out = torch.empty(max(int(n), 0), dtype=torch.int32, device=u.device)
+            flags = 0
+            up, vp, op = u.data_ptr(), v.data_ptr(), out.data_ptr()
+        else:
+            u = np.ascontiguousarray(u, dtype=np.int32)
+            v = np.ascontiguousarray(v, dtype=np.int32)
+            if out is None:
+                out = np.empty(max(int(n), 0), dtype=np.int32)
+            flags = CC_REQ_HOST_EDGES | CC_REQ_HOST_LABELS
+            up, vp, op = u.ctypes.data, v.ctypes.data, out.ctypes.data
+        if len(u) != len(v):
+            raise ValueError("u and v differ in length")
+        t = ctypes.c_int64()
+        _check(load().cc_server_submit(self._h, int(n), up if len(u) else None,
+                                       vp if len(v) else None, len(u), op if n else None, flags,
+                                       ctypes.byref(t)))
+        self._keep[t.value] = (u, v, out)
+        return t.value
+
+    def _info(self, info):
+        return {f: getattr(info, f) for f, _ in _CRequestInfo._fields_}
+
+    def wait(self, ticket: int):
+        """(labels, info dict) of a finished request; raises CCError on failure."""
+        info = _CRequestInfo()
+        rc = load().cc_server_wait(self._h, ticket, ctypes.byref(info))
+        keep = self._keep.pop(ticket)
+        _check(rc)
+        return keep[2], self._info(info)
+
+    def poll(self, ticket: int):
+        """None while queued or running, else as ``wait``."""
+        info = _CRequestInfo()
+        rc = load().cc_server_poll(self._h, ticket, ctypes.byref(info))
+        if rc == 1:
+            return None
+        keep = self._keep.pop(ticket)
+        _check(rc)
+        return keep[2], self._info(info)
+
+    def stats(self):
+        p, a = ctypes.c_int64(), ctypes.c_int64()
+        _check(load().cc_server_stats(self._h, ctypes.byref(p), ctypes.byref(a)))
+        return {"pending": p.value, "arena_used": a.value}
+
+    def close(self) -> None:
+        if self._h:
+            rc = load().cc_server_destroy(self._h)
+            self._h = None
+            _check(rc)
+
+    def __enter__(self):
+        return self
+
+    def __exit__(self, *exc):
+        self.close()

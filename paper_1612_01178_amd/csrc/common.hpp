@@ -20,7 +20,9 @@ struct Ctrl {
     uint32_t nofilter;    // giant sample: 1 when no component is large enough to filter
     int32_t queue_head;   // batched solve: next position of the graph work queue
     int64_t active_round1;  // atomic-free Hook: frontier size after round 1
-    int32_t pad[54];
+    int32_t hook_changed;   // host-loop form of Fig. 1: a Hook pass found an active edge
+    int32_t jump_changed;   // host-loop form of Fig. 1: a Jump pass moved a pointer
+    int32_t pad[52];
 };
 static_assert(sizeof(Ctrl) == 256, "control block is one 256-byte line");
 

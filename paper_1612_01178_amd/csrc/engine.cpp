@@ -1,0 +1,677 @@
+// Host engine of libhookcc (the C ABI wrappers are in capi.cpp).
+//
+// The engine turns a call into a plan (hook variant, segment bounds, filter,
+// tiling), takes device scratch from a per-(device, stream) cache, enqueues
+// the kernel sequence on the caller's stream, and ends with one stream
+// synchronisation plus a 256-byte read of the device control block (status
+// bits and statistics).  No step of the solve runs on the host.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cmath>
+#include <cstdio>
+#include <cstring>
+#include <map>
+#include <memory>
+#include <mutex>
+#include <string>
+#include <vector>
+
+#include "engine.hpp"
+
+namespace hookcc {
+
+namespace {
+thread_local std::string t_err;
+}  // namespace
+
+int32_t fail(int32_t code, const std::string& msg) {
+    t_err = msg;
+    return code;
+}
+
+const char* last_error() { return t_err.c_str(); }
+
+namespace {
+
+#define HIPCHK(expr)                                                                       \
+    do {                                                                                   \
+        hipError_t e_ = (expr);                                                            \
+        if (e_ != hipSuccess)                                                              \
+            return fail(e_ == hipErrorOutOfMemory ? CC_ERR_NOMEM : CC_ERR_HIP,             \
+                        std::string(#expr) + ": " + hipGetErrorString(e_));                \
+    } while (0)
+
+size_t align256(size_t x) { return (x + 255) & ~size_t(255); }
+
+// ---------------------------------------------------------------------- plans
+struct Plan {
+    int hook = CC_HOOK_ATOMIC;
+    int segments = 1;
+    int filter = CC_FILTER_OFF;
+    int filter_after = 1;
+    int block = 256;
+    int ept = 8;
+    int64_t max_rounds = 0;
+    int rounds_per_check = 4;
+    bool profile = false;
+    int host_loop = CC_HOST_LOOP_OFF;
+};
+
+int32_t make_plan(int32_t n, int64_t m, const cc_options* o, Plan& p) {
+    cc_options d;
+    std::memset(&d, 0, sizeof d);
+    d.filter = CC_FILTER_AUTO;
+    const cc_options& op = o ? *o : d;
+    for (int i = 0; i < 6; ++i)
+        if (op.reserved[i] != 0) return fail(CC_ERR_ARG, "cc_options.reserved must be zero");
+    if (op.hook != CC_HOOK_ATOMIC && op.hook != CC_HOOK_PLAIN)
+        return fail(CC_ERR_ARG, "unknown cc_options.hook");
+    p.hook = op.hook;
+    if (op.segments < 0) return fail(CC_ERR_ARG, "cc_options.segments < 0");
+    // Average-degree heuristic (Section 3.B, Fig. 4): s = 2|E|/|V| with |E|
+    // counted once per undirected edge, i.e. s = (entries passed) / n.
+    int64_t s = op.segments;
+    if (s == 0) s = n > 0 ? (m + n / 2) / n : 1;
+    const int64_t smax = std::max<int64_t>(1, (m + 3) / 4);
+    s = std::max<int64_t>(1, std::min<int64_t>(s, smax));
+    s = std::min<int64_t>(s, 1 << 20);
+    p.segments = (int)s;
+    if (op.filter < CC_FILTER_OFF || op.filter > CC_FILTER_AUTO)
+        return fail(CC_ERR_ARG, "unknown cc_options.filter");
+    if (op.filter_after < 0) return fail(CC_ERR_ARG, "cc_options.filter_after < 0");
+    p.filter_after = op.filter_after ? op.filter_after : 1;
+    if (p.hook != CC_HOOK_ATOMIC) {
+        p.filter = CC_FILTER_OFF;
+    } else if (op.filter == CC_FILTER_AUTO) {
+        // A giant component is near-certain at average degree >= 3.5, and the
+        // sample + bitmap cost only pays off on large edge lists.
+        p.filter = (p.segments >= 4 && m >= (int64_t(1) << 22)) ? CC_FILTER_GIANT : CC_FILTER_OFF;
+    } else {
+        p.filter = op.filter;
+    }
+    if (p.filter == CC_FILTER_GIANT && p.filter_after >= p.segments) p.filter = CC_FILTER_OFF;
+    if (op.block != 0) {
+        if (op.block < 64 || op.block > 1024 || op.block % 64)
+            return fail(CC_ERR_ARG, "cc_options.block must be a multiple of 64 in [64, 1024]");
+        p.block = op.block;
+    }
+    if (op.edges_per_thread != 0) {
+        if (op.edges_per_thread != 4 && op.edges_per_thread != 8 && op.edges_per_thread != 16)
+            return fail(CC_ERR_ARG, "cc_options.edges_per_thread must be 4, 8 or 16");
+        p.ept = op.edges_per_thread;
+    }
+    if (op.max_rounds < 0) return fail(CC_ERR_ARG, "cc_options.max_rounds < 0");
+    p.max_rounds = op.max_rounds ? op.max_rounds : (int64_t)n + 1;
+    if (op.rounds_per_check < 0) return fail(CC_ERR_ARG, "cc_options.rounds_per_check < 0");
+    p.rounds_per_check = op.rounds_per_check ? op.rounds_per_check : 4;
+    if (op.profile != 0 && op.profile != 1) return fail(CC_ERR_ARG, "cc_options.profile must be 0 or 1");
+    p.profile = op.profile == 1;
+    if (op.host_loop < CC_HOST_LOOP_OFF || op.host_loop > CC_HOST_LOOP_MULTIJUMP)
+        return fail(CC_ERR_ARG, "unknown cc_options.host_loop");
+    if (op.host_loop != CC_HOST_LOOP_OFF && p.hook != CC_HOOK_PLAIN)
+        return fail(CC_ERR_ARG, "cc_options.host_loop needs the atomic-free Hook");
+    p.host_loop = op.host_loop;
+    if (p.hook == CC_HOOK_PLAIN && m >= (int64_t(1) << 32))
+        return fail(CC_ERR_ARG, "atomic-free Hook supports m < 2^32 entries");
+    return CC_OK;
+}
+
+// Workspace: [Ctrl 256 B][giant bitmap][frontier 0][frontier 1]
+struct Layout {
+    size_t bits = 0, f0 = 0, f1 = 0, total = 0;
+    int64_t cap = 0;
+};
+
+Layout layout(int32_t n, int64_t m, const Plan& p) {
+    Layout L;
+    size_t off = 256;
+    if (p.hook == CC_HOOK_ATOMIC && p.filter == CC_FILTER_GIANT) {
+        L.bits = off;
+        off += align256(((size_t)n + 31) / 32 * 4);
+    }
+    if (p.hook == CC_HOOK_PLAIN && p.host_loop == CC_HOST_LOOP_OFF) {
+        L.cap = m;
+        L.f0 = off;
+        off += align256((size_t)m * 8);
+        L.f1 = off;
+        off += align256((size_t)m * 8);
+    }
+    L.total = off;
+    return L;
+}
+
+// ---------------------------------------------------------------------- workspace cache
+struct PoolEntry {
+    std::mutex mu;  // held for the whole duration of a call using this entry
+    void* dev = nullptr;
+    size_t bytes = 0;
+    Ctrl* host_ctrl = nullptr;  // pinned, host_ctrl_count control blocks
+    int64_t host_ctrl_count = 0;
+    void* host_stage = nullptr; // pinned staging for batch descriptors
+    size_t stage_bytes = 0;
+};
+
+std::mutex g_pool_mu;
+std::map<std::pair<int, hipStream_t>, std::unique_ptr<PoolEntry>> g_pool;
+
+PoolEntry* pool_entry(hipStream_t s) {
+    int dev = 0;
+    if (hipGetDevice(&dev) != hipSuccess) dev = -1;
+    std::lock_guard<std::mutex> g(g_pool_mu);
+    auto& e = g_pool[{dev, s}];
+    if (!e) e.reset(new PoolEntry());
+    return e.get();
+}
+
+int32_t ensure_dev(PoolEntry* e, size_t bytes) {
+    if (e->bytes >= bytes && e->dev) return CC_OK;
+    if (e->dev) {
+        HIPCHK(hipFree(e->dev));
+        e->dev = nullptr;
+        e->bytes = 0;
+    }
+    size_t want = std::max<size_t>(bytes, 1 << 20);
+    HIPCHK(hipMalloc(&e->dev, want));
+    e->bytes = want;
+    return CC_OK;
+}
+
+int32_t ensure_host(PoolEntry* e, int64_t count = 1) {
+    if (e->host_ctrl && e->host_ctrl_count >= count) return CC_OK;
+    if (e->host_ctrl) {
+        HIPCHK(hipHostFree(e->host_ctrl));
+        e->host_ctrl = nullptr;
+        e->host_ctrl_count = 0;
+    }
+    const int64_t want = std::max<int64_t>(count, 16);
+    HIPCHK(hipHostMalloc((void**)&e->host_ctrl, sizeof(Ctrl) * want, hipHostMallocDefault));
+    e->host_ctrl_count = want;
+    return CC_OK;
+}
+
+int32_t ensure_stage(PoolEntry* e, size_t bytes) {
+    if (e->stage_bytes >= bytes && e->host_stage) return CC_OK;
+    if (e->host_stage) {
+        HIPCHK(hipHostFree(e->host_stage));
+        e->host_stage = nullptr;
+        e->stage_bytes = 0;
+    }
+    size_t want = std::max<size_t>(bytes, 1 << 16);
+    HIPCHK(hipHostMalloc(&e->host_stage, want, hipHostMallocDefault));
+    e->stage_bytes = want;
+    return CC_OK;
+}
+
+// ---------------------------------------------------------------------- profiling
+struct Timer {
+    bool on = false;
+    hipStream_t s = nullptr;
+    struct Ev {
+        hipEvent_t a, b;
+        int phase;
+    };
+    std::vector<Ev> evs;
+    ~Timer() {
+        for (auto& e : evs) {
+            (void)hipEventDestroy(e.a);
+            (void)hipEventDestroy(e.b);
+        }
+    }
+    hipError_t begin(int phase) {
+        if (!on) return hipSuccess;
+        Ev e;
+        e.phase = phase;
+        hipError_t r = hipEventCreate(&e.a);
+        if (r != hipSuccess) return r;
+        r = hipEventCreate(&e.b);
+        if (r != hipSuccess) return r;
+        evs.push_back(e);
+        return hipEventRecord(e.a, s);
+    }
+    hipError_t end() {
+        if (!on) return hipSuccess;
+        return hipEventRecord(evs.back().b, s);
+    }
+    void collect(cc_stats* st) {
+        if (!on || !st) return;
+        float t[3] = {0, 0, 0};
+        for (auto& e : evs) {
+            float ms = 0;
+            if (hipEventElapsedTime(&ms, e.a, e.b) == hipSuccess) t[e.phase] += ms;
+        }
+        st->hook_ms = t[0];
+        st->compress_ms = t[1];
+        st->other_ms = t[2];
+    }
+};
+enum { kPhaseHook = 0, kPhaseCompress = 1, kPhaseOther = 2 };
+
+#define TIMED(phase, expr)                 \
+    do {                                   \
+        HIPCHK(tm.begin(phase));           \
+        HIPCHK(expr);                      \
+        HIPCHK(tm.end());                  \
+    } while (0)
+
+// ---------------------------------------------------------------------- single solve
+int32_t finish(hipStream_t s, Ctrl* dctrl, Ctrl* hctrl, cc_stats* st) {
+    HIPCHK(hipMemcpyAsync(hctrl, dctrl, sizeof(Ctrl), hipMemcpyDeviceToHost, s));
+    HIPCHK(hipStreamSynchronize(s));
+    if (st) st->host_syncs += 1;
+    return CC_OK;
+}
+
+// Enqueues the Atomic-Hook solve (Fig. 4) of one graph on s; no synchronisation.
+// `ctrl` is the graph's control block, `bits` its giant bitmap (filter plans).
+int32_t enqueue_atomic(int32_t n, const int32_t* u, const int32_t* v, int64_t m, int32_t* pi,
+                       const Plan& p, Ctrl* ctrl, uint32_t* bits, hipStream_t s, Timer& tm,
+                       cc_stats* st) {
+    const int S = p.segments;
+    auto bound = [&](int64_t i) -> int64_t {
+        if (i >= S) return m;
+        return (m * i / S) & ~int64_t(3);  // multiples of 4 keep 16-byte loads aligned
+    };
+    int hooks = 0, jumps = 0;
+    TIMED(kPhaseOther, launch_init(pi, n, ctrl, s));
+    if (p.filter != CC_FILTER_GIANT) {
+        // Fig. 4: for each segment, Atomic-Hook the segment, then Multi-Jump all of V.
+        for (int i = 0; i < S; ++i) {
+            TIMED(kPhaseHook, launch_ahook(u, v, bound(i), bound(i + 1), pi, n, ctrl, nullptr,
+                                           p.block, p.ept, s));
+            TIMED(kPhaseCompress, launch_mj(pi, n, nullptr, s));
+            ++hooks;
+            ++jumps;
+        }
+    } else {
+        const int fa = p.filter_after;
+        for (int i = 0; i < fa; ++i) {
+            TIMED(kPhaseHook, launch_ahook(u, v, bound(i), bound(i + 1), pi, n, ctrl, nullptr,
+                                           p.block, p.ept, s));
+            TIMED(kPhaseCompress, launch_mj(pi, n, nullptr, s));
+            ++hooks;
+            ++jumps;
+        }
+        TIMED(kPhaseOther, launch_sample_giant(u, m, pi, n, ctrl, 2048, s));
+        TIMED(kPhaseOther, launch_bitmap(pi, n, ctrl, bits, s));
+        // The rest of the list in super-segments that double in size, each
+        // followed by a Compress and a bitmap refresh.
+        int64_t g = fa, step = fa;
+        while (g < S) {
+            const int64_t h = std::min<int64_t>(S, g + step);
+            TIMED(kPhaseHook, launch_ahook(u, v, bound(g), bound(h), pi, n, ctrl, bits, p.block,
+                                           p.ept, s));
+            TIMED(kPhaseCompress, launch_mj(pi, n, nullptr, s));
+            ++hooks;
+            ++jumps;
+            if (h < S) TIMED(kPhaseOther, launch_bitmap(pi, n, ctrl, bits, s));
+            g = h;
+            step *= 2;
+        }
+    }
+    if (st) {
+        st->hook_launches += hooks;
+        st->compress_launches += jumps;
+    }
+    return CC_OK;
+}
+
+int32_t solve_plain(int32_t n, const int32_t* u, const int32_t* v, int64_t m, int32_t* pi,
+                    const Plan& p, char* ws, const Layout& L, hipStream_t s, Ctrl* hctrl,
+                    Timer& tm, cc_stats* st, int64_t* rounds_run) {
+    Ctrl* ctrl = reinterpret_cast<Ctrl*>(ws);
+    int2* F[2] = {reinterpret_cast<int2*>(ws + L.f0), reinterpret_cast<int2*>(ws + L.f1)};
+    const int grid_cap = device_cu_count() * 8;
+    TIMED(kPhaseOther, launch_init(pi, n, ctrl, s));
+    int64_t r = 0;
+    int hooks = 0, jumps = 0;
+    while (true) {
+        for (int k = 0; k < p.rounds_per_check; ++k) {
+            ++r;
+            const int2* src = F[(r - 1) & 1];
+            int2* dst = F[r & 1];
+            const int64_t work = (r == 1) ? m : L.cap;
+            TIMED(kPhaseHook, launch_hook_plain((int)r, u, v, work, src, pi, n, ctrl, p.block,
+                                                p.ept, grid_cap, s));
+            TIMED(kPhaseCompress,
+                  launch_mj(pi, n, r == 1 ? nullptr : &ctrl->count[(r - 1) & 1], s));
+            TIMED(kPhaseHook, launch_compact((int)r, u, v, work, src, dst, L.cap, pi, n, ctrl,
+                                             p.block, p.ept, grid_cap, s));
+            hooks += 2;
+            ++jumps;
+        }
+        int32_t rc = finish(s, ctrl, hctrl, st);
+        if (rc != CC_OK) return rc;
+        if (hctrl->status) break;  // reported by the caller
+        if (hctrl->count[r & 1] == 0) break;
+        if (r >= p.max_rounds) {
+            *rounds_run = r;
+            if (st) {
+                st->hook_launches += hooks;
+                st->compress_launches += jumps;
+            }
+            return fail(CC_ERR_NOCONVERGE, "atomic-free Hook did not converge within max_rounds");
+        }
+    }
+    *rounds_run = r;
+    if (st) {
+        st->hook_launches += hooks;
+        st->compress_launches += jumps;
+    }
+    return CC_OK;
+}
+
+// Fig. 1 exactly as the paper's baseline runs it: every Hook pass covers all
+// entries, and the host reads a device "changed" flag after every launch
+// (the CPU-GPU round trips that Section 1 sets out to remove).  Compress is
+// either repeated single-level Jump launches (Fig. 2) or one Multi-Jump.
+int32_t solve_host_loop(int32_t n, const int32_t* u, const int32_t* v, int64_t m, int32_t* pi,
+                        const Plan& p, char* ws, hipStream_t s, Ctrl* hctrl, Timer& tm,
+                        cc_stats* st) {
+    Ctrl* ctrl = reinterpret_cast<Ctrl*>(ws);
+    TIMED(kPhaseOther, launch_init(pi, n, ctrl, s));
+    int64_t rounds = 0;
+    int hooks = 0, jumps = 0;
+    while (true) {
+        ++rounds;
+        HIPCHK(hipMemsetAsync(&ctrl->hook_changed, 0, 4, s));
+        TIMED(kPhaseHook, launch_hook_flag(u, v, m, pi, n, ctrl, p.block, p.ept, s));
+        ++hooks;
+        int32_t rc = finish(s, ctrl, hctrl, st);
+        if (rc != CC_OK) return rc;
+        if (hctrl->status) break;
+        const bool hooked = hctrl->hook_changed != 0;
+        if (p.host_loop == CC_HOST_LOOP_MULTIJUMP) {
+            TIMED(kPhaseCompress, launch_mj(pi, n, nullptr, s));
+            ++jumps;
+        } else {
+            while (true) {
+                HIPCHK(hipMemsetAsync(&ctrl->jump_changed, 0, 4, s));
+                TIMED(kPhaseCompress, launch_jump(pi, n, ctrl, s));
+                ++jumps;
+                rc = finish(s, ctrl, hctrl, st);
+                if (rc != CC_OK) return rc;
+                if (!hctrl->jump_changed) break;
+            }
+        }
+        if (!hooked) break;
+        if (rounds >= p.max_rounds) {
+            if (st) {
+                st->rounds = (int32_t)rounds;
+                st->hook_launches += hooks;
+                st->compress_launches += jumps;
+            }
+            return fail(CC_ERR_NOCONVERGE, "Hook did not converge within max_rounds");
+        }
+    }
+    int32_t rc = finish(s, ctrl, hctrl, st);
+    if (rc != CC_OK) return rc;
+    if (st) {
+        st->rounds = (int32_t)rounds;
+        st->hook_launches += hooks;
+        st->compress_launches += jumps;
+    }
+    return CC_OK;
+}
+
+int32_t check_args(int32_t n, const int32_t* u, const int32_t* v, int64_t m, const int32_t* out) {
+    if (n < 0) return fail(CC_ERR_ARG, "n < 0");
+    if (m < 0) return fail(CC_ERR_ARG, "m < 0");
+    if (m > 0 && (!u || !v)) return fail(CC_ERR_ARG, "null edge array with m > 0");
+    if (n > 0 && !out) return fail(CC_ERR_ARG, "null out_label with n > 0");
+    return CC_OK;
+}
+
+}  // namespace
+
+int32_t labels_impl(int32_t n, const int32_t* u, const int32_t* v, int64_t m, int32_t* out,
+                    const cc_options* opts, void* workspace, size_t ws_bytes, hipStream_t s,
+                    cc_stats* st) {
+    int32_t rc = check_args(n, u, v, m, out);
+    if (rc != CC_OK) return rc;
+    Plan p;
+    rc = make_plan(n, m, opts, p);
+    if (rc != CC_OK) return rc;
+    if (st) {
+        std::memset(st, 0, sizeof *st);
+        st->hook = p.hook;
+        st->segments = p.hook == CC_HOOK_ATOMIC ? p.segments : 0;
+        st->giant_label = -1;
+    }
+    if (n == 0) {
+        if (m > 0) return fail(CC_ERR_RANGE, "edge endpoint outside [0, n) (n == 0)");
+        return CC_OK;
+    }
+    const Layout L = layout(n, m, p);
+    PoolEntry* pe = pool_entry(s);
+    std::lock_guard<std::mutex> lk(pe->mu);
+    rc = ensure_host(pe);
+    if (rc != CC_OK) return rc;
+    char* ws;
+    if (workspace) {
+        if (ws_bytes < L.total) return fail(CC_ERR_NOMEM, "workspace smaller than cc_workspace_bytes()");
+        if ((uintptr_t)workspace & 255) return fail(CC_ERR_ARG, "workspace must be 256-byte aligned");
+        ws = static_cast<char*>(workspace);
+    } else {
+        rc = ensure_dev(pe, L.total);
+        if (rc != CC_OK) return rc;
+        ws = static_cast<char*>(pe->dev);
+    }
+    Timer tm;
+    tm.on = p.profile;
+    tm.s = s;
+    int64_t rounds = 0;
+    if (p.hook == CC_HOOK_ATOMIC) {
+        rc = enqueue_atomic(n, u, v, m, out, p, reinterpret_cast<Ctrl*>(ws),
+                            L.bits ? reinterpret_cast<uint32_t*>(ws + L.bits) : nullptr, s, tm, st);
+        if (rc == CC_OK) rc = finish(s, reinterpret_cast<Ctrl*>(ws), pe->host_ctrl, st);
+    } else if (p.host_loop != CC_HOST_LOOP_OFF) {
+        rc = solve_host_loop(n, u, v, m, out, p, ws, s, pe->host_ctrl, tm, st);
+    } else {
+        rc = solve_plain(n, u, v, m, out, p, ws, L, s, pe->host_ctrl, tm, st, &rounds);
+    }
+    if (rc != CC_OK && rc != CC_ERR_NOCONVERGE) return rc;
+    const Ctrl& c = *pe->host_ctrl;
+    tm.collect(st);
+    if (st) {
+        st->filter_used = (p.filter == CC_FILTER_GIANT && c.filter_on) ? 1 : 0;
+        st->giant_label = st->filter_used ? c.giant : -1;
+        if (p.hook == CC_HOOK_PLAIN && p.host_loop == CC_HOST_LOOP_OFF) {
+            st->rounds = c.rounds;
+            st->active_edges = c.active_round1;
+        }
+    }
+    if (c.status & kStatusRange) return fail(CC_ERR_RANGE, "edge endpoint outside [0, n)");
+    if (c.status & kStatusOverflow) return fail(CC_ERR_NOMEM, "frontier capacity exceeded");
+    return rc;
+}
+
+
+size_t workspace_bytes_impl(int32_t n, int64_t m, const cc_options* opts) {
+    if (n < 0 || m < 0) return 0;
+    Plan p;
+    if (make_plan(n, m, opts, p) != CC_OK) return 0;
+    return layout(n, m, p).total;
+}
+
+// ---------------------------------------------------------------------- graph lists
+// Small graphs (n <= CC_BATCH_LDS_MAX_N) go to one persistent LDS launch whose
+// workgroups take them largest first; every larger graph gets the device-memory
+// Atomic-Hook solve with its own control block.  Everything is enqueued on `s`
+// and the call ends with one synchronisation and one read of all control blocks.
+int32_t list_impl(int32_t count, const cc_graph* graphs, hipStream_t s, cc_stats* st) {
+    if (count < 0) return fail(CC_ERR_ARG, "graph count < 0");
+    if (st) {
+        std::memset(st, 0, sizeof *st);
+        st->giant_label = -1;
+    }
+    if (count == 0) return CC_OK;
+    if (!graphs) return fail(CC_ERR_ARG, "null graph list");
+    std::vector<int32_t> small, large;
+    int64_t maxn_small = 0;
+    for (int32_t g = 0; g < count; ++g) {
+        const cc_graph& G = graphs[g];
+        if (G.reserved != 0) return fail(CC_ERR_ARG, "cc_graph.reserved must be zero");
+        if (G.n < 0 || G.m < 0) return fail(CC_ERR_ARG, "graph with n < 0 or m < 0");
+        if (G.m > 0 && (!G.edges_u || !G.edges_v)) return fail(CC_ERR_ARG, "null edge array");
+        if (G.n > 0 && !G.out_label) return fail(CC_ERR_ARG, "null out_label");
+        if (G.n == 0) {
+            if (G.m > 0) return fail(CC_ERR_RANGE, "edge endpoint outside [0, n) (empty graph)");
+            continue;
+        }
+        if (G.n <= CC_BATCH_LDS_MAX_N) {
+            small.push_back(g);
+            maxn_small = std::max<int64_t>(maxn_small, G.n);
+        } else {
+            large.push_back(g);
+        }
+    }
+    // Largest first (longest-processing-time order): the queue's tail holds
+    // the small graphs, which even out the workgroups' finishing times.
+    std::stable_sort(small.begin(), small.end(), [&](int32_t a, int32_t b) {
+        return graphs[a].m + graphs[a].n > graphs[b].m + graphs[b].n;
+    });
+    const int32_t ns = (int32_t)small.size();
+    const int32_t nl = (int32_t)large.size();
+    std::vector<Plan> plans(nl);
+    std::vector<size_t> bits_off(nl, 0);
+    size_t off = align256((size_t)(1 + nl) * sizeof(Ctrl));
+    const size_t desc_off = off;
+    const size_t desc_bytes = align256((size_t)ns * sizeof(GraphDesc));
+    off += desc_bytes;
+    const size_t order_off = off;
+    const size_t order_bytes = align256((size_t)ns * 4);
+    off += order_bytes;
+    for (int32_t i = 0; i < nl; ++i) {
+        const cc_graph& G = graphs[large[i]];
+        int32_t rc = make_plan(G.n, G.m, nullptr, plans[i]);
+        if (rc != CC_OK) return rc;
+        if (plans[i].filter == CC_FILTER_GIANT) {
+            bits_off[i] = off;
+            off += align256(((size_t)G.n + 31) / 32 * 4);
+        }
+    }
+    PoolEntry* pe = pool_entry(s);
+    std::lock_guard<std::mutex> lk(pe->mu);
+    int32_t rc = ensure_host(pe, 1 + nl);
+    if (rc != CC_OK) return rc;
+    rc = ensure_dev(pe, off);
+    if (rc != CC_OK) return rc;
+    char* ws = static_cast<char*>(pe->dev);
+    Ctrl* ctrls = reinterpret_cast<Ctrl*>(ws);
+    HIPCHK(hipMemsetAsync(ctrls, 0, sizeof(Ctrl), s));
+    if (ns > 0) {
+        rc = ensure_stage(pe, desc_bytes + order_bytes);
+        if (rc != CC_OK) return rc;
+        GraphDesc* hd = static_cast<GraphDesc*>(pe->host_stage);
+        int32_t* ho = reinterpret_cast<int32_t*>(static_cast<char*>(pe->host_stage) + desc_bytes);
+        for (int32_t i = 0; i < ns; ++i) {
+            const cc_graph& G = graphs[small[i]];
+            GraphDesc d;
+            d.u = G.edges_u;
+            d.v = G.edges_v;
+            d.out = G.out_label;
+            d.m = G.m;
+            d.n = G.n;
+            // average-degree segmentation per graph (Section 3.B)
+            d.segments = (int32_t)std::max<int64_t>(1, (G.m + G.n / 2) / G.n);
+            hd[i] = d;
+            ho[i] = i;
+        }
+        HIPCHK(hipMemcpyAsync(ws + desc_off, pe->host_stage, desc_bytes + order_bytes,
+                              hipMemcpyHostToDevice, s));
+        HIPCHK(launch_batch_lds(reinterpret_cast<GraphDesc*>(ws + desc_off),
+                                reinterpret_cast<int32_t*>(ws + order_off), ns, (int32_t)maxn_small,
+                                &ctrls[0].queue_head, &ctrls[0].status, device_cu_count(), s));
+        if (st) st->hook_launches += 1;
+    }
+    Timer tm;
+    for (int32_t i = 0; i < nl; ++i) {
+        const cc_graph& G = graphs[large[i]];
+        rc = enqueue_atomic(G.n, G.edges_u, G.edges_v, G.m, G.out_label, plans[i], &ctrls[1 + i],
+                            bits_off[i] ? reinterpret_cast<uint32_t*>(ws + bits_off[i]) : nullptr,
+                            s, tm, st);
+        if (rc != CC_OK) return rc;
+    }
+    HIPCHK(hipMemcpyAsync(pe->host_ctrl, ctrls, sizeof(Ctrl) * (1 + nl), hipMemcpyDeviceToHost, s));
+    HIPCHK(hipStreamSynchronize(s));
+    if (st) st->host_syncs += 1;
+    for (int32_t i = 0; i <= nl; ++i)
+        if (pe->host_ctrl[i].status & kStatusRange)
+            return fail(CC_ERR_RANGE, "edge endpoint outside [0, n_g)");
+    return CC_OK;
+}
+
+int32_t batch_impl(int32_t B, const int64_t* vo, const int64_t* eo, const int32_t* u,
+                   const int32_t* v, int32_t* out, hipStream_t s, cc_stats* st) {
+    if (B < 0) return fail(CC_ERR_ARG, "num_graphs < 0");
+    if (B == 0) {
+        if (st) {
+            std::memset(st, 0, sizeof *st);
+            st->giant_label = -1;
+        }
+        return CC_OK;
+    }
+    if (!vo || !eo) return fail(CC_ERR_ARG, "null offsets");
+    if (vo[0] != 0 || eo[0] != 0) return fail(CC_ERR_ARG, "offsets must start at 0");
+    for (int32_t g = 0; g < B; ++g) {
+        const int64_t nv = vo[g + 1] - vo[g], ne = eo[g + 1] - eo[g];
+        if (nv < 0 || ne < 0) return fail(CC_ERR_ARG, "offsets must be non-decreasing");
+        if (nv > INT32_MAX) return fail(CC_ERR_ARG, "graph with 2^31 or more vertices");
+    }
+    if (eo[B] > 0 && (!u || !v)) return fail(CC_ERR_ARG, "null edge array");
+    if (vo[B] > 0 && !out) return fail(CC_ERR_ARG, "null out_label");
+    std::vector<cc_graph> list(B);
+    for (int32_t g = 0; g < B; ++g) {
+        cc_graph& G = list[g];
+        const int64_t ne = eo[g + 1] - eo[g];
+        G.edges_u = ne ? u + eo[g] : nullptr;
+        G.edges_v = ne ? v + eo[g] : nullptr;
+        G.out_label = out ? out + vo[g] : nullptr;
+        G.m = ne;
+        G.n = (int32_t)(vo[g + 1] - vo[g]);
+        G.reserved = 0;
+    }
+    return list_impl(B, list.data(), s, st);
+}
+
+// ---------------------------------------------------------------------- probes, release
+int32_t probe_impl(int32_t mode, const int32_t* u, const int32_t* v, int64_t m, const void* table,
+                   int32_t n, hipStream_t s) {
+    if (m < 0 || mode < 0 || mode > 2) return fail(CC_ERR_ARG, "bad probe arguments");
+    if (m > 0 && (!u || !v)) return fail(CC_ERR_ARG, "null edge array");
+    if (mode > 0 && (!table || n <= 0)) return fail(CC_ERR_ARG, "probe table required");
+    if (((uintptr_t)u & 15) || ((uintptr_t)v & 15))
+        return fail(CC_ERR_ARG, "probe edge arrays must be 16-byte aligned");
+    PoolEntry* pe = pool_entry(s);
+    std::lock_guard<std::mutex> lk(pe->mu);
+    int32_t rc = ensure_dev(pe, 256);
+    if (rc != CC_OK) return rc;
+    uint32_t* sink = static_cast<uint32_t*>(pe->dev);
+    if (mode == 0)
+        HIPCHK(launch_probe_stream(u, v, m, sink, s));
+    else if (mode == 1)
+        HIPCHK(launch_probe_gather(u, v, m, static_cast<const int32_t*>(table), n, sink, s));
+    else
+        HIPCHK(launch_probe_bitgather(u, v, m, static_cast<const uint32_t*>(table), n, sink, s));
+    return CC_OK;
+}
+
+void release_impl() {
+    std::lock_guard<std::mutex> g(g_pool_mu);
+    for (auto& kv : g_pool) {
+        PoolEntry* e = kv.second.get();
+        std::lock_guard<std::mutex> lk(e->mu);
+        if (e->dev) (void)hipFree(e->dev);
+        if (e->host_ctrl) (void)hipHostFree(e->host_ctrl);
+        if (e->host_stage) (void)hipHostFree(e->host_stage);
+        e->dev = nullptr;
+        e->host_ctrl = nullptr;
+        e->host_stage = nullptr;
+        e->bytes = e->stage_bytes = 0;
+        e->host_ctrl_count = 0;
+    }
+    g_pool.clear();
+}
+
+}  // namespace hookcc

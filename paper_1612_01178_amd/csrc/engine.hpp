@@ -1,0 +1,33 @@
+// Host engine of libhookcc: plans, workspace cache, launch sequences.
+// Internal; the public ABI is include/hookcc.h.
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <string>
+
+#include "../../include/hookcc.h"
+#include "kernels.hpp"
+
+namespace hookcc {
+
+// Records `msg` as the calling thread's last error and returns `code`.
+int32_t fail(int32_t code, const std::string& msg);
+const char* last_error();
+
+int32_t labels_impl(int32_t n, const int32_t* u, const int32_t* v, int64_t m, int32_t* out,
+                    const cc_options* opts, void* workspace, size_t ws_bytes, hipStream_t s,
+                    cc_stats* st);
+size_t workspace_bytes_impl(int32_t n, int64_t m, const cc_options* opts);
+
+// Independent graphs given by descriptors (device arrays); synchronous on s.
+int32_t list_impl(int32_t count, const cc_graph* graphs, hipStream_t s, cc_stats* st);
+// Graphs packed back to back with host offsets; synchronous on s.
+int32_t batch_impl(int32_t B, const int64_t* vo, const int64_t* eo, const int32_t* u,
+                   const int32_t* v, int32_t* out, hipStream_t s, cc_stats* st);
+
+int32_t probe_impl(int32_t mode, const int32_t* u, const int32_t* v, int64_t m, const void* table,
+                   int32_t n, hipStream_t s);
+void release_impl();
+
+}  // namespace hookcc

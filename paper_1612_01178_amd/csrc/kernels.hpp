@@ -42,6 +42,14 @@ hipError_t launch_compact(int round, const int32_t* u, const int32_t* v, int64_t
                           const int2* src, int2* dst, int64_t cap, const int32_t* pi, int32_t n,
                           Ctrl* ctrl, int block, int ept, int grid_cap, hipStream_t s);
 
+// Fig. 1 as a host loop: a Hook pass over all m entries that sets
+// ctrl->hook_changed when an entry's parents differ, and one level of Jump
+// (Fig. 2) over all vertices that sets ctrl->jump_changed when it moves a
+// pointer.
+hipError_t launch_hook_flag(const int32_t* u, const int32_t* v, int64_t m, int32_t* pi, int32_t n,
+                            Ctrl* ctrl, int block, int ept, hipStream_t s);
+hipError_t launch_jump(int32_t* pi, int32_t n, Ctrl* ctrl, hipStream_t s);
+
 // Streaming and gather probes used to measure the memory ceilings.
 hipError_t launch_probe_stream(const int32_t* u, const int32_t* v, int64_t m, uint32_t* sink,
                                hipStream_t s);

@@ -585,6 +585,92 @@ hipError_t launch_compact(int round, const int32_t* u, const int32_t* v, int64_t
     return hipGetLastError();
 }
 
+// ----------------------------------------------------------------------------- Fig. 1 host loop
+// Hook (Fig. 2) over every entry, raising ctrl->hook_changed (one store per
+// wave that saw an active entry) -- the flag the host reads after the launch.
+template <int EPT, bool VEC>
+__global__ __launch_bounds__(1024) void k_hook_flag(const int32_t* __restrict__ eu,
+                                                    const int32_t* __restrict__ ev, int64_t m,
+                                                    int32_t* pi, int32_t n, Ctrl* ctrl) {
+    const int64_t stride = (int64_t)blockDim.x * 4;
+    const int64_t e0 = (int64_t)blockIdx.x * blockDim.x * EPT + (int64_t)threadIdx.x * 4;
+    int32_t a[EPT], b[EPT];
+    load_edges<EPT, VEC>(eu, e0, stride, m, a);
+    load_edges<EPT, VEC>(ev, e0, stride, m, b);
+    bool bad = false, changed = false;
+    int32_t pa[EPT], pb[EPT];
+    uint32_t act = 0;
+#pragma unroll
+    for (int j = 0; j < EPT; ++j) {
+        const bool in = (uint32_t)a[j] < (uint32_t)n && (uint32_t)b[j] < (uint32_t)n;
+        bad |= !in;
+        if (in && a[j] != b[j]) {
+            act |= 1u << j;
+            pa[j] = ld_rlx(pi + a[j]);
+            pb[j] = ld_rlx(pi + b[j]);
+        }
+    }
+    if (bad) atomicOr(&ctrl->status, kStatusRange);
+#pragma unroll
+    for (int j = 0; j < EPT; ++j) {
+        if ((act >> j & 1) && pa[j] != pb[j]) {
+            st_rlx(pi + (pa[j] > pb[j] ? pa[j] : pb[j]), pa[j] > pb[j] ? pb[j] : pa[j]);
+            changed = true;
+        }
+    }
+    if (__ballot(changed) != 0 && (threadIdx.x & 63) == 0) ctrl->hook_changed = 1;
+}
+
+// One Jump (Fig. 2): pi(v) <- pi(pi(v)) for every vertex, raising
+// ctrl->jump_changed when any pointer moved.
+__global__ __launch_bounds__(256) void k_jump(int32_t* pi, int32_t n, Ctrl* ctrl) {
+    const int64_t x = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    bool changed = false;
+    if (x < n) {
+        const int32_t p = ld_rlx(pi + x);
+        const int32_t g = ld_rlx(pi + p);
+        if (g != p) {
+            st_rlx(pi + x, g);
+            changed = true;
+        }
+    }
+    if (__ballot(changed) != 0 && (threadIdx.x & 63) == 0) ctrl->jump_changed = 1;
+}
+
+hipError_t launch_hook_flag(const int32_t* u, const int32_t* v, int64_t m, int32_t* pi, int32_t n,
+                            Ctrl* ctrl, int block, int ept, hipStream_t s) {
+    if (m <= 0) return hipSuccess;
+    const int64_t tile = (int64_t)block * ept;
+    const int64_t grid64 = (m + tile - 1) / tile;
+    if (grid64 > 0x7fffffff) return hipErrorInvalidValue;
+    const int grid = (int)grid64;
+    const bool vec = aligned16(u) && aligned16(v);
+    switch (ept) {
+        case 4:
+            vec ? k_hook_flag<4, true><<<grid, block, 0, s>>>(u, v, m, pi, n, ctrl)
+                : k_hook_flag<4, false><<<grid, block, 0, s>>>(u, v, m, pi, n, ctrl);
+            break;
+        case 8:
+            vec ? k_hook_flag<8, true><<<grid, block, 0, s>>>(u, v, m, pi, n, ctrl)
+                : k_hook_flag<8, false><<<grid, block, 0, s>>>(u, v, m, pi, n, ctrl);
+            break;
+        case 16:
+            vec ? k_hook_flag<16, true><<<grid, block, 0, s>>>(u, v, m, pi, n, ctrl)
+                : k_hook_flag<16, false><<<grid, block, 0, s>>>(u, v, m, pi, n, ctrl);
+            break;
+        default:
+            return hipErrorInvalidValue;
+    }
+    return hipGetLastError();
+}
+
+hipError_t launch_jump(int32_t* pi, int32_t n, Ctrl* ctrl, hipStream_t s) {
+    if (n <= 0) return hipSuccess;
+    const int grid = (int)(((int64_t)n + 255) / 256);
+    k_jump<<<grid, 256, 0, s>>>(pi, n, ctrl);
+    return hipGetLastError();
+}
+
 int device_cu_count() {
     int dev = 0, cus = 0;
     if (hipGetDevice(&dev) != hipSuccess) return 256;

@@ -40,6 +40,8 @@ VARIANTS = {
     "plain_b128_e16_k1": cc.Options(hook="plain", edges_per_thread=16, block=128,
                                     rounds_per_check=1),
     "plain_e4_k7": cc.Options(hook="plain", edges_per_thread=4, rounds_per_check=7),
+    "hostloop_jump": cc.Options(hook="plain", host_loop="jump"),
+    "hostloop_multijump": cc.Options(hook="plain", host_loop="multijump", edges_per_thread=16),
 }
 
 

@@ -53,8 +53,14 @@ def main():
     ap.add_argument("--ept", type=int, default=0)
     ap.add_argument("--block", type=int, default=0)
     ap.add_argument("--profile-steps", type=int, default=3)
+    ap.add_argument("--coherent", action="store_true", help="agent-scope tree loads (A/B only)")
     ap.add_argument("--skip-cpu", action="store_true")
     ap.add_argument("--skip-batch", action="store_true")
+    ap.add_argument("--mode", default="solve", choices=["solve", "ablation", "serving"],
+                    help="solve: the headline line; ablation: the paper's Fig. 5/6 variants "
+                         "on --workloads; serving: the request-server experiment")
+    ap.add_argument("--workloads", default="er16,grid4k,rmat24")
+    ap.add_argument("--requests", type=int, default=300)
     args = ap.parse_args()
 
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
@@ -70,8 +76,15 @@ def main():
 
     dev = torch.device("cuda:0")
     cc.load()
+    if args.mode == "ablation":
+        return ablation(cc, torch, dev, args)
+    if args.mode == "serving":
+        print(json.dumps({"mode": "serving",
+                          "results": serving(cc, torch, dev, args.requests,
+                                             loads=(0.5, 0.7, 0.9), host_mode=True)}), flush=True)
+        return
     opts = cc.Options(hook=args.hook, filter=args.filter, segments=args.segments,
-                      edges_per_thread=args.ept, block=args.block)
+                      edges_per_thread=args.ept, block=args.block, coherent_loads=args.coherent)
 
     log("generating", args.workload)
     t = time.time()
@@ -112,6 +125,7 @@ def main():
         comp_ms += st["compress_ms"]
         other_ms += st["other_ms"]
     k = max(args.profile_steps, 1)
+    st = st or {"segments": None, "filter_used": None}
     hook_ms, comp_ms, other_ms = hook_ms / k, comp_ms / k, other_ms / k
     if args.hook == "atomic":
         alg_bytes = 8.0 * m  # each int32 (u, v) entry read once across the Atomic-Hook launches
@@ -176,8 +190,147 @@ def main():
 
     if not args.skip_batch:
         result["batch"] = bench_batch(cc, torch, dev)
+        result["serving"] = serving(cc, torch, dev, args.requests, loads=(0.7,), host_mode=False)
 
     print(json.dumps(result), flush=True)
+
+
+ABLATION = [
+    # Fig. 5 progression, then this build's additions
+    ("fig1_hostloop_jump", dict(hook="plain", host_loop="jump")),
+    ("fig1_hostloop_multijump", dict(hook="plain", host_loop="multijump")),
+    ("atomic_hook_s1", dict(hook="atomic", segments=1, filter="off")),
+    ("adaptive_fig4", dict(hook="atomic", filter="off")),
+    ("adaptive_giant_filter", dict(hook="atomic", filter="giant")),
+    ("plain_device_convergence", dict(hook="plain")),
+]
+SEGMENT_SWEEP = [1, 2, 4, 8, 16, 32, 64, 128]
+
+
+def ablation(cc, torch, dev, args, reps=5):
+    """The paper's ablation (Fig. 5) and segmentation sweep (Fig. 6) with this
+    build's kernels: median ms per solve of each variant on each workload,
+    every result checked against the oracle digest."""
+    import numpy as np
+    import graphgen
+    golden = json.load(open(os.path.join(ROOT, "tests", "golden", "oracle_digests.json")))
+    results = {}
+    for name in args.workloads.split(","):
+        log("ablation workload", name)
+        u_np, v_np, n = graphgen.workload(name)
+        m = len(u_np)
+        u = torch.from_numpy(u_np).to(dev)
+        v = torch.from_numpy(v_np).to(dev)
+        del u_np, v_np
+        out = torch.empty(n, dtype=torch.int32, device=dev)
+        rows = {}
+        variants = list(ABLATION) + [("fig6_s%d" % s, dict(hook="atomic", filter="off", segments=s))
+                                     for s in SEGMENT_SWEEP]
+        for vname, kw in variants:
+            opt = cc.Options(**kw)
+            cc.labels(u, v, n, out=out, options=opt)
+            times = []
+            for _ in range(reps):
+                torch.cuda.synchronize()
+                t = time.perf_counter()
+                _, st = cc.labels(u, v, n, out=out, options=opt, return_stats=True)
+                times.append((time.perf_counter() - t) * 1e3)
+            ok = digest(out.cpu().numpy()) == golden[name]["sha256"]
+            med = float(np.median(times))
+            rows[vname] = {"ms": round(med, 4), "edges_per_s": m / (med * 1e-3), "parity": ok,
+                           "segments": st["segments"], "rounds": st["rounds"],
+                           "host_syncs": st["host_syncs"],
+                           "launches": st["hook_launches"] + st["compress_launches"]}
+            log("  %-28s %9.3f ms  parity=%s syncs=%d" % (vname, med, ok, st["host_syncs"]))
+        base = rows["fig1_hostloop_jump"]["ms"]
+        for r in rows.values():
+            r["speedup_vs_fig1"] = round(base / r["ms"], 3)
+        results[name] = {"n": n, "m": m, "variants": rows}
+        del u, v, out
+        torch.cuda.empty_cache()
+    print(json.dumps({"mode": "ablation", "results": results}), flush=True)
+
+
+def serving(cc, torch, dev, requests, loads=(0.5, 0.7, 0.9), host_mode=False, pool_size=32,
+            warm=20, seed=1005):
+    """Continuous-batching server vs a FIFO one-request-at-a-time server on a
+    Poisson stream of R-MAT requests (scale U{10..22}, edge factor U{8..32},
+    a/b/c = .57/.19/.19, permuted, not symmetrised) drawn from a seeded pool.
+
+    Device mode: request edges already in HBM, latency = submit -> labels in
+    HBM.  Host mode adds the PCIe copies (edges in, labels out).  For each
+    server the saturation rate is measured closed-loop first; open-loop runs
+    at the given fractions of the batched server's saturation rate report
+    p50/p99 latency, achieved req/s and edges/s."""
+    import numpy as np
+    import graphgen
+    scales, efs = graphgen.serving_request_shapes(pool_size, seed=seed)
+    log("serving: generating a pool of %d requests" % pool_size)
+    pool = [graphgen.serving_request(i, int(scales[i]), int(efs[i]), seed=seed)
+            for i in range(pool_size)]
+    dpool = [(torch.from_numpy(u).to(dev), torch.from_numpy(v).to(dev), n) for u, v, n in pool]
+    torch.cuda.synchronize()
+    pick = graphgen.draws(seed, 3, warm + requests) % np.uint64(pool_size)
+    pick = pick.astype(np.int64)
+
+    def submit(srv, i):
+        u, v, n = (pool if host_mode else dpool)[pick[i]]
+        return srv.submit(u, v, n)
+
+    def closed_loop(srv, count):
+        t = time.perf_counter()
+        tickets = [submit(srv, i % len(pick)) for i in range(count)]
+        for tk in tickets:
+            srv.wait(tk)
+        return count / (time.perf_counter() - t)
+
+    def open_loop(srv, rate):
+        arr = graphgen.poisson_arrivals(warm + requests, rate, seed + 7)
+        tickets = []
+        t0 = time.perf_counter()
+        for i in range(warm + requests):
+            while True:
+                dt = arr[i] - (time.perf_counter() - t0)
+                if dt <= 0:
+                    break
+                if dt > 2e-4:
+                    time.sleep(dt - 1e-4)
+            tickets.append(submit(srv, i))
+        infos = [srv.wait(tk)[1] for tk in tickets]
+        span = time.perf_counter() - t0
+        key = "t_host_done" if host_mode else "t_device_done"
+        lat = np.array([(x[key] - x["t_submit"]) * 1e3 for x in infos[warm:]])
+        bs = np.array([x["batch_size"] for x in infos[warm:]])
+        edges = sum(len(pool[pick[i]][0]) for i in range(warm, warm + requests))
+        t_first = infos[warm]["t_submit"]
+        t_last = max(x[key] for x in infos[warm:])
+        return {"offered_req_per_s": round(rate, 1),
+                "achieved_req_per_s": round(requests / (t_last - t_first), 1),
+                "edges_per_s": edges / (t_last - t_first),
+                "p50_ms": round(float(np.percentile(lat, 50)), 3),
+                "p99_ms": round(float(np.percentile(lat, 99)), 3),
+                "mean_batch": round(float(bs.mean()), 2)}
+
+    out = {"mode": "host (PCIe copies in latency)" if host_mode else "device-resident requests",
+           "pool": pool_size, "requests": requests, "warmup": warm}
+    servers = {"batched": dict(workers=3, max_batch=256),
+               "fifo_single": dict(workers=1, max_batch=1)}
+    sat = {}
+    for name, cfg in servers.items():
+        with cc.Server(**cfg) as srv:
+            closed_loop(srv, warm)
+            sat[name] = closed_loop(srv, requests)
+        log("serving: %s saturation %.1f req/s" % (name, sat[name]))
+    out["saturation_req_per_s"] = {k: round(x, 1) for k, x in sat.items()}
+    for frac in loads:
+        rate = frac * sat["batched"]
+        row = {}
+        for name, cfg in servers.items():
+            with cc.Server(**cfg) as srv:
+                row[name] = open_loop(srv, rate)
+            log("serving: load %.2f %s %s" % (frac, name, row[name]))
+        out["load_%.2f" % frac] = row
+    return out
 
 
 def probe_ceilings(cc, torch, u, v, n, m, reps=5):

@@ -94,7 +94,12 @@ typedef struct cc_options {
                                  convergence and compaction), CC_HOST_LOOP_JUMP (Compress as
                                  repeated single-level Jump launches, Fig. 2) or
                                  CC_HOST_LOOP_MULTIJUMP (Compress as one Multi-Jump)    */
-    int32_t reserved[6];      /* must be zero                                           */
+    int32_t coherent_loads;   /* Atomic-Hook path: 1 = tree loads and stores are coherent
+                                 across the XCDs (agent scope, served beyond the per-XCD
+                                 L2); 0 (default) = cached loads, which may return an
+                                 older ancestor -- always a valid one (kept for
+                                 measurement; results are identical)                   */
+    int32_t reserved[5];      /* must be zero                                           */
 } cc_options;
 
 #define CC_HOST_LOOP_OFF 0

@@ -56,7 +56,7 @@ class _COptions(ctypes.Structure):
                 ("block", ctypes.c_int32), ("edges_per_thread", ctypes.c_int32),
                 ("max_rounds", ctypes.c_int32), ("rounds_per_check", ctypes.c_int32),
                 ("profile", ctypes.c_int32), ("host_loop", ctypes.c_int32),
-                ("reserved", ctypes.c_int32 * 6)]
+                ("coherent_loads", ctypes.c_int32), ("reserved", ctypes.c_int32 * 5)]
 
 
 class _CStats(ctypes.Structure):
@@ -101,6 +101,7 @@ class Options:
     rounds_per_check: int = 0
     profile: bool = False
     host_loop: str = "off"
+    coherent_loads: bool = False
 
     def _c(self) -> _COptions:
         o = _COptions()
@@ -114,6 +115,7 @@ class Options:
         o.rounds_per_check = self.rounds_per_check
         o.profile = 1 if self.profile else 0
         o.host_loop = _HOST_LOOPS[self.host_loop]
+        o.coherent_loads = 1 if self.coherent_loads else 0
         return o
 
 

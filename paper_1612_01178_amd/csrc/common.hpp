@@ -41,19 +41,33 @@ struct GraphDesc {
 };
 static_assert(sizeof(GraphDesc) == 40, "descriptor layout");
 
-// Relaxed atomic accesses of the tree array.  The races on pi are part of the
-// method (concurrent hooks and jumps, Section 3): every value a load can
-// return is some ancestor of the vertex, which is all the algorithm needs, and
-// the atomic forms keep the compiler from caching, merging or dropping the
-// accesses inside the climbing loops.  Agent scope: the kernels of one solve
-// run on every CU of the device.
-__device__ __forceinline__ int32_t ld_rlx(const int32_t* p) {
-    return __hip_atomic_load(p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+// Accesses of the tree array pi.
+//
+// The races on pi are part of the method (concurrent hooks and jumps,
+// Section 3): every value pi[x] ever holds is x itself or an ancestor of x,
+// and values only move up the tree, so a load that returns an out-of-date
+// value still returns a valid ancestor.  The climbing loops only need that
+// (each kernel states why it stays correct and finite), so loads and the
+// plain stores are relaxed atomics of WORKGROUP scope: ordinary cached
+// accesses on gfx950 that hit in L1 / the XCD's L2 and may not yet see a
+// value another XCD wrote during the same kernel.  Kernel boundaries make
+// every earlier write visible.  Only the compare-and-swap that takes a root
+// must be device-coherent, so it is an AGENT-scope atomic.  COH = true makes
+// the loads and stores agent scope as well (coherent across XCDs, served
+// beyond the per-XCD L2); it is kept for measurement.
+template <bool COH>
+__device__ __forceinline__ int32_t ld_tree(const int32_t* p) {
+    if (COH) return __hip_atomic_load(p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    return __hip_atomic_load(p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
 }
-__device__ __forceinline__ void st_rlx(int32_t* p, int32_t x) {
-    __hip_atomic_store(p, x, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+template <bool COH>
+__device__ __forceinline__ void st_tree(int32_t* p, int32_t x) {
+    if (COH) __hip_atomic_store(p, x, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    else __hip_atomic_store(p, x, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
 }
-__device__ __forceinline__ int32_t cas_rlx(int32_t* p, int32_t expected, int32_t desired) {
+__device__ __forceinline__ int32_t ld_rlx(const int32_t* p) { return ld_tree<false>(p); }
+__device__ __forceinline__ void st_rlx(int32_t* p, int32_t x) { st_tree<false>(p, x); }
+__device__ __forceinline__ int32_t cas_root(int32_t* p, int32_t expected, int32_t desired) {
     __hip_atomic_compare_exchange_strong(p, &expected, desired, __ATOMIC_RELAXED,
                                          __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
     return expected;  // the value found (== the old expected on success)

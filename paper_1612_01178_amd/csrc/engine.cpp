@@ -56,6 +56,7 @@ struct Plan {
     int rounds_per_check = 4;
     bool profile = false;
     int host_loop = CC_HOST_LOOP_OFF;
+    bool coherent = false;
 };
 
 int32_t make_plan(int32_t n, int64_t m, const cc_options* o, Plan& p) {
@@ -63,8 +64,11 @@ int32_t make_plan(int32_t n, int64_t m, const cc_options* o, Plan& p) {
     std::memset(&d, 0, sizeof d);
     d.filter = CC_FILTER_AUTO;
     const cc_options& op = o ? *o : d;
-    for (int i = 0; i < 6; ++i)
+    for (int i = 0; i < 5; ++i)
         if (op.reserved[i] != 0) return fail(CC_ERR_ARG, "cc_options.reserved must be zero");
+    if (op.coherent_loads != 0 && op.coherent_loads != 1)
+        return fail(CC_ERR_ARG, "cc_options.coherent_loads must be 0 or 1");
+    p.coherent = op.coherent_loads == 1;
     if (op.hook != CC_HOOK_ATOMIC && op.hook != CC_HOOK_PLAIN)
         return fail(CC_ERR_ARG, "unknown cc_options.hook");
     p.hook = op.hook;
@@ -278,8 +282,8 @@ int32_t enqueue_atomic(int32_t n, const int32_t* u, const int32_t* v, int64_t m,
         // Fig. 4: for each segment, Atomic-Hook the segment, then Multi-Jump all of V.
         for (int i = 0; i < S; ++i) {
             TIMED(kPhaseHook, launch_ahook(u, v, bound(i), bound(i + 1), pi, n, ctrl, nullptr,
-                                           p.block, p.ept, s));
-            TIMED(kPhaseCompress, launch_mj(pi, n, nullptr, s));
+                                           p.block, p.ept, p.coherent, s));
+            TIMED(kPhaseCompress, launch_mj(pi, n, nullptr, p.coherent, s));
             ++hooks;
             ++jumps;
         }
@@ -287,8 +291,8 @@ int32_t enqueue_atomic(int32_t n, const int32_t* u, const int32_t* v, int64_t m,
         const int fa = p.filter_after;
         for (int i = 0; i < fa; ++i) {
             TIMED(kPhaseHook, launch_ahook(u, v, bound(i), bound(i + 1), pi, n, ctrl, nullptr,
-                                           p.block, p.ept, s));
-            TIMED(kPhaseCompress, launch_mj(pi, n, nullptr, s));
+                                           p.block, p.ept, p.coherent, s));
+            TIMED(kPhaseCompress, launch_mj(pi, n, nullptr, p.coherent, s));
             ++hooks;
             ++jumps;
         }
@@ -300,8 +304,8 @@ int32_t enqueue_atomic(int32_t n, const int32_t* u, const int32_t* v, int64_t m,
         while (g < S) {
             const int64_t h = std::min<int64_t>(S, g + step);
             TIMED(kPhaseHook, launch_ahook(u, v, bound(g), bound(h), pi, n, ctrl, bits, p.block,
-                                           p.ept, s));
-            TIMED(kPhaseCompress, launch_mj(pi, n, nullptr, s));
+                                           p.ept, p.coherent, s));
+            TIMED(kPhaseCompress, launch_mj(pi, n, nullptr, p.coherent, s));
             ++hooks;
             ++jumps;
             if (h < S) TIMED(kPhaseOther, launch_bitmap(pi, n, ctrl, bits, s));
@@ -334,7 +338,7 @@ int32_t solve_plain(int32_t n, const int32_t* u, const int32_t* v, int64_t m, in
             TIMED(kPhaseHook, launch_hook_plain((int)r, u, v, work, src, pi, n, ctrl, p.block,
                                                 p.ept, grid_cap, s));
             TIMED(kPhaseCompress,
-                  launch_mj(pi, n, r == 1 ? nullptr : &ctrl->count[(r - 1) & 1], s));
+                  launch_mj(pi, n, r == 1 ? nullptr : &ctrl->count[(r - 1) & 1], false, s));
             TIMED(kPhaseHook, launch_compact((int)r, u, v, work, src, dst, L.cap, pi, n, ctrl,
                                              p.block, p.ept, grid_cap, s));
             hooks += 2;
@@ -382,7 +386,7 @@ int32_t solve_host_loop(int32_t n, const int32_t* u, const int32_t* v, int64_t m
         if (hctrl->status) break;
         const bool hooked = hctrl->hook_changed != 0;
         if (p.host_loop == CC_HOST_LOOP_MULTIJUMP) {
-            TIMED(kPhaseCompress, launch_mj(pi, n, nullptr, s));
+            TIMED(kPhaseCompress, launch_mj(pi, n, nullptr, p.coherent, s));
             ++jumps;
         } else {
             while (true) {

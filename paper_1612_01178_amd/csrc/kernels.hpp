@@ -12,11 +12,12 @@ hipError_t launch_init(int32_t* pi, int32_t n, Ctrl* ctrl, hipStream_t s);
 // giant-component filter is applied (only if ctrl->filter_on is set).
 hipError_t launch_ahook(const int32_t* u, const int32_t* v, int64_t begin, int64_t end,
                         int32_t* pi, int32_t n, Ctrl* ctrl, const uint32_t* bits, int block,
-                        int ept, hipStream_t s);
+                        int ept, bool coherent, hipStream_t s);
 
 // Multi-Jump (Fig. 3) over all n vertices.  When `gate` is non-null the
-// kernel does nothing if *gate == 0.
-hipError_t launch_mj(int32_t* pi, int32_t n, const uint32_t* gate, hipStream_t s);
+// kernel does nothing if *gate == 0.  `coherent` selects agent-scope tree
+// loads and stores (see common.hpp).
+hipError_t launch_mj(int32_t* pi, int32_t n, const uint32_t* gate, bool coherent, hipStream_t s);
 
 // Giant-component sample: label of the component that holds the most of
 // `samples` edge endpoints drawn across entries [0, m); sets ctrl->giant and

@@ -54,18 +54,26 @@ __device__ __forceinline__ void load_edges(const int32_t* __restrict__ p, int64_
 // (Fig. 3, top; Section 3.A).  While the two parents differ, the larger one,
 // H, is hooked under the smaller one, L, by a compare-and-swap that succeeds
 // only if H is still a root (pi[H] == H), so no existing link is ever
-// overwritten.  When the CAS fails, H already has a parent; the pair to join
-// becomes (parent of the value found at pi[H], parent of L), one level up.
-// Every value written is smaller than the slot's index, so no cycle can form,
-// and the loop ends because max(pu, pv) strictly decreases.
+// overwritten.  When H already has a parent, the pair to join becomes
+// (parent of that parent, parent of L), one level up.  A cached read of pi[H]
+// comes first: if it already shows a parent (values only decrease, so it
+// cannot be wrong about that), the doomed CAS is skipped and the climb uses
+// the value read; only apparent roots are CAS'd.  Every value written is
+// smaller than the slot's index, so no cycle can form, and the loop ends
+// because max(pu, pv) strictly decreases (every value read at a slot is at
+// most the slot's index, and below it once the slot is not a root).
+template <bool COH>
 __device__ __forceinline__ void atomic_hook(int32_t* pi, int32_t pu, int32_t pv) {
     while (pu != pv) {
         const int32_t H = pu > pv ? pu : pv;
         const int32_t L = pu > pv ? pv : pu;
-        const int32_t found = cas_rlx(pi + H, H, L);
-        if (found == H) return;
-        pu = ld_rlx(pi + found);
-        pv = ld_rlx(pi + L);
+        int32_t found = ld_tree<COH>(pi + H);
+        if (found == H) {
+            found = cas_root(pi + H, H, L);
+            if (found == H) return;
+        }
+        pu = ld_tree<COH>(pi + found);
+        pv = ld_tree<COH>(pi + L);
     }
 }
 
@@ -110,7 +118,7 @@ hipError_t launch_init(int32_t* pi, int32_t n, Ctrl* ctrl, hipStream_t s) {
 // satisfied and is skipped; an endpoint with its bit set starts its climb at
 // g instead of gathering pi (any vertex of the endpoint's tree is a valid
 // start for Atomic-Hook, since only tree membership matters).
-template <int EPT, bool VEC, bool FILTER>
+template <int EPT, bool VEC, bool FILTER, bool COH>
 __global__ __launch_bounds__(1024) void k_ahook(const int32_t* __restrict__ eu,
                                                 const int32_t* __restrict__ ev, int64_t begin,
                                                 int64_t end, int32_t* pi, int32_t n, Ctrl* ctrl,
@@ -142,8 +150,8 @@ __global__ __launch_bounds__(1024) void k_ahook(const int32_t* __restrict__ eu,
                 if (ba & bb) {
                     act &= ~(1u << j);
                 } else {
-                    pa[j] = ba ? g : ld_rlx(pi + a[j]);
-                    pb[j] = bb ? g : ld_rlx(pi + b[j]);
+                    pa[j] = ba ? g : ld_tree<COH>(pi + a[j]);
+                    pb[j] = bb ? g : ld_tree<COH>(pi + b[j]);
                 }
             }
         }
@@ -151,31 +159,44 @@ __global__ __launch_bounds__(1024) void k_ahook(const int32_t* __restrict__ eu,
 #pragma unroll
         for (int j = 0; j < EPT; ++j) {
             if (act >> j & 1) {
-                pa[j] = ld_rlx(pi + a[j]);
-                pb[j] = ld_rlx(pi + b[j]);
+                pa[j] = ld_tree<COH>(pi + a[j]);
+                pb[j] = ld_tree<COH>(pi + b[j]);
             }
         }
     }
 #pragma unroll
     for (int j = 0; j < EPT; ++j)
-        if (act >> j & 1) atomic_hook(pi, pa[j], pb[j]);
+        if (act >> j & 1) atomic_hook<COH>(pi, pa[j], pb[j]);
 }
 
-template <int EPT, bool FILTER>
+template <int EPT, bool FILTER, bool COH>
 static void ahook_dispatch(bool vec, int grid, int block, hipStream_t s, const int32_t* u,
                            const int32_t* v, int64_t begin, int64_t end, int32_t* pi, int32_t n,
                            Ctrl* ctrl, const uint32_t* bits) {
     if (vec)
-        k_ahook<EPT, true, FILTER><<<grid, block, 0, s>>>(u, v, begin, end, pi, n, ctrl, bits);
+        k_ahook<EPT, true, FILTER, COH><<<grid, block, 0, s>>>(u, v, begin, end, pi, n, ctrl, bits);
     else
-        k_ahook<EPT, false, FILTER><<<grid, block, 0, s>>>(u, v, begin, end, pi, n, ctrl, bits);
+        k_ahook<EPT, false, FILTER, COH><<<grid, block, 0, s>>>(u, v, begin, end, pi, n, ctrl, bits);
+}
+
+template <int EPT>
+static void ahook_dispatch2(bool vec, bool filter, bool coh, int grid, int block, hipStream_t s,
+                            const int32_t* u, const int32_t* v, int64_t begin, int64_t end,
+                            int32_t* pi, int32_t n, Ctrl* ctrl, const uint32_t* bits) {
+    if (filter) {
+        if (coh) ahook_dispatch<EPT, true, true>(vec, grid, block, s, u, v, begin, end, pi, n, ctrl, bits);
+        else ahook_dispatch<EPT, true, false>(vec, grid, block, s, u, v, begin, end, pi, n, ctrl, bits);
+    } else {
+        if (coh) ahook_dispatch<EPT, false, true>(vec, grid, block, s, u, v, begin, end, pi, n, ctrl, bits);
+        else ahook_dispatch<EPT, false, false>(vec, grid, block, s, u, v, begin, end, pi, n, ctrl, bits);
+    }
 }
 
 static bool aligned16(const void* p) { return ((uintptr_t)p & 15) == 0; }
 
 hipError_t launch_ahook(const int32_t* u, const int32_t* v, int64_t begin, int64_t end,
                         int32_t* pi, int32_t n, Ctrl* ctrl, const uint32_t* bits, int block,
-                        int ept, hipStream_t s) {
+                        int ept, bool coherent, hipStream_t s) {
     if (end <= begin) return hipSuccess;
     const int64_t tile = (int64_t)block * ept;
     const int64_t grid64 = (end - begin + tile - 1) / tile;
@@ -184,20 +205,10 @@ hipError_t launch_ahook(const int32_t* u, const int32_t* v, int64_t begin, int64
     const bool vec = aligned16(u + begin) && aligned16(v + begin);
     const bool f = bits != nullptr;
     switch (ept) {
-        case 4:
-            f ? ahook_dispatch<4, true>(vec, grid, block, s, u, v, begin, end, pi, n, ctrl, bits)
-              : ahook_dispatch<4, false>(vec, grid, block, s, u, v, begin, end, pi, n, ctrl, bits);
-            break;
-        case 8:
-            f ? ahook_dispatch<8, true>(vec, grid, block, s, u, v, begin, end, pi, n, ctrl, bits)
-              : ahook_dispatch<8, false>(vec, grid, block, s, u, v, begin, end, pi, n, ctrl, bits);
-            break;
-        case 16:
-            f ? ahook_dispatch<16, true>(vec, grid, block, s, u, v, begin, end, pi, n, ctrl, bits)
-              : ahook_dispatch<16, false>(vec, grid, block, s, u, v, begin, end, pi, n, ctrl, bits);
-            break;
-        default:
-            return hipErrorInvalidValue;
+        case 4: ahook_dispatch2<4>(vec, f, coherent, grid, block, s, u, v, begin, end, pi, n, ctrl, bits); break;
+        case 8: ahook_dispatch2<8>(vec, f, coherent, grid, block, s, u, v, begin, end, pi, n, ctrl, bits); break;
+        case 16: ahook_dispatch2<16>(vec, f, coherent, grid, block, s, u, v, begin, end, pi, n, ctrl, bits); break;
+        default: return hipErrorInvalidValue;
     }
     return hipGetLastError();
 }
@@ -217,7 +228,7 @@ hipError_t launch_ahook(const int32_t* u, const int32_t* v, int64_t begin, int64
 // with ancestors), so "grandparent == parent" holds exactly when the parent is
 // a root: on exit every vertex points at its tree's root, i.e. at the minimum
 // id of its tree.
-template <bool VEC>
+template <bool VEC, bool COH>
 __global__ __launch_bounds__(256) void k_mj(int32_t* pi, int32_t n, const uint32_t* gate) {
     if (gate != nullptr && *gate == 0) return;
     const int64_t base = ((int64_t)blockIdx.x * blockDim.x + threadIdx.x) * 4;
@@ -230,30 +241,32 @@ __global__ __launch_bounds__(256) void k_mj(int32_t* pi, int32_t n, const uint32
         p[3] = q.w;
     } else {
 #pragma unroll
-        for (int j = 0; j < 4; ++j) p[j] = (base + j < n) ? ld_rlx(pi + base + j) : (int32_t)(base + j);
+        for (int j = 0; j < 4; ++j)
+            p[j] = (base + j < n) ? ld_tree<COH>(pi + base + j) : (int32_t)(base + j);
     }
     int32_t gp[4];
 #pragma unroll
-    for (int j = 0; j < 4; ++j) gp[j] = (p[j] != base + j) ? ld_rlx(pi + p[j]) : p[j];
+    for (int j = 0; j < 4; ++j) gp[j] = (p[j] != base + j) ? ld_tree<COH>(pi + p[j]) : p[j];
 #pragma unroll
     for (int j = 0; j < 4; ++j) {
         int32_t q = p[j], g = gp[j];
         while (g != q) {
-            st_rlx(pi + base + j, g);
+            st_tree<COH>(pi + base + j, g);
             q = g;
-            g = ld_rlx(pi + q);
+            g = ld_tree<COH>(pi + q);
         }
     }
 }
 
-hipError_t launch_mj(int32_t* pi, int32_t n, const uint32_t* gate, hipStream_t s) {
+hipError_t launch_mj(int32_t* pi, int32_t n, const uint32_t* gate, bool coherent, hipStream_t s) {
     if (n <= 0) return hipSuccess;
     const int64_t groups = ((int64_t)n + 3) / 4;
     const int grid = (int)((groups + 255) / 256);
-    if (((uintptr_t)pi & 15) == 0)
-        k_mj<true><<<grid, 256, 0, s>>>(pi, n, gate);
-    else
-        k_mj<false><<<grid, 256, 0, s>>>(pi, n, gate);
+    const bool vec = ((uintptr_t)pi & 15) == 0;
+    if (vec && coherent) k_mj<true, true><<<grid, 256, 0, s>>>(pi, n, gate);
+    else if (vec) k_mj<true, false><<<grid, 256, 0, s>>>(pi, n, gate);
+    else if (coherent) k_mj<false, true><<<grid, 256, 0, s>>>(pi, n, gate);
+    else k_mj<false, false><<<grid, 256, 0, s>>>(pi, n, gate);
     return hipGetLastError();
 }
 

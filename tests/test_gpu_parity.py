@@ -40,6 +40,8 @@ VARIANTS = {
     "plain_b128_e16_k1": cc.Options(hook="plain", edges_per_thread=16, block=128,
                                     rounds_per_check=1),
     "plain_e4_k7": cc.Options(hook="plain", edges_per_thread=4, rounds_per_check=7),
+    "coherent_giant": cc.Options(coherent_loads=True, segments=6, filter="giant"),
+    "coherent_s3": cc.Options(coherent_loads=True, segments=3, filter="off", block=128),
     "hostloop_jump": cc.Options(hook="plain", host_loop="jump"),
     "hostloop_multijump": cc.Options(hook="plain", host_loop="multijump", edges_per_thread=16),
 }
@@ -315,7 +317,7 @@ def test_full_size_workloads_match_oracle_digest(dev, name):
     assert (n, len(u)) == (rec["n"], rec["m"])
     du, dv = to_dev(u, dev), to_dev(v, dev)
     del u, v
-    for opt in ("default", "plain", "s1"):
+    for opt in ("default", "plain", "s1", "coherent_giant"):
         if name == "rmat24" and opt == "s1":
             opt = "s9_giant_after3"
         say("full size", name, opt)

@@ -56,7 +56,7 @@ def main():
     ap.add_argument("--coherent", action="store_true", help="agent-scope tree loads (A/B only)")
     ap.add_argument("--skip-cpu", action="store_true")
     ap.add_argument("--skip-batch", action="store_true")
-    ap.add_argument("--mode", default="solve", choices=["solve", "ablation", "serving"],
+    ap.add_argument("--mode", default="solve", choices=["solve", "ablation", "serving", "tune"],
                     help="solve: the headline line; ablation: the paper's Fig. 5/6 variants "
                          "on --workloads; serving: the request-server experiment")
     ap.add_argument("--workloads", default="er16,grid4k,rmat24")
@@ -78,6 +78,21 @@ def main():
     cc.load()
     if args.mode == "ablation":
         return ablation(cc, torch, dev, args)
+    if args.mode == "tune":
+        from paper_1612_01178_amd import autotune
+        import graphgen
+        res = {}
+        for name in args.workloads.split(","):
+            u_np, v_np, n = graphgen.workload(name)
+            u = torch.from_numpy(u_np).to(dev)
+            v = torch.from_numpy(v_np).to(dev)
+            del u_np, v_np
+            best, table = autotune.tune(u, v, n, reps=3, cache=False, log=log)
+            res[name] = {"best": best.__dict__, "table": [[round(t, 4), o] for t, o in table]}
+            del u, v
+            torch.cuda.empty_cache()
+        print(json.dumps({"mode": "tune", "results": res}), flush=True)
+        return
     if args.mode == "serving":
         print(json.dumps({"mode": "serving",
                           "results": serving(cc, torch, dev, args.requests,

@@ -39,14 +39,18 @@ __global__ __launch_bounds__(256) void k_probe(const int32_t* __restrict__ eu,
 #pragma unroll
     for (int j = 0; j < EPT; ++j) {
         const uint32_t x = (uint32_t)a[j], y = (uint32_t)b[j];
+        uint32_t val;
         if (MODE == 0) {
-            acc ^= x + 3 * y;
+            val = x + 3 * y;
         } else if (MODE == 1) {
-            if (x < (uint32_t)n && y < (uint32_t)n) acc ^= (uint32_t)table[x] + 3u * (uint32_t)table[y];
+            val = (x < (uint32_t)n && y < (uint32_t)n)
+                      ? (uint32_t)table[x] + 3u * (uint32_t)table[y] : 0u;
         } else {
-            if (x < (uint32_t)n && y < (uint32_t)n)
-                acc ^= (bits[x >> 5] >> (x & 31)) & (bits[y >> 5] >> (y & 31)) & 1u;
+            val = (x < (uint32_t)n && y < (uint32_t)n)
+                      ? ((bits[x >> 5] >> (x & 31)) & 1u) | (((bits[y >> 5] >> (y & 31)) & 1u) << 1)
+                      : 0u;
         }
+        acc = ((acc << 5) | (acc >> 27)) ^ val;  // rotate-xor: every value matters
     }
     if (acc == 0x9e3779b9u) sink[0] = acc;  // practically never taken
 }

@@ -47,7 +47,7 @@ def main():
     ap.add_argument("--steps", type=int, default=20)
     ap.add_argument("--warmup", type=int, default=3)
     ap.add_argument("--workload", default="rmat24", choices=["rmat24", "er16", "grid4k"])
-    ap.add_argument("--hook", default="atomic", choices=["atomic", "plain"])
+    ap.add_argument("--hook", default="auto", choices=["auto", "atomic", "plain"])
     ap.add_argument("--filter", default="auto", choices=["auto", "off", "giant"])
     ap.add_argument("--segments", type=int, default=0)
     ap.add_argument("--ept", type=int, default=0)
@@ -142,7 +142,7 @@ def main():
     k = max(args.profile_steps, 1)
     st = st or {"segments": None, "filter_used": None}
     hook_ms, comp_ms, other_ms = hook_ms / k, comp_ms / k, other_ms / k
-    if args.hook == "atomic":
+    if st.get("hook") == 1:
         alg_bytes = 8.0 * m  # each int32 (u, v) entry read once across the Atomic-Hook launches
         kernel = "k_ahook (all Atomic-Hook launches of one solve)"
     else:
@@ -167,7 +167,8 @@ def main():
         "dtype": "int32",
         "data": "synthetic (seeded generator, no dataset)",
         "config": {"workload": args.workload, "n": n, "m_entries": m,
-                   "hook": args.hook, "filter": args.filter,
+                   "hook": {1: "atomic", 2: "plain"}.get(st.get("hook"), args.hook),
+                   "filter": args.filter,
                    "segments": st["segments"] if st else None,
                    "filter_used": st["filter_used"] if st else None,
                    "parallelism": "single GPU"},
@@ -218,6 +219,7 @@ ABLATION = [
     ("adaptive_fig4", dict(hook="atomic", filter="off")),
     ("adaptive_giant_filter", dict(hook="atomic", filter="giant")),
     ("plain_device_convergence", dict(hook="plain")),
+    ("library_auto", dict()),
 ]
 SEGMENT_SWEEP = [1, 2, 4, 8, 16, 32, 64, 128]
 

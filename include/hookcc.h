@@ -58,8 +58,11 @@ extern "C" {
 #define CC_ERR_NOCONVERGE (-5) /* the atomic-free Hook hit opts->max_rounds       */
 
 /* ---------------------------------------------------------------- options */
-#define CC_HOOK_ATOMIC 0 /* Atomic-Hook (Fig. 3, CAS on roots) + segmentation (Fig. 4) */
-#define CC_HOOK_PLAIN 1  /* atomic-free Hook (Fig. 2) rounds until no change (Fig. 1),
+#define CC_HOOK_AUTO 0   /* library choice (the default): Atomic-Hook with the giant
+                            filter for large dense lists (m >= 2^22 entries and
+                            m / n >= 8), the atomic-free Hook otherwise                 */
+#define CC_HOOK_ATOMIC 1 /* Atomic-Hook (Fig. 3, CAS on roots) + segmentation (Fig. 4) */
+#define CC_HOOK_PLAIN 2  /* atomic-free Hook (Fig. 2) rounds until no change (Fig. 1),
                             convergence test and active-edge frontier on the device   */
 
 #define CC_FILTER_OFF 0  /* Atomic-Hook only: hook every edge entry                   */
@@ -71,9 +74,11 @@ extern "C" {
 #define CC_FILTER_AUTO 2 /* library chooses (the default)                             */
 
 typedef struct cc_options {
-    int32_t hook;             /* CC_HOOK_ATOMIC (default) or CC_HOOK_PLAIN               */
+    int32_t hook;             /* CC_HOOK_AUTO (default), CC_HOOK_ATOMIC or CC_HOOK_PLAIN  */
     int32_t segments;         /* Atomic-Hook: number of edge segments s; 0 = default
-                                 max(1, round(m / n)); clamped to [1, ceil(m / 4)]     */
+                                 max(1, round(m / n)) (8x that when CC_HOOK_AUTO picks the
+                                 filtered Atomic-Hook, so the first segment is ~n/8
+                                 entries); clamped to [1, ceil(m / 4)]                  */
     int32_t filter;           /* CC_FILTER_* (Atomic-Hook only); default CC_FILTER_AUTO  */
     int32_t filter_after;     /* segments hooked before the giant-component sample
                                  (0 = default 1)                                        */
@@ -88,7 +93,7 @@ typedef struct cc_options {
     int32_t profile;          /* 1 = time every kernel with HIP events on the call's stream
                                  and report the phase times in cc_stats (adds a few
                                  microseconds per launch); 0 = off                      */
-    int32_t host_loop;        /* atomic-free Hook only, for ablations of the paper's
+    int32_t host_loop;        /* hook = CC_HOOK_PLAIN only, for ablations of the paper's
                                  baseline (Fig. 1 as written, convergence read by the host
                                  after every launch): CC_HOST_LOOP_OFF (default: device-side
                                  convergence and compaction), CC_HOST_LOOP_JUMP (Compress as
@@ -111,7 +116,7 @@ void cc_options_init(cc_options* opts);
 
 /* Per-call statistics (optional output of cc_labels_ex). */
 typedef struct cc_stats {
-    int32_t hook;          /* variant that ran                                         */
+    int32_t hook;          /* variant that ran (CC_HOOK_ATOMIC or CC_HOOK_PLAIN)       */
     int32_t segments;      /* Atomic-Hook: segments used                               */
     int32_t filter_used;   /* 1 if the giant-component filter was active              */
     int32_t rounds;        /* atomic-free Hook: Hook rounds run until no change        */

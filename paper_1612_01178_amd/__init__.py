@@ -30,7 +30,7 @@ CC_ERR_HIP = -4
 CC_ERR_NOCONVERGE = -5
 CC_BATCH_LDS_MAX_N = 65536
 
-_HOOKS = {"atomic": 0, "plain": 1}
+_HOOKS = {"auto": 0, "atomic": 1, "plain": 2}
 _FILTERS = {"off": 0, "giant": 1, "auto": 2}
 _HOST_LOOPS = {"off": 0, "jump": 1, "multijump": 2}
 
@@ -91,7 +91,7 @@ class _CRequestInfo(ctypes.Structure):
 @dataclasses.dataclass
 class Options:
     """Solver options (0 / "auto" = library default).  See cc_options in hookcc.h."""
-    hook: str = "atomic"
+    hook: str = "auto"
     segments: int = 0
     filter: str = "auto"
     filter_after: int = 0

@@ -99,11 +99,11 @@ def tune(u, v, n: int, *, reps: int = 3, cache: bool = True, path: str | None = 
     best_t, best = run(base), base
     # 1. hook variant, segment count, filter
     cands = [Options(hook="plain")]
-    for mult in (0.25, 0.5, 1, 2, 4, 8):
+    for mult in (0.25, 0.5, 1, 2, 4, 8, 16):
         s = max(1, int(round(s0 * mult)))
-        cands.append(Options(segments=s, filter="off"))
+        cands.append(Options(hook="atomic", segments=s, filter="off"))
         if s >= 4:
-            cands.append(Options(segments=s, filter="giant"))
+            cands.append(Options(hook="atomic", segments=s, filter="giant"))
     for c in cands:
         t = run(c)
         if t < best_t:

@@ -46,7 +46,7 @@ size_t align256(size_t x) { return (x + 255) & ~size_t(255); }
 
 // ---------------------------------------------------------------------- plans
 struct Plan {
-    int hook = CC_HOOK_ATOMIC;
+    int hook = CC_HOOK_ATOMIC;  // resolved variant: CC_HOOK_ATOMIC or CC_HOOK_PLAIN
     int segments = 1;
     int filter = CC_FILTER_OFF;
     int filter_after = 1;
@@ -59,7 +59,7 @@ struct Plan {
     bool coherent = false;
 };
 
-int32_t make_plan(int32_t n, int64_t m, const cc_options* o, Plan& p) {
+int32_t make_plan(int32_t n, int64_t m, const cc_options* o, Plan& p, bool allow_plain = true) {
     cc_options d;
     std::memset(&d, 0, sizeof d);
     d.filter = CC_FILTER_AUTO;
@@ -69,14 +69,32 @@ int32_t make_plan(int32_t n, int64_t m, const cc_options* o, Plan& p) {
     if (op.coherent_loads != 0 && op.coherent_loads != 1)
         return fail(CC_ERR_ARG, "cc_options.coherent_loads must be 0 or 1");
     p.coherent = op.coherent_loads == 1;
-    if (op.hook != CC_HOOK_ATOMIC && op.hook != CC_HOOK_PLAIN)
+    if (op.hook != CC_HOOK_AUTO && op.hook != CC_HOOK_ATOMIC && op.hook != CC_HOOK_PLAIN)
         return fail(CC_ERR_ARG, "unknown cc_options.hook");
-    p.hook = op.hook;
     if (op.segments < 0) return fail(CC_ERR_ARG, "cc_options.segments < 0");
     // Average-degree heuristic (Section 3.B, Fig. 4): s = 2|E|/|V| with |E|
     // counted once per undirected edge, i.e. s = (entries passed) / n.
+    const int64_t s_paper = n > 0 ? std::max<int64_t>(1, (m + n / 2) / n) : 1;
+    // Automatic variant (measured on gfx950): on large lists of average degree
+    // >= 8 the giant filter turns most entries into two L2 bitmap tests and
+    // Atomic-Hook wins; on sparse or small lists (few rounds, long chains that
+    // a Compress per round flattens) the atomic-free rounds win.
+    const bool dense_large = m >= (int64_t(1) << 22) && n > 0 && m >= 8 * (int64_t)n;
+    bool auto_filtered = false;
+    if (op.hook == CC_HOOK_AUTO) {
+        if (dense_large && allow_plain) {
+            p.hook = CC_HOOK_ATOMIC;
+            auto_filtered = op.filter != CC_FILTER_OFF;
+        } else {
+            p.hook = allow_plain ? CC_HOOK_PLAIN : CC_HOOK_ATOMIC;
+        }
+    } else {
+        p.hook = op.hook;
+    }
+    if (!allow_plain && p.hook == CC_HOOK_PLAIN)
+        return fail(CC_ERR_ARG, "the atomic-free Hook is not available here");
     int64_t s = op.segments;
-    if (s == 0) s = n > 0 ? (m + n / 2) / n : 1;
+    if (s == 0) s = auto_filtered ? 8 * s_paper : s_paper;
     const int64_t smax = std::max<int64_t>(1, (m + 3) / 4);
     s = std::max<int64_t>(1, std::min<int64_t>(s, smax));
     s = std::min<int64_t>(s, 1 << 20);
@@ -113,8 +131,8 @@ int32_t make_plan(int32_t n, int64_t m, const cc_options* o, Plan& p) {
     p.profile = op.profile == 1;
     if (op.host_loop < CC_HOST_LOOP_OFF || op.host_loop > CC_HOST_LOOP_MULTIJUMP)
         return fail(CC_ERR_ARG, "unknown cc_options.host_loop");
-    if (op.host_loop != CC_HOST_LOOP_OFF && p.hook != CC_HOOK_PLAIN)
-        return fail(CC_ERR_ARG, "cc_options.host_loop needs the atomic-free Hook");
+    if (op.host_loop != CC_HOST_LOOP_OFF && op.hook != CC_HOOK_PLAIN)
+        return fail(CC_ERR_ARG, "cc_options.host_loop needs hook = CC_HOOK_PLAIN");
     p.host_loop = op.host_loop;
     if (p.hook == CC_HOOK_PLAIN && m >= (int64_t(1) << 32))
         return fail(CC_ERR_ARG, "atomic-free Hook supports m < 2^32 entries");
@@ -548,7 +566,7 @@ int32_t list_impl(int32_t count, const cc_graph* graphs, hipStream_t s, cc_stats
     off += order_bytes;
     for (int32_t i = 0; i < nl; ++i) {
         const cc_graph& G = graphs[large[i]];
-        int32_t rc = make_plan(G.n, G.m, nullptr, plans[i]);
+        int32_t rc = make_plan(G.n, G.m, nullptr, plans[i], /*allow_plain=*/false);
         if (rc != CC_OK) return rc;
         if (plans[i].filter == CC_FILTER_GIANT) {
             bits_off[i] = off;

@@ -31,17 +31,19 @@ GOLDEN = os.path.join(os.path.dirname(os.path.abspath(__file__)), "golden", "ora
 VARIANTS = {
     "default": cc.Options(),
     "plain": cc.Options(hook="plain"),
-    "s1": cc.Options(segments=1, filter="off"),
-    "s7_b64_e4": cc.Options(segments=7, filter="off", edges_per_thread=4, block=64),
-    "s5_giant_b1024_e16": cc.Options(segments=5, filter="giant", filter_after=1,
+    "atomic": cc.Options(hook="atomic"),
+    "s1": cc.Options(hook="atomic", segments=1, filter="off"),
+    "s7_b64_e4": cc.Options(hook="atomic", segments=7, filter="off", edges_per_thread=4, block=64),
+    "s5_giant_b1024_e16": cc.Options(hook="atomic", segments=5, filter="giant", filter_after=1,
                                      edges_per_thread=16, block=1024),
-    "s9_giant_after3": cc.Options(segments=9, filter="giant", filter_after=3,
+    "s9_giant_after3": cc.Options(hook="atomic", segments=9, filter="giant", filter_after=3,
                                   edges_per_thread=8, block=512),
     "plain_b128_e16_k1": cc.Options(hook="plain", edges_per_thread=16, block=128,
                                     rounds_per_check=1),
     "plain_e4_k7": cc.Options(hook="plain", edges_per_thread=4, rounds_per_check=7),
-    "coherent_giant": cc.Options(coherent_loads=True, segments=6, filter="giant"),
-    "coherent_s3": cc.Options(coherent_loads=True, segments=3, filter="off", block=128),
+    "coherent_giant": cc.Options(hook="atomic", coherent_loads=True, segments=6, filter="giant"),
+    "coherent_s3": cc.Options(hook="atomic", coherent_loads=True, segments=3, filter="off",
+                              block=128),
     "hostloop_jump": cc.Options(hook="plain", host_loop="jump"),
     "hostloop_multijump": cc.Options(hook="plain", host_loop="multijump", edges_per_thread=16),
 }
@@ -124,7 +126,7 @@ def test_random_graphs_against_oracle(dev, variant):
         assert np.array_equal(got, want), (variant, trial, n, m, int(np.sum(got != want)))
 
 
-@pytest.mark.parametrize("variant", ["default", "plain", "s5_giant_b1024_e16", "s1"])
+@pytest.mark.parametrize("variant", ["default", "plain", "atomic", "s5_giant_b1024_e16", "s1"])
 def test_adversarial_shapes(dev, variant):
     opt = VARIANTS[variant]
     n = 100003
@@ -187,7 +189,7 @@ def test_metamorphic_invariance(dev):
                              np.concatenate([v, np.arange(n, dtype=np.int32)])),
     }
     for name, (uu, vv) in variants.items():
-        for opt in ("default", "plain", "s9_giant_after3"):
+        for opt in ("default", "plain", "atomic", "s9_giant_after3"):
             say("metamorphic", name, opt)
             assert np.array_equal(solve(uu, vv, n, dev, VARIANTS[opt]), want), (name, opt)
 
@@ -197,7 +199,7 @@ def test_repeated_solves_are_identical(dev):
     u, v, n, _ = graphgen.er_planted(seed=1001)
     want = oracle.labels(u, v, n)
     du, dv = to_dev(u, dev), to_dev(v, dev)
-    for opt in ("default", "plain", "s5_giant_b1024_e16"):
+    for opt in ("default", "plain", "atomic", "s5_giant_b1024_e16"):
         for rep in range(15):
             got = cc.labels(du, dv, n, options=VARIANTS[opt]).cpu().numpy()
             assert np.array_equal(got, want), (opt, rep)
@@ -205,7 +207,7 @@ def test_repeated_solves_are_identical(dev):
 
 # ----------------------------------------------------------------------------- errors
 def test_range_errors_are_reported(dev):
-    for opt in ("default", "plain", "s5_giant_b1024_e16"):
+    for opt in ("default", "plain", "atomic", "s5_giant_b1024_e16"):
         for bad in (10, -1, 1 << 30):
             u = np.array([0, 1, 2, bad, 3], np.int32)
             v = np.array([1, 2, 3, 4, 0], np.int32)
@@ -238,7 +240,7 @@ def test_round_cap_and_workspace_errors(dev):
 def test_stats_are_reported(dev):
     u, v, n = graphgen.rmat(16, 16, seed=31, symmetrize=True)
     du, dv = to_dev(u, dev), to_dev(v, dev)
-    lab, st = cc.labels(du, dv, n, options=cc.Options(filter="giant", profile=True),
+    lab, st = cc.labels(du, dv, n, options=cc.Options(hook="atomic", filter="giant", profile=True),
                         return_stats=True)
     assert st["segments"] == 32 and st["filter_used"] == 1 and st["host_syncs"] == 1
     assert st["hook_ms"] > 0 and st["compress_ms"] > 0
@@ -317,7 +319,7 @@ def test_full_size_workloads_match_oracle_digest(dev, name):
     assert (n, len(u)) == (rec["n"], rec["m"])
     du, dv = to_dev(u, dev), to_dev(v, dev)
     del u, v
-    for opt in ("default", "plain", "s1", "coherent_giant"):
+    for opt in ("default", "plain", "atomic", "s1", "coherent_giant"):
         if name == "rmat24" and opt == "s1":
             opt = "s9_giant_after3"
         say("full size", name, opt)

@@ -359,7 +359,8 @@ def probe_ceilings(cc, torch, u, v, n, m, reps=5):
     bits = torch.zeros((n + 31) // 32, dtype=torch.int32, device=u.device)
     out = {}
     for mode, name, tab in ((0, "stream", None), (1, "stream+gather", table),
-                            (2, "stream+bitmap", bits)):
+                            (2, "stream+bitmap", bits), (3, "stream+bitmap_nt", bits),
+                            (4, "stream+bitmap_agent", bits)):
         cc.probe(mode, u, v, tab, n)
         torch.cuda.synchronize()
         s0, s1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)

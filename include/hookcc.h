@@ -104,8 +104,15 @@ typedef struct cc_options {
                                  L2); 0 (default) = cached loads, which may return an
                                  older ancestor -- always a valid one (kept for
                                  measurement; results are identical)                   */
-    int32_t reserved[5];      /* must be zero                                           */
+    int32_t hot_cache;        /* giant filter only: CC_HOT_AUTO (default, on), CC_HOT_ON or
+                                 CC_HOT_OFF -- keep the bitmap words that sampled endpoints
+                                 hit most often in LDS and answer those bit tests there  */
+    int32_t reserved[4];      /* must be zero                                           */
 } cc_options;
+
+#define CC_HOT_AUTO 0
+#define CC_HOT_ON 1
+#define CC_HOT_OFF 2
 
 #define CC_HOST_LOOP_OFF 0
 #define CC_HOST_LOOP_JUMP 1
@@ -278,10 +285,11 @@ double cc_server_clock(void);
 /* Memory-ceiling probe (measurement only, no labels).  Streams the m entries
  * of edges_u/edges_v ([device], 16-byte aligned) with the tiling of the hook
  * kernels and, for mode 1, also gathers table[u] and table[v] from the
- * [device] int32[n] array `table`, or, for mode 2, tests bits u and v of the
- * [device] n-bit bitmap `table` (uint32 words).  Entries with an endpoint
- * outside [0, n) are skipped by modes 1 and 2.  Asynchronous on `stream`.
- * Returns CC_OK, CC_ERR_ARG or CC_ERR_HIP. */
+ * [device] int32[n] array `table`, or, for modes 2-4, tests bits u and v of
+ * the [device] n-bit bitmap `table` (uint32 words) with cached loads (2),
+ * non-temporal loads (3) or agent-scope atomic loads (4).  Entries with an
+ * endpoint outside [0, n) are skipped by modes 1-4.  Asynchronous on
+ * `stream`.  Returns CC_OK, CC_ERR_ARG or CC_ERR_HIP. */
 int32_t cc_probe(int32_t mode, const int32_t* edges_u, const int32_t* edges_v, int64_t m,
                  const void* table, int32_t n, void* stream);
 

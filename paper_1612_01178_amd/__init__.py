@@ -56,7 +56,8 @@ class _COptions(ctypes.Structure):
                 ("block", ctypes.c_int32), ("edges_per_thread", ctypes.c_int32),
                 ("max_rounds", ctypes.c_int32), ("rounds_per_check", ctypes.c_int32),
                 ("profile", ctypes.c_int32), ("host_loop", ctypes.c_int32),
-                ("coherent_loads", ctypes.c_int32), ("reserved", ctypes.c_int32 * 5)]
+                ("coherent_loads", ctypes.c_int32), ("hot_cache", ctypes.c_int32),
+                ("reserved", ctypes.c_int32 * 4)]
 
 
 class _CStats(ctypes.Structure):
@@ -102,6 +103,7 @@ class Options:
     profile: bool = False
     host_loop: str = "off"
     coherent_loads: bool = False
+    hot_cache: str = "auto"
 
     def _c(self) -> _COptions:
         o = _COptions()
@@ -116,6 +118,7 @@ class Options:
         o.profile = 1 if self.profile else 0
         o.host_loop = _HOST_LOOPS[self.host_loop]
         o.coherent_loads = 1 if self.coherent_loads else 0
+        o.hot_cache = {"auto": 0, "on": 1, "off": 2}[self.hot_cache]
         return o
 
 

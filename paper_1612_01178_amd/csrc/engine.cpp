@@ -57,6 +57,7 @@ struct Plan {
     bool profile = false;
     int host_loop = CC_HOST_LOOP_OFF;
     bool coherent = false;
+    bool hot = false;  // hot-word LDS cache of the giant bitmap
 };
 
 int32_t make_plan(int32_t n, int64_t m, const cc_options* o, Plan& p, bool allow_plain = true) {
@@ -64,8 +65,10 @@ int32_t make_plan(int32_t n, int64_t m, const cc_options* o, Plan& p, bool allow
     std::memset(&d, 0, sizeof d);
     d.filter = CC_FILTER_AUTO;
     const cc_options& op = o ? *o : d;
-    for (int i = 0; i < 5; ++i)
+    for (int i = 0; i < 4; ++i)
         if (op.reserved[i] != 0) return fail(CC_ERR_ARG, "cc_options.reserved must be zero");
+    if (op.hot_cache < CC_HOT_AUTO || op.hot_cache > CC_HOT_OFF)
+        return fail(CC_ERR_ARG, "unknown cc_options.hot_cache");
     if (op.coherent_loads != 0 && op.coherent_loads != 1)
         return fail(CC_ERR_ARG, "cc_options.coherent_loads must be 0 or 1");
     p.coherent = op.coherent_loads == 1;
@@ -113,6 +116,7 @@ int32_t make_plan(int32_t n, int64_t m, const cc_options* o, Plan& p, bool allow
         p.filter = op.filter;
     }
     if (p.filter == CC_FILTER_GIANT && p.filter_after >= p.segments) p.filter = CC_FILTER_OFF;
+    p.hot = p.filter == CC_FILTER_GIANT && op.hot_cache != CC_HOT_OFF && !p.coherent;
     if (op.block != 0) {
         if (op.block < 64 || op.block > 1024 || op.block % 64)
             return fail(CC_ERR_ARG, "cc_options.block must be a multiple of 64 in [64, 1024]");
@@ -142,6 +146,7 @@ int32_t make_plan(int32_t n, int64_t m, const cc_options* o, Plan& p, bool allow
 // Workspace: [Ctrl 256 B][giant bitmap][frontier 0][frontier 1]
 struct Layout {
     size_t bits = 0, f0 = 0, f1 = 0, total = 0;
+    size_t hot_counts = 0, hot_tags = 0, hot_vals = 0;
     int64_t cap = 0;
 };
 
@@ -151,6 +156,14 @@ Layout layout(int32_t n, int64_t m, const Plan& p) {
     if (p.hook == CC_HOOK_ATOMIC && p.filter == CC_FILTER_GIANT) {
         L.bits = off;
         off += align256(((size_t)n + 31) / 32 * 4);
+        if (p.hot) {
+            L.hot_counts = off;
+            off += align256(((size_t)n + 31) / 32 * 4);
+            L.hot_tags = off;
+            off += align256((size_t)kHotSlots * 4);
+            L.hot_vals = off;
+            off += align256((size_t)kHotSlots * 4);
+        }
     }
     if (p.hook == CC_HOOK_PLAIN && p.host_loop == CC_HOST_LOOP_OFF) {
         L.cap = m;
@@ -286,9 +299,30 @@ int32_t finish(hipStream_t s, Ctrl* dctrl, Ctrl* hctrl, cc_stats* st) {
 
 // Enqueues the Atomic-Hook solve (Fig. 4) of one graph on s; no synchronisation.
 // `ctrl` is the graph's control block, `bits` its giant bitmap (filter plans).
+// Giant-filter buffers of one solve (null when the plan does not use them).
+struct FilterBufs {
+    uint32_t* bits = nullptr;
+    uint32_t* hot_counts = nullptr;
+    uint32_t* hot_tags = nullptr;
+    uint32_t* hot_vals = nullptr;
+};
+
+FilterBufs filter_bufs(char* base, const Layout& L) {
+    FilterBufs f;
+    if (L.bits) f.bits = reinterpret_cast<uint32_t*>(base + L.bits);
+    if (L.hot_counts) {
+        f.hot_counts = reinterpret_cast<uint32_t*>(base + L.hot_counts);
+        f.hot_tags = reinterpret_cast<uint32_t*>(base + L.hot_tags);
+        f.hot_vals = reinterpret_cast<uint32_t*>(base + L.hot_vals);
+    }
+    return f;
+}
+
 int32_t enqueue_atomic(int32_t n, const int32_t* u, const int32_t* v, int64_t m, int32_t* pi,
-                       const Plan& p, Ctrl* ctrl, uint32_t* bits, hipStream_t s, Timer& tm,
+                       const Plan& p, Ctrl* ctrl, const FilterBufs& fb, hipStream_t s, Timer& tm,
                        cc_stats* st) {
+    uint32_t* bits = fb.bits;
+    const bool hot = p.hot && fb.hot_tags != nullptr;
     const int S = p.segments;
     auto bound = [&](int64_t i) -> int64_t {
         if (i >= S) return m;
@@ -316,17 +350,28 @@ int32_t enqueue_atomic(int32_t n, const int32_t* u, const int32_t* v, int64_t m,
         }
         TIMED(kPhaseOther, launch_sample_giant(u, m, pi, n, ctrl, 2048, s));
         TIMED(kPhaseOther, launch_bitmap(pi, n, ctrl, bits, s));
+        if (hot) {
+            TIMED(kPhaseOther, launch_hot_prepare(u, v, m, n, fb.hot_counts, fb.hot_tags, s));
+            TIMED(kPhaseOther, launch_hot_values(bits, fb.hot_tags, fb.hot_vals, ctrl, s));
+        }
         // The rest of the list in super-segments that double in size, each
         // followed by a Compress and a bitmap refresh.
         int64_t g = fa, step = fa;
         while (g < S) {
             const int64_t h = std::min<int64_t>(S, g + step);
-            TIMED(kPhaseHook, launch_ahook(u, v, bound(g), bound(h), pi, n, ctrl, bits, p.block,
-                                           p.ept, p.coherent, s));
+            if (hot)
+                TIMED(kPhaseHook, launch_ahook_hot(u, v, bound(g), bound(h), pi, n, ctrl, bits,
+                                                   fb.hot_tags, fb.hot_vals, p.ept, s));
+            else
+                TIMED(kPhaseHook, launch_ahook(u, v, bound(g), bound(h), pi, n, ctrl, bits,
+                                               p.block, p.ept, p.coherent, s));
             TIMED(kPhaseCompress, launch_mj(pi, n, nullptr, p.coherent, s));
             ++hooks;
             ++jumps;
-            if (h < S) TIMED(kPhaseOther, launch_bitmap(pi, n, ctrl, bits, s));
+            if (h < S) {
+                TIMED(kPhaseOther, launch_bitmap(pi, n, ctrl, bits, s));
+                if (hot) TIMED(kPhaseOther, launch_hot_values(bits, fb.hot_tags, fb.hot_vals, ctrl, s));
+            }
             g = h;
             step *= 2;
         }
@@ -484,8 +529,8 @@ int32_t labels_impl(int32_t n, const int32_t* u, const int32_t* v, int64_t m, in
     tm.s = s;
     int64_t rounds = 0;
     if (p.hook == CC_HOOK_ATOMIC) {
-        rc = enqueue_atomic(n, u, v, m, out, p, reinterpret_cast<Ctrl*>(ws),
-                            L.bits ? reinterpret_cast<uint32_t*>(ws + L.bits) : nullptr, s, tm, st);
+        rc = enqueue_atomic(n, u, v, m, out, p, reinterpret_cast<Ctrl*>(ws), filter_bufs(ws, L), s,
+                            tm, st);
         if (rc == CC_OK) rc = finish(s, reinterpret_cast<Ctrl*>(ws), pe->host_ctrl, st);
     } else if (p.host_loop != CC_HOST_LOOP_OFF) {
         rc = solve_host_loop(n, u, v, m, out, p, ws, s, pe->host_ctrl, tm, st);
@@ -556,7 +601,8 @@ int32_t list_impl(int32_t count, const cc_graph* graphs, hipStream_t s, cc_stats
     const int32_t ns = (int32_t)small.size();
     const int32_t nl = (int32_t)large.size();
     std::vector<Plan> plans(nl);
-    std::vector<size_t> bits_off(nl, 0);
+    std::vector<size_t> region_off(nl, 0);
+    std::vector<Layout> layouts(nl);
     size_t off = align256((size_t)(1 + nl) * sizeof(Ctrl));
     const size_t desc_off = off;
     const size_t desc_bytes = align256((size_t)ns * sizeof(GraphDesc));
@@ -568,10 +614,9 @@ int32_t list_impl(int32_t count, const cc_graph* graphs, hipStream_t s, cc_stats
         const cc_graph& G = graphs[large[i]];
         int32_t rc = make_plan(G.n, G.m, nullptr, plans[i], /*allow_plain=*/false);
         if (rc != CC_OK) return rc;
-        if (plans[i].filter == CC_FILTER_GIANT) {
-            bits_off[i] = off;
-            off += align256(((size_t)G.n + 31) / 32 * 4);
-        }
+        layouts[i] = layout(G.n, G.m, plans[i]);  // its control block is ctrls[1 + i] instead
+        region_off[i] = off;
+        off += align256(layouts[i].total);
     }
     PoolEntry* pe = pool_entry(s);
     std::lock_guard<std::mutex> lk(pe->mu);
@@ -611,8 +656,7 @@ int32_t list_impl(int32_t count, const cc_graph* graphs, hipStream_t s, cc_stats
     for (int32_t i = 0; i < nl; ++i) {
         const cc_graph& G = graphs[large[i]];
         rc = enqueue_atomic(G.n, G.edges_u, G.edges_v, G.m, G.out_label, plans[i], &ctrls[1 + i],
-                            bits_off[i] ? reinterpret_cast<uint32_t*>(ws + bits_off[i]) : nullptr,
-                            s, tm, st);
+                            filter_bufs(ws + region_off[i], layouts[i]), s, tm, st);
         if (rc != CC_OK) return rc;
     }
     HIPCHK(hipMemcpyAsync(pe->host_ctrl, ctrls, sizeof(Ctrl) * (1 + nl), hipMemcpyDeviceToHost, s));
@@ -660,7 +704,7 @@ int32_t batch_impl(int32_t B, const int64_t* vo, const int64_t* eo, const int32_
 // ---------------------------------------------------------------------- probes, release
 int32_t probe_impl(int32_t mode, const int32_t* u, const int32_t* v, int64_t m, const void* table,
                    int32_t n, hipStream_t s) {
-    if (m < 0 || mode < 0 || mode > 2) return fail(CC_ERR_ARG, "bad probe arguments");
+    if (m < 0 || mode < 0 || mode > 4) return fail(CC_ERR_ARG, "bad probe arguments");
     if (m > 0 && (!u || !v)) return fail(CC_ERR_ARG, "null edge array");
     if (mode > 0 && (!table || n <= 0)) return fail(CC_ERR_ARG, "probe table required");
     if (((uintptr_t)u & 15) || ((uintptr_t)v & 15))
@@ -675,7 +719,8 @@ int32_t probe_impl(int32_t mode, const int32_t* u, const int32_t* v, int64_t m, 
     else if (mode == 1)
         HIPCHK(launch_probe_gather(u, v, m, static_cast<const int32_t*>(table), n, sink, s));
     else
-        HIPCHK(launch_probe_bitgather(u, v, m, static_cast<const uint32_t*>(table), n, sink, s));
+        HIPCHK(launch_probe_bitgather(u, v, m, static_cast<const uint32_t*>(table), n, mode - 2,
+                                      sink, s));
     return CC_OK;
 }
 

@@ -51,13 +51,31 @@ hipError_t launch_hook_flag(const int32_t* u, const int32_t* v, int64_t m, int32
                             Ctrl* ctrl, int block, int ept, hipStream_t s);
 hipError_t launch_jump(int32_t* pi, int32_t n, Ctrl* ctrl, hipStream_t s);
 
+// Hot-word LDS cache of the giant bitmap (kernels_hot.hip).  kHotSlots
+// direct-mapped slots; tags[t] = k means slot t caches bitmap word
+// k * kHotSlots + t.
+constexpr int kHotSlots = 16384;
+// Counts sampled endpoints per bitmap word (counts: ceil(n/32) words of
+// scratch) and picks the hottest word for every slot (tags: kHotSlots words).
+hipError_t launch_hot_prepare(const int32_t* u, const int32_t* v, int64_t m, int32_t n,
+                              uint32_t* counts, uint32_t* tags, hipStream_t s);
+// vals[t] = bits[tags[t] * kHotSlots + t]; no-op unless ctrl->filter_on.
+hipError_t launch_hot_values(const uint32_t* bits, const uint32_t* tags, uint32_t* vals,
+                             const Ctrl* ctrl, hipStream_t s);
+// Filtered Atomic-Hook of entries [begin, end) answering bit tests from the
+// LDS copy of (tags, vals) when possible (persistent, one workgroup per CU).
+hipError_t launch_ahook_hot(const int32_t* u, const int32_t* v, int64_t begin, int64_t end,
+                            int32_t* pi, int32_t n, Ctrl* ctrl, const uint32_t* bits,
+                            const uint32_t* tags, const uint32_t* vals, int ept, hipStream_t s);
+
 // Streaming and gather probes used to measure the memory ceilings.
 hipError_t launch_probe_stream(const int32_t* u, const int32_t* v, int64_t m, uint32_t* sink,
                                hipStream_t s);
 hipError_t launch_probe_gather(const int32_t* u, const int32_t* v, int64_t m, const int32_t* table,
                                int32_t n, uint32_t* sink, hipStream_t s);
 hipError_t launch_probe_bitgather(const int32_t* u, const int32_t* v, int64_t m,
-                                  const uint32_t* bits, int32_t n, uint32_t* sink, hipStream_t s);
+                                  const uint32_t* bits, int32_t n, int variant, uint32_t* sink,
+                                  hipStream_t s);
 
 // Batched solve: one workgroup per graph, tree array in LDS, graphs taken
 // from a device work queue in the order of `order`.

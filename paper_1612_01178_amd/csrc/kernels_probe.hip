@@ -45,9 +45,19 @@ __global__ __launch_bounds__(256) void k_probe(const int32_t* __restrict__ eu,
         } else if (MODE == 1) {
             val = (x < (uint32_t)n && y < (uint32_t)n)
                       ? (uint32_t)table[x] + 3u * (uint32_t)table[y] : 0u;
-        } else {
+        } else if (MODE == 2) {
             val = (x < (uint32_t)n && y < (uint32_t)n)
                       ? ((bits[x >> 5] >> (x & 31)) & 1u) | (((bits[y >> 5] >> (y & 31)) & 1u) << 1)
+                      : 0u;
+        } else if (MODE == 3) {  // bitmap words read with the non-temporal hint
+            val = (x < (uint32_t)n && y < (uint32_t)n)
+                      ? ((__builtin_nontemporal_load(bits + (x >> 5)) >> (x & 31)) & 1u) |
+                            (((__builtin_nontemporal_load(bits + (y >> 5)) >> (y & 31)) & 1u) << 1)
+                      : 0u;
+        } else {  // bitmap words read as agent-scope atomics (past the L1)
+            val = (x < (uint32_t)n && y < (uint32_t)n)
+                      ? ((__hip_atomic_load(bits + (x >> 5), __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) >> (x & 31)) & 1u) |
+                            (((__hip_atomic_load(bits + (y >> 5), __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) >> (y & 31)) & 1u) << 1)
                       : 0u;
         }
         acc = ((acc << 5) | (acc >> 27)) ^ val;  // rotate-xor: every value matters
@@ -62,9 +72,13 @@ static hipError_t probe(int mode, const int32_t* u, const int32_t* v, int64_t m,
     if (((uintptr_t)u & 15) || ((uintptr_t)v & 15)) return hipErrorInvalidValue;
     const int64_t tile = 256 * 16;
     const int grid = (int)((m + tile - 1) / tile);
-    if (mode == 0) k_probe<0><<<grid, 256, 0, s>>>(u, v, m, table, bits, n, sink);
-    else if (mode == 1) k_probe<1><<<grid, 256, 0, s>>>(u, v, m, table, bits, n, sink);
-    else k_probe<2><<<grid, 256, 0, s>>>(u, v, m, table, bits, n, sink);
+    switch (mode) {
+        case 0: k_probe<0><<<grid, 256, 0, s>>>(u, v, m, table, bits, n, sink); break;
+        case 1: k_probe<1><<<grid, 256, 0, s>>>(u, v, m, table, bits, n, sink); break;
+        case 2: k_probe<2><<<grid, 256, 0, s>>>(u, v, m, table, bits, n, sink); break;
+        case 3: k_probe<3><<<grid, 256, 0, s>>>(u, v, m, table, bits, n, sink); break;
+        default: k_probe<4><<<grid, 256, 0, s>>>(u, v, m, table, bits, n, sink); break;
+    }
     return hipGetLastError();
 }
 
@@ -77,8 +91,9 @@ hipError_t launch_probe_gather(const int32_t* u, const int32_t* v, int64_t m, co
     return probe(1, u, v, m, table, nullptr, n, sink, s);
 }
 hipError_t launch_probe_bitgather(const int32_t* u, const int32_t* v, int64_t m,
-                                  const uint32_t* bits, int32_t n, uint32_t* sink, hipStream_t s) {
-    return probe(2, u, v, m, nullptr, bits, n, sink, s);
+                                  const uint32_t* bits, int32_t n, int variant, uint32_t* sink,
+                                  hipStream_t s) {
+    return probe(2 + variant, u, v, m, nullptr, bits, n, sink, s);
 }
 
 }  // namespace hookcc

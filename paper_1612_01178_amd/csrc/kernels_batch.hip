@@ -12,6 +12,8 @@
 
 namespace hookcc {
 
+constexpr int kBatchEPT = 8;  // edge entries per thread per step
+
 // 16-bit compare-and-swap in LDS, built on the 32-bit CAS of the containing
 // word: succeeds iff slot `idx` holds `expected`; returns the value found.
 // The other half-word may change concurrently; the loop then retries with
@@ -72,15 +74,25 @@ __global__ __launch_bounds__(1024) void k_batch_lds(const GraphDesc* __restrict_
         const int32_t s = d.segments > 0 ? d.segments : 1;
         for (int32_t seg = 0; seg < s; ++seg) {
             const int64_t b0 = d.m * seg / s, b1 = d.m * (seg + 1) / s;
-            for (int64_t e = b0 + tid; e < b1; e += nthr) {
-                const int32_t a = __builtin_nontemporal_load(d.u + e);
-                const int32_t b = __builtin_nontemporal_load(d.v + e);
-                if ((uint32_t)a >= n || (uint32_t)b >= n) {
-                    bad = true;
-                    continue;
+            // kBatchEPT entries per thread per step, all loads issued before
+            // any hook so that the HBM latency of the edge stream overlaps.
+            for (int64_t e0 = b0 + tid; e0 < b1; e0 += (int64_t)nthr * kBatchEPT) {
+                int32_t a[kBatchEPT], b[kBatchEPT];
+#pragma unroll
+                for (int j = 0; j < kBatchEPT; ++j) {
+                    const int64_t e = e0 + (int64_t)j * nthr;
+                    a[j] = e < b1 ? __builtin_nontemporal_load(d.u + e) : 0;
+                    b[j] = e < b1 ? __builtin_nontemporal_load(d.v + e) : 0;
                 }
-                if (a == b) continue;
-                lds_atomic_hook(spi, lds_ld16(spi, a), lds_ld16(spi, b));
+#pragma unroll
+                for (int j = 0; j < kBatchEPT; ++j) {
+                    if ((uint32_t)a[j] >= n || (uint32_t)b[j] >= n) {
+                        bad = true;
+                        continue;
+                    }
+                    if (a[j] == b[j]) continue;
+                    lds_atomic_hook(spi, lds_ld16(spi, a[j]), lds_ld16(spi, b[j]));
+                }
             }
             __syncthreads();
             // Multi-Jump (Fig. 3, bottom) over the graph's vertices, low ids first.

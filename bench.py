@@ -142,9 +142,13 @@ def main():
     k = max(args.profile_steps, 1)
     st = st or {"segments": None, "filter_used": None}
     hook_ms, comp_ms, other_ms = hook_ms / k, comp_ms / k, other_ms / k
+    traffic = None
     if st.get("hook") == 1:
         alg_bytes = 8.0 * m  # each int32 (u, v) entry read once across the Atomic-Hook launches
-        kernel = "k_ahook (all Atomic-Hook launches of one solve)"
+        kernel = "k_ahook + k_ahook_hot (all Atomic-Hook launches of one solve)"
+        if args.hook == "auto" and args.filter == "auto" and not (args.segments or args.ept or
+                                                                  args.block or args.coherent):
+            traffic = measured_traffic(args.workload, "atomic")
     else:
         alg_bytes = 8.0 * m  # first Hook pass over the input entries
         kernel = "k_hook_plain + k_compact (all edge passes of one solve)"
@@ -175,7 +179,7 @@ def main():
         "parity_vs_oracle_digest": parity,
         "components": comps,
         "roofline": {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS,
-                     "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": None,
+                     "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": traffic,
                      "kernel": kernel, "kernel_ms": round(hook_ms, 4),
                      "alg_bytes_per_solve": alg_bytes},
         "solve_roofline": {"alg_bytes": solve_bytes,
@@ -348,6 +352,26 @@ def serving(cc, torch, dev, requests, loads=(0.5, 0.7, 0.9), host_mode=False, po
             log("serving: load %.2f %s %s" % (frac, name, row[name]))
         out["load_%.2f" % frac] = row
     return out
+
+
+def measured_traffic(workload, kernel_tag):
+    """HBM traffic per solve of the dominant kernel from the committed counter
+    summary (profiles/<workload>_ahook_counters.md), or None when there is
+    none or the kernel sources have changed since the counters were taken."""
+    import re
+    path = os.path.join(ROOT, "profiles", "%s_ahook_counters.md" % workload)
+    if not os.path.exists(path) or kernel_tag != "atomic":
+        return None
+    text = open(path).read()
+    m = re.search(r"```json\n(.*?)\n```", text, flags=re.S)
+    if not m:
+        return None
+    rec = json.loads(m.group(1))
+    h = hashlib.sha256(b"".join(open(os.path.join(ROOT, f), "rb").read()
+                                for f in rec["sources"])).hexdigest()[:16]
+    if h != rec["sources_sha256_16"]:
+        return None
+    return rec["traffic_bytes_per_solve"]
 
 
 def probe_ceilings(cc, torch, u, v, n, m, reps=5):

@@ -118,7 +118,7 @@ class Options:
         o.profile = 1 if self.profile else 0
         o.host_loop = _HOST_LOOPS[self.host_loop]
         o.coherent_loads = 1 if self.coherent_loads else 0
-        o.hot_cache = {"auto": 0, "on": 1, "off": 2}[self.hot_cache]
+        o.hot_cache = {"auto": 0, "on": 1, "off": 2, "large": 3}[self.hot_cache]
         return o
 
 

@@ -58,6 +58,7 @@ struct Plan {
     int host_loop = CC_HOST_LOOP_OFF;
     bool coherent = false;
     bool hot = false;  // hot-word LDS cache of the giant bitmap
+    int hot_slots = 16384;
 };
 
 int32_t make_plan(int32_t n, int64_t m, const cc_options* o, Plan& p, bool allow_plain = true) {
@@ -67,8 +68,9 @@ int32_t make_plan(int32_t n, int64_t m, const cc_options* o, Plan& p, bool allow
     const cc_options& op = o ? *o : d;
     for (int i = 0; i < 4; ++i)
         if (op.reserved[i] != 0) return fail(CC_ERR_ARG, "cc_options.reserved must be zero");
-    if (op.hot_cache < CC_HOT_AUTO || op.hot_cache > CC_HOT_OFF)
+    if (op.hot_cache < CC_HOT_AUTO || op.hot_cache > CC_HOT_LARGE)
         return fail(CC_ERR_ARG, "unknown cc_options.hot_cache");
+    p.hot_slots = op.hot_cache == CC_HOT_LARGE ? 32768 : 16384;
     if (op.coherent_loads != 0 && op.coherent_loads != 1)
         return fail(CC_ERR_ARG, "cc_options.coherent_loads must be 0 or 1");
     p.coherent = op.coherent_loads == 1;
@@ -160,9 +162,9 @@ Layout layout(int32_t n, int64_t m, const Plan& p) {
             L.hot_counts = off;
             off += align256(((size_t)n + 31) / 32 * 4);
             L.hot_tags = off;
-            off += align256((size_t)kHotSlots * 4);
+            off += align256((size_t)kHotSlotsMax * 4);
             L.hot_vals = off;
-            off += align256((size_t)kHotSlots * 4);
+            off += align256((size_t)kHotSlotsMax * 4);
         }
     }
     if (p.hook == CC_HOOK_PLAIN && p.host_loop == CC_HOST_LOOP_OFF) {
@@ -351,8 +353,10 @@ int32_t enqueue_atomic(int32_t n, const int32_t* u, const int32_t* v, int64_t m,
         TIMED(kPhaseOther, launch_sample_giant(u, m, pi, n, ctrl, 2048, s));
         TIMED(kPhaseOther, launch_bitmap(pi, n, ctrl, bits, s));
         if (hot) {
-            TIMED(kPhaseOther, launch_hot_prepare(u, v, m, n, fb.hot_counts, fb.hot_tags, s));
-            TIMED(kPhaseOther, launch_hot_values(bits, fb.hot_tags, fb.hot_vals, ctrl, s));
+            TIMED(kPhaseOther, launch_hot_prepare(u, v, m, n, fb.hot_counts, fb.hot_tags,
+                                                  p.hot_slots, s));
+            TIMED(kPhaseOther, launch_hot_values(bits, fb.hot_tags, fb.hot_vals, ctrl,
+                                                 p.hot_slots, s));
         }
         // The rest of the list in super-segments that double in size, each
         // followed by a Compress and a bitmap refresh.
@@ -361,7 +365,8 @@ int32_t enqueue_atomic(int32_t n, const int32_t* u, const int32_t* v, int64_t m,
             const int64_t h = std::min<int64_t>(S, g + step);
             if (hot)
                 TIMED(kPhaseHook, launch_ahook_hot(u, v, bound(g), bound(h), pi, n, ctrl, bits,
-                                                   fb.hot_tags, fb.hot_vals, p.ept, s));
+                                                   fb.hot_tags, fb.hot_vals, p.ept, p.hot_slots,
+                                                   s));
             else
                 TIMED(kPhaseHook, launch_ahook(u, v, bound(g), bound(h), pi, n, ctrl, bits,
                                                p.block, p.ept, p.coherent, s));
@@ -370,7 +375,9 @@ int32_t enqueue_atomic(int32_t n, const int32_t* u, const int32_t* v, int64_t m,
             ++jumps;
             if (h < S) {
                 TIMED(kPhaseOther, launch_bitmap(pi, n, ctrl, bits, s));
-                if (hot) TIMED(kPhaseOther, launch_hot_values(bits, fb.hot_tags, fb.hot_vals, ctrl, s));
+                if (hot)
+                    TIMED(kPhaseOther, launch_hot_values(bits, fb.hot_tags, fb.hot_vals, ctrl,
+                                                         p.hot_slots, s));
             }
             g = h;
             step *= 2;

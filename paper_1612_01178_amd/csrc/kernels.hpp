@@ -51,22 +51,23 @@ hipError_t launch_hook_flag(const int32_t* u, const int32_t* v, int64_t m, int32
                             Ctrl* ctrl, int block, int ept, hipStream_t s);
 hipError_t launch_jump(int32_t* pi, int32_t n, Ctrl* ctrl, hipStream_t s);
 
-// Hot-word LDS cache of the giant bitmap (kernels_hot.hip).  kHotSlots
-// direct-mapped slots; tags[t] = k means slot t caches bitmap word
-// k * kHotSlots + t.
-constexpr int kHotSlots = 16384;
+// Hot-word LDS cache of the giant bitmap (kernels_hot.hip): `slots`
+// direct-mapped slots (16384 or 32768); tags[t] = k means slot t caches bitmap
+// word k * slots + t.  Global tag/value arrays hold kHotSlotsMax words.
+constexpr int kHotSlotsMax = 32768;
 // Counts sampled endpoints per bitmap word (counts: ceil(n/32) words of
-// scratch) and picks the hottest word for every slot (tags: kHotSlots words).
+// scratch) and picks the hottest word for every slot.
 hipError_t launch_hot_prepare(const int32_t* u, const int32_t* v, int64_t m, int32_t n,
-                              uint32_t* counts, uint32_t* tags, hipStream_t s);
-// vals[t] = bits[tags[t] * kHotSlots + t]; no-op unless ctrl->filter_on.
+                              uint32_t* counts, uint32_t* tags, int slots, hipStream_t s);
+// vals[t] = bits[tags[t] * slots + t]; no-op unless ctrl->filter_on.
 hipError_t launch_hot_values(const uint32_t* bits, const uint32_t* tags, uint32_t* vals,
-                             const Ctrl* ctrl, hipStream_t s);
+                             const Ctrl* ctrl, int slots, hipStream_t s);
 // Filtered Atomic-Hook of entries [begin, end) answering bit tests from the
 // LDS copy of (tags, vals) when possible (persistent, one workgroup per CU).
 hipError_t launch_ahook_hot(const int32_t* u, const int32_t* v, int64_t begin, int64_t end,
                             int32_t* pi, int32_t n, Ctrl* ctrl, const uint32_t* bits,
-                            const uint32_t* tags, const uint32_t* vals, int ept, hipStream_t s);
+                            const uint32_t* tags, const uint32_t* vals, int ept, int slots,
+                            hipStream_t s);
 
 // Streaming and gather probes used to measure the memory ceilings.
 hipError_t launch_probe_stream(const int32_t* u, const int32_t* v, int64_t m, uint32_t* sink,

@@ -7,8 +7,8 @@
 // This file keeps the hottest words in LDS:
 //
 //   k_hot_count   counts sampled endpoint occurrences per bitmap word
-//   k_hot_select  for every LDS slot t (of kHotSlots), picks the hottest word
-//                 w = k * kHotSlots + t (direct-mapped; ties -> smallest k)
+//   k_hot_select  for every LDS slot t (of `slots`, 16384 or 32768), picks the
+//                 hottest word w = k * slots + t (direct-mapped; ties -> smallest k)
 //   k_hot_values  copies the chosen words' current bits (after each bitmap build)
 //   k_ahook_hot   the filtered Atomic-Hook, persistent: each workgroup loads
 //                 the (tag, word) table into LDS once and answers a bit test
@@ -44,11 +44,11 @@ __global__ __launch_bounds__(256) void k_hot_count(const int32_t* __restrict__ e
 }
 
 __global__ __launch_bounds__(256) void k_hot_select(const uint32_t* __restrict__ counts, int64_t nw,
-                                                    uint32_t* __restrict__ tags) {
+                                                    uint32_t* __restrict__ tags, int slots) {
     const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (t >= kHotSlots) return;
+    if (t >= slots) return;
     uint32_t best_k = kHotNone, best_c = 0;
-    for (int64_t w = t, k = 0; w < nw; w += kHotSlots, ++k) {
+    for (int64_t w = t, k = 0; w < nw; w += slots, ++k) {
         const uint32_t c = counts[w];
         if (best_k == kHotNone || c > best_c) {
             best_k = (uint32_t)k;
@@ -60,12 +60,13 @@ __global__ __launch_bounds__(256) void k_hot_select(const uint32_t* __restrict__
 
 __global__ __launch_bounds__(256) void k_hot_values(const uint32_t* __restrict__ bits,
                                                     const uint32_t* __restrict__ tags,
-                                                    uint32_t* __restrict__ vals, const Ctrl* ctrl) {
+                                                    uint32_t* __restrict__ vals, const Ctrl* ctrl,
+                                                    int slots) {
     if (!ctrl->filter_on) return;
     const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (t >= kHotSlots) return;
+    if (t >= slots) return;
     const uint32_t k = tags[t];
-    vals[t] = (k == kHotNone) ? 0u : bits[(int64_t)k * kHotSlots + t];
+    vals[t] = (k == kHotNone) ? 0u : bits[(int64_t)k * slots + t];
 }
 
 template <int EPT>
@@ -105,21 +106,25 @@ __device__ __forceinline__ void hot_climb(int32_t* pi, int32_t pu, int32_t pv) {
     }
 }
 
-template <int EPT>
+// SLOTS slots with tags of type TagT (16384 x uint16 = 96 KiB of LDS with the
+// words, or 32768 x uint8 = 160 KiB); a tag equal to TagT's maximum marks an
+// empty slot (also used for a word index too large for the tag type).
+template <int EPT, int SLOTS, typename TagT>
 __global__ __launch_bounds__(1024) void k_ahook_hot(const int32_t* __restrict__ eu,
                                                     const int32_t* __restrict__ ev, int64_t begin,
                                                     int64_t end, bool vec, int32_t* pi, int32_t n,
                                                     Ctrl* ctrl, const uint32_t* __restrict__ bits,
                                                     const uint32_t* __restrict__ gtags,
                                                     const uint32_t* __restrict__ gvals) {
-    __shared__ uint16_t ltag[kHotSlots];
-    __shared__ uint32_t lval[kHotSlots];
+    constexpr uint32_t kEmpty = (uint32_t)(TagT)(~(TagT)0);
+    __shared__ TagT ltag[SLOTS];
+    __shared__ uint32_t lval[SLOTS];
     const bool filter = ctrl->filter_on != 0;
     const int32_t g = ctrl->giant;
     if (filter) {
-        for (uint32_t t = threadIdx.x; t < kHotSlots; t += blockDim.x) {
+        for (uint32_t t = threadIdx.x; t < (uint32_t)SLOTS; t += blockDim.x) {
             const uint32_t k = gtags[t];
-            ltag[t] = (k == kHotNone || k > 0xfffe) ? (uint16_t)0xffff : (uint16_t)k;
+            ltag[t] = (TagT)((k == kHotNone || k >= kEmpty) ? kEmpty : k);
             lval[t] = gvals[t];
         }
         __syncthreads();
@@ -146,10 +151,11 @@ __global__ __launch_bounds__(1024) void k_ahook_hot(const int32_t* __restrict__ 
             uint32_t ba = 0, bb = 0;
             if (filter) {
                 const uint32_t wa = (uint32_t)a[j] >> 5, wb = (uint32_t)b[j] >> 5;
-                const uint32_t sa = wa & (kHotSlots - 1), sb = wb & (kHotSlots - 1);
-                const uint32_t ka = wa / kHotSlots, kb = wb / kHotSlots;
-                const uint32_t worda = (ltag[sa] == ka) ? lval[sa] : bits[wa];
-                const uint32_t wordb = (ltag[sb] == kb) ? lval[sb] : bits[wb];
+                const uint32_t sa = wa & (SLOTS - 1), sb = wb & (SLOTS - 1);
+                const uint32_t ka = wa / SLOTS, kb = wb / SLOTS;
+                // ka == kEmpty can never be cached (it is the empty marker)
+                const uint32_t worda = (ka < kEmpty && ltag[sa] == ka) ? lval[sa] : bits[wa];
+                const uint32_t wordb = (kb < kEmpty && ltag[sb] == kb) ? lval[sb] : bits[wb];
                 ba = worda >> (a[j] & 31) & 1;
                 bb = wordb >> (b[j] & 31) & 1;
             }
@@ -168,24 +174,41 @@ __global__ __launch_bounds__(1024) void k_ahook_hot(const int32_t* __restrict__ 
 }
 
 hipError_t launch_hot_prepare(const int32_t* u, const int32_t* v, int64_t m, int32_t n,
-                              uint32_t* counts, uint32_t* tags, hipStream_t s) {
+                              uint32_t* counts, uint32_t* tags, int slots, hipStream_t s) {
+    if (slots != 16384 && slots != 32768) return hipErrorInvalidValue;
     const int64_t nw = ((int64_t)n + 31) / 32;
     k_hot_zero<<<1024, 256, 0, s>>>(counts, nw);
-    const int64_t S = std::min<int64_t>(m, int64_t(1) << 20);
+    const int64_t S = std::min<int64_t>(m, int64_t(1) << 19);
     if (S > 0) k_hot_count<<<(int)((S + 255) / 256), 256, 0, s>>>(u, v, m, n, S, counts);
-    k_hot_select<<<kHotSlots / 256, 256, 0, s>>>(counts, nw, tags);
+    k_hot_select<<<slots / 256, 256, 0, s>>>(counts, nw, tags, slots);
     return hipGetLastError();
 }
 
 hipError_t launch_hot_values(const uint32_t* bits, const uint32_t* tags, uint32_t* vals,
-                             const Ctrl* ctrl, hipStream_t s) {
-    k_hot_values<<<kHotSlots / 256, 256, 0, s>>>(bits, tags, vals, ctrl);
+                             const Ctrl* ctrl, int slots, hipStream_t s) {
+    if (slots != 16384 && slots != 32768) return hipErrorInvalidValue;
+    k_hot_values<<<slots / 256, 256, 0, s>>>(bits, tags, vals, ctrl, slots);
+    return hipGetLastError();
+}
+
+template <int SLOTS, typename TagT>
+static hipError_t ahook_hot_ept(int ept, int grid, int block, hipStream_t s, const int32_t* u,
+                                const int32_t* v, int64_t begin, int64_t end, bool vec, int32_t* pi,
+                                int32_t n, Ctrl* ctrl, const uint32_t* bits, const uint32_t* tags,
+                                const uint32_t* vals) {
+    switch (ept) {
+        case 4: k_ahook_hot<4, SLOTS, TagT><<<grid, block, 0, s>>>(u, v, begin, end, vec, pi, n, ctrl, bits, tags, vals); break;
+        case 8: k_ahook_hot<8, SLOTS, TagT><<<grid, block, 0, s>>>(u, v, begin, end, vec, pi, n, ctrl, bits, tags, vals); break;
+        case 16: k_ahook_hot<16, SLOTS, TagT><<<grid, block, 0, s>>>(u, v, begin, end, vec, pi, n, ctrl, bits, tags, vals); break;
+        default: return hipErrorInvalidValue;
+    }
     return hipGetLastError();
 }
 
 hipError_t launch_ahook_hot(const int32_t* u, const int32_t* v, int64_t begin, int64_t end,
                             int32_t* pi, int32_t n, Ctrl* ctrl, const uint32_t* bits,
-                            const uint32_t* tags, const uint32_t* vals, int ept, hipStream_t s) {
+                            const uint32_t* tags, const uint32_t* vals, int ept, int slots,
+                            hipStream_t s) {
     if (end <= begin) return hipSuccess;
     const int block = 1024;
     const int64_t tile = (int64_t)block * ept;
@@ -193,13 +216,13 @@ hipError_t launch_ahook_hot(const int32_t* u, const int32_t* v, int64_t begin, i
     const int64_t cap = (int64_t)device_cu_count();  // one 1024-thread workgroup per CU (LDS)
     const int grid = (int)std::max<int64_t>(1, std::min<int64_t>(tiles, cap));
     const bool vec = (((uintptr_t)(u + begin) | (uintptr_t)(v + begin)) & 15) == 0;
-    switch (ept) {
-        case 4: k_ahook_hot<4><<<grid, block, 0, s>>>(u, v, begin, end, vec, pi, n, ctrl, bits, tags, vals); break;
-        case 8: k_ahook_hot<8><<<grid, block, 0, s>>>(u, v, begin, end, vec, pi, n, ctrl, bits, tags, vals); break;
-        case 16: k_ahook_hot<16><<<grid, block, 0, s>>>(u, v, begin, end, vec, pi, n, ctrl, bits, tags, vals); break;
-        default: return hipErrorInvalidValue;
-    }
-    return hipGetLastError();
+    if (slots == 16384)
+        return ahook_hot_ept<16384, uint16_t>(ept, grid, block, s, u, v, begin, end, vec, pi, n,
+                                              ctrl, bits, tags, vals);
+    if (slots == 32768)
+        return ahook_hot_ept<32768, uint8_t>(ept, grid, block, s, u, v, begin, end, vec, pi, n,
+                                             ctrl, bits, tags, vals);
+    return hipErrorInvalidValue;
 }
 
 }  // namespace hookcc

@@ -117,7 +117,7 @@ def test_workspace_sizes(lib):
     giant = cc.workspace_bytes(n, m, cc.Options(filter="giant", hot_cache="off"))
     assert giant == 256 + (n // 32) * 4
     hot = cc.workspace_bytes(n, m, cc.Options(filter="giant"))
-    assert hot == 256 + 2 * (n // 32) * 4 + 2 * 16384 * 4
+    assert hot == 256 + 2 * (n // 32) * 4 + 2 * 32768 * 4
     plain = cc.workspace_bytes(n, m, cc.Options(hook="plain"))
     assert plain == 256 + 2 * m * 8
     assert cc.workspace_bytes(-1, 5) == 0

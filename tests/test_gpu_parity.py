@@ -40,6 +40,8 @@ VARIANTS = {
                                   edges_per_thread=8, block=512),
     "s6_giant_nohot_e4": cc.Options(hook="atomic", segments=6, filter="giant", hot_cache="off",
                                     edges_per_thread=4),
+    "s12_giant_hotlarge_e16": cc.Options(hook="atomic", segments=12, filter="giant",
+                                         hot_cache="large", edges_per_thread=16),
     "plain_b128_e16_k1": cc.Options(hook="plain", edges_per_thread=16, block=128,
                                     rounds_per_check=1),
     "plain_e4_k7": cc.Options(hook="plain", edges_per_thread=4, rounds_per_check=7),
@@ -321,7 +323,8 @@ def test_full_size_workloads_match_oracle_digest(dev, name):
     assert (n, len(u)) == (rec["n"], rec["m"])
     du, dv = to_dev(u, dev), to_dev(v, dev)
     del u, v
-    for opt in ("default", "plain", "atomic", "s1", "coherent_giant", "s6_giant_nohot_e4"):
+    for opt in ("default", "plain", "atomic", "s1", "coherent_giant", "s6_giant_nohot_e4",
+                "s12_giant_hotlarge_e16"):
         if name == "rmat24" and opt == "s1":
             opt = "s9_giant_after3"
         say("full size", name, opt)

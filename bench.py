@@ -54,6 +54,7 @@ def main():
     ap.add_argument("--block", type=int, default=0)
     ap.add_argument("--profile-steps", type=int, default=3)
     ap.add_argument("--coherent", action="store_true", help="agent-scope tree loads (A/B only)")
+    ap.add_argument("--hot", default="auto", choices=["auto", "on", "off", "large"])
     ap.add_argument("--skip-cpu", action="store_true")
     ap.add_argument("--skip-batch", action="store_true")
     ap.add_argument("--mode", default="solve", choices=["solve", "ablation", "serving", "tune"],
@@ -99,7 +100,8 @@ def main():
                                              loads=(0.5, 0.7, 0.9), host_mode=True)}), flush=True)
         return
     opts = cc.Options(hook=args.hook, filter=args.filter, segments=args.segments,
-                      edges_per_thread=args.ept, block=args.block, coherent_loads=args.coherent)
+                      edges_per_thread=args.ept, block=args.block, coherent_loads=args.coherent,
+                      hot_cache=args.hot)
 
     log("generating", args.workload)
     t = time.time()
@@ -146,8 +148,8 @@ def main():
     if st.get("hook") == 1:
         alg_bytes = 8.0 * m  # each int32 (u, v) entry read once across the Atomic-Hook launches
         kernel = "k_ahook + k_ahook_hot (all Atomic-Hook launches of one solve)"
-        if args.hook == "auto" and args.filter == "auto" and not (args.segments or args.ept or
-                                                                  args.block or args.coherent):
+        if args.hook == "auto" and args.filter == "auto" and args.hot == "auto" and not (
+                args.segments or args.ept or args.block or args.coherent):
             traffic = measured_traffic(args.workload, "atomic")
     else:
         alg_bytes = 8.0 * m  # first Hook pass over the input entries

@@ -221,9 +221,13 @@ ABLATION = [
     # Fig. 5 progression, then this build's additions
     ("fig1_hostloop_jump", dict(hook="plain", host_loop="jump")),
     ("fig1_hostloop_multijump", dict(hook="plain", host_loop="multijump")),
-    ("atomic_hook_s1", dict(hook="atomic", segments=1, filter="off")),
-    ("adaptive_fig4", dict(hook="atomic", filter="off")),
-    ("adaptive_giant_filter", dict(hook="atomic", filter="giant")),
+    ("atomic_hook_s1", dict(hook="atomic", segments=1, filter="off", path_halving="off")),
+    ("adaptive_fig4", dict(hook="atomic", filter="off", path_halving="off")),
+    ("adaptive_fig4_halving", dict(hook="atomic", filter="off")),
+    ("atomic_s1_halving", dict(hook="atomic", segments=1, filter="off")),
+    ("adaptive_giant_filter", dict(hook="atomic", filter="giant", path_halving="off",
+                                   hot_cache="off")),
+    ("giant_filter_hot_halving", dict(hook="atomic", filter="giant")),
     ("plain_device_convergence", dict(hook="plain")),
     ("library_auto", dict()),
 ]
@@ -247,7 +251,8 @@ def ablation(cc, torch, dev, args, reps=5):
         del u_np, v_np
         out = torch.empty(n, dtype=torch.int32, device=dev)
         rows = {}
-        variants = list(ABLATION) + [("fig6_s%d" % s, dict(hook="atomic", filter="off", segments=s))
+        variants = list(ABLATION) + [("fig6_s%d" % s, dict(hook="atomic", filter="off", segments=s,
+                                                       path_halving="off"))
                                      for s in SEGMENT_SWEEP]
         for vname, kw in variants:
             opt = cc.Options(**kw)

@@ -104,18 +104,25 @@ typedef struct cc_options {
                                  L2); 0 (default) = cached loads, which may return an
                                  older ancestor -- always a valid one (kept for
                                  measurement; results are identical)                   */
-    int32_t hot_cache;        /* giant filter only: CC_HOT_AUTO (default, = CC_HOT_ON),
+    int32_t hot_cache;        /* giant filter only: CC_HOT_AUTO (default, = CC_HOT_LARGE),
                                  CC_HOT_ON (16,384 LDS slots), CC_HOT_LARGE (32,768 slots,
                                  all 160 KiB of LDS) or CC_HOT_OFF -- keep the bitmap words
                                  that sampled endpoints hit most often in LDS and answer
                                  those bit tests there                                   */
-    int32_t reserved[4];      /* must be zero                                           */
+    int32_t path_halving;     /* Atomic-Hook climb: CC_HALVE_AUTO (default, on), CC_HALVE_ON
+                                 or CC_HALVE_OFF (Fig. 3 exactly) -- re-point each non-root
+                                 passed on the way up at its grandparent                  */
+    int32_t reserved[3];      /* must be zero                                           */
 } cc_options;
 
 #define CC_HOT_AUTO 0
 #define CC_HOT_ON 1
 #define CC_HOT_OFF 2
 #define CC_HOT_LARGE 3
+
+#define CC_HALVE_AUTO 0
+#define CC_HALVE_ON 1
+#define CC_HALVE_OFF 2
 
 #define CC_HOST_LOOP_OFF 0
 #define CC_HOST_LOOP_JUMP 1

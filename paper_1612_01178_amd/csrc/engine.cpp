@@ -58,7 +58,8 @@ struct Plan {
     int host_loop = CC_HOST_LOOP_OFF;
     bool coherent = false;
     bool hot = false;  // hot-word LDS cache of the giant bitmap
-    int hot_slots = 16384;
+    int hot_slots = 32768;
+    bool halve = true;  // path halving in the Atomic-Hook climb
 };
 
 int32_t make_plan(int32_t n, int64_t m, const cc_options* o, Plan& p, bool allow_plain = true) {
@@ -66,11 +67,14 @@ int32_t make_plan(int32_t n, int64_t m, const cc_options* o, Plan& p, bool allow
     std::memset(&d, 0, sizeof d);
     d.filter = CC_FILTER_AUTO;
     const cc_options& op = o ? *o : d;
-    for (int i = 0; i < 4; ++i)
+    for (int i = 0; i < 3; ++i)
         if (op.reserved[i] != 0) return fail(CC_ERR_ARG, "cc_options.reserved must be zero");
     if (op.hot_cache < CC_HOT_AUTO || op.hot_cache > CC_HOT_LARGE)
         return fail(CC_ERR_ARG, "unknown cc_options.hot_cache");
-    p.hot_slots = op.hot_cache == CC_HOT_LARGE ? 32768 : 16384;
+    p.hot_slots = op.hot_cache == CC_HOT_ON ? 16384 : 32768;
+    if (op.path_halving < CC_HALVE_AUTO || op.path_halving > CC_HALVE_OFF)
+        return fail(CC_ERR_ARG, "unknown cc_options.path_halving");
+    p.halve = op.path_halving != CC_HALVE_OFF;
     if (op.coherent_loads != 0 && op.coherent_loads != 1)
         return fail(CC_ERR_ARG, "cc_options.coherent_loads must be 0 or 1");
     p.coherent = op.coherent_loads == 1;
@@ -336,7 +340,7 @@ int32_t enqueue_atomic(int32_t n, const int32_t* u, const int32_t* v, int64_t m,
         // Fig. 4: for each segment, Atomic-Hook the segment, then Multi-Jump all of V.
         for (int i = 0; i < S; ++i) {
             TIMED(kPhaseHook, launch_ahook(u, v, bound(i), bound(i + 1), pi, n, ctrl, nullptr,
-                                           p.block, p.ept, p.coherent, s));
+                                           p.block, p.ept, p.coherent, p.halve, s));
             TIMED(kPhaseCompress, launch_mj(pi, n, nullptr, p.coherent, s));
             ++hooks;
             ++jumps;
@@ -345,7 +349,7 @@ int32_t enqueue_atomic(int32_t n, const int32_t* u, const int32_t* v, int64_t m,
         const int fa = p.filter_after;
         for (int i = 0; i < fa; ++i) {
             TIMED(kPhaseHook, launch_ahook(u, v, bound(i), bound(i + 1), pi, n, ctrl, nullptr,
-                                           p.block, p.ept, p.coherent, s));
+                                           p.block, p.ept, p.coherent, p.halve, s));
             TIMED(kPhaseCompress, launch_mj(pi, n, nullptr, p.coherent, s));
             ++hooks;
             ++jumps;
@@ -366,10 +370,10 @@ int32_t enqueue_atomic(int32_t n, const int32_t* u, const int32_t* v, int64_t m,
             if (hot)
                 TIMED(kPhaseHook, launch_ahook_hot(u, v, bound(g), bound(h), pi, n, ctrl, bits,
                                                    fb.hot_tags, fb.hot_vals, p.ept, p.hot_slots,
-                                                   s));
+                                                   p.halve, s));
             else
                 TIMED(kPhaseHook, launch_ahook(u, v, bound(g), bound(h), pi, n, ctrl, bits,
-                                               p.block, p.ept, p.coherent, s));
+                                               p.block, p.ept, p.coherent, p.halve, s));
             TIMED(kPhaseCompress, launch_mj(pi, n, nullptr, p.coherent, s));
             ++hooks;
             ++jumps;

@@ -62,7 +62,13 @@ __device__ __forceinline__ void load_edges(const int32_t* __restrict__ p, int64_
 // smaller than the slot's index, so no cycle can form, and the loop ends
 // because max(pu, pv) strictly decreases (every value read at a slot is at
 // most the slot's index, and below it once the slot is not a root).
-template <bool COH>
+//
+// HALVE (not in the paper): on the way up, a non-root H whose grandparent
+// differs from its parent is re-pointed at the grandparent (path halving, as
+// in sequential union-find).  H is already a non-root, so no CAS on it can
+// succeed any more, and the value stored is an ancestor of H, smaller than
+// H: the tree relation is unchanged and later climbs through H are shorter.
+template <bool COH, bool HALVE>
 __device__ __forceinline__ void atomic_hook(int32_t* pi, int32_t pu, int32_t pv) {
     while (pu != pv) {
         const int32_t H = pu > pv ? pu : pv;
@@ -74,6 +80,7 @@ __device__ __forceinline__ void atomic_hook(int32_t* pi, int32_t pu, int32_t pv)
         }
         pu = ld_tree<COH>(pi + found);
         pv = ld_tree<COH>(pi + L);
+        if (HALVE && pu != found) st_tree<COH>(pi + H, pu);
     }
 }
 
@@ -118,7 +125,7 @@ hipError_t launch_init(int32_t* pi, int32_t n, Ctrl* ctrl, hipStream_t s) {
 // satisfied and is skipped; an endpoint with its bit set starts its climb at
 // g instead of gathering pi (any vertex of the endpoint's tree is a valid
 // start for Atomic-Hook, since only tree membership matters).
-template <int EPT, bool VEC, bool FILTER, bool COH>
+template <int EPT, bool VEC, bool FILTER, bool COH, bool HALVE>
 __global__ __launch_bounds__(1024) void k_ahook(const int32_t* __restrict__ eu,
                                                 const int32_t* __restrict__ ev, int64_t begin,
                                                 int64_t end, int32_t* pi, int32_t n, Ctrl* ctrl,
@@ -166,29 +173,33 @@ __global__ __launch_bounds__(1024) void k_ahook(const int32_t* __restrict__ eu,
     }
 #pragma unroll
     for (int j = 0; j < EPT; ++j)
-        if (act >> j & 1) atomic_hook<COH>(pi, pa[j], pb[j]);
+        if (act >> j & 1) atomic_hook<COH, HALVE>(pi, pa[j], pb[j]);
 }
 
 template <int EPT, bool FILTER, bool COH>
-static void ahook_dispatch(bool vec, int grid, int block, hipStream_t s, const int32_t* u,
-                           const int32_t* v, int64_t begin, int64_t end, int32_t* pi, int32_t n,
-                           Ctrl* ctrl, const uint32_t* bits) {
-    if (vec)
-        k_ahook<EPT, true, FILTER, COH><<<grid, block, 0, s>>>(u, v, begin, end, pi, n, ctrl, bits);
+static void ahook_dispatch(bool vec, bool halve, int grid, int block, hipStream_t s,
+                           const int32_t* u, const int32_t* v, int64_t begin, int64_t end,
+                           int32_t* pi, int32_t n, Ctrl* ctrl, const uint32_t* bits) {
+    if (vec && halve)
+        k_ahook<EPT, true, FILTER, COH, true><<<grid, block, 0, s>>>(u, v, begin, end, pi, n, ctrl, bits);
+    else if (vec)
+        k_ahook<EPT, true, FILTER, COH, false><<<grid, block, 0, s>>>(u, v, begin, end, pi, n, ctrl, bits);
+    else if (halve)
+        k_ahook<EPT, false, FILTER, COH, true><<<grid, block, 0, s>>>(u, v, begin, end, pi, n, ctrl, bits);
     else
-        k_ahook<EPT, false, FILTER, COH><<<grid, block, 0, s>>>(u, v, begin, end, pi, n, ctrl, bits);
+        k_ahook<EPT, false, FILTER, COH, false><<<grid, block, 0, s>>>(u, v, begin, end, pi, n, ctrl, bits);
 }
 
 template <int EPT>
-static void ahook_dispatch2(bool vec, bool filter, bool coh, int grid, int block, hipStream_t s,
-                            const int32_t* u, const int32_t* v, int64_t begin, int64_t end,
-                            int32_t* pi, int32_t n, Ctrl* ctrl, const uint32_t* bits) {
+static void ahook_dispatch2(bool vec, bool filter, bool coh, bool halve, int grid, int block,
+                            hipStream_t s, const int32_t* u, const int32_t* v, int64_t begin,
+                            int64_t end, int32_t* pi, int32_t n, Ctrl* ctrl, const uint32_t* bits) {
     if (filter) {
-        if (coh) ahook_dispatch<EPT, true, true>(vec, grid, block, s, u, v, begin, end, pi, n, ctrl, bits);
-        else ahook_dispatch<EPT, true, false>(vec, grid, block, s, u, v, begin, end, pi, n, ctrl, bits);
+        if (coh) ahook_dispatch<EPT, true, true>(vec, halve, grid, block, s, u, v, begin, end, pi, n, ctrl, bits);
+        else ahook_dispatch<EPT, true, false>(vec, halve, grid, block, s, u, v, begin, end, pi, n, ctrl, bits);
     } else {
-        if (coh) ahook_dispatch<EPT, false, true>(vec, grid, block, s, u, v, begin, end, pi, n, ctrl, bits);
-        else ahook_dispatch<EPT, false, false>(vec, grid, block, s, u, v, begin, end, pi, n, ctrl, bits);
+        if (coh) ahook_dispatch<EPT, false, true>(vec, halve, grid, block, s, u, v, begin, end, pi, n, ctrl, bits);
+        else ahook_dispatch<EPT, false, false>(vec, halve, grid, block, s, u, v, begin, end, pi, n, ctrl, bits);
     }
 }
 
@@ -196,7 +207,7 @@ static bool aligned16(const void* p) { return ((uintptr_t)p & 15) == 0; }
 
 hipError_t launch_ahook(const int32_t* u, const int32_t* v, int64_t begin, int64_t end,
                         int32_t* pi, int32_t n, Ctrl* ctrl, const uint32_t* bits, int block,
-                        int ept, bool coherent, hipStream_t s) {
+                        int ept, bool coherent, bool halve, hipStream_t s) {
     if (end <= begin) return hipSuccess;
     const int64_t tile = (int64_t)block * ept;
     const int64_t grid64 = (end - begin + tile - 1) / tile;
@@ -205,9 +216,9 @@ hipError_t launch_ahook(const int32_t* u, const int32_t* v, int64_t begin, int64
     const bool vec = aligned16(u + begin) && aligned16(v + begin);
     const bool f = bits != nullptr;
     switch (ept) {
-        case 4: ahook_dispatch2<4>(vec, f, coherent, grid, block, s, u, v, begin, end, pi, n, ctrl, bits); break;
-        case 8: ahook_dispatch2<8>(vec, f, coherent, grid, block, s, u, v, begin, end, pi, n, ctrl, bits); break;
-        case 16: ahook_dispatch2<16>(vec, f, coherent, grid, block, s, u, v, begin, end, pi, n, ctrl, bits); break;
+        case 4: ahook_dispatch2<4>(vec, f, coherent, halve, grid, block, s, u, v, begin, end, pi, n, ctrl, bits); break;
+        case 8: ahook_dispatch2<8>(vec, f, coherent, halve, grid, block, s, u, v, begin, end, pi, n, ctrl, bits); break;
+        case 16: ahook_dispatch2<16>(vec, f, coherent, halve, grid, block, s, u, v, begin, end, pi, n, ctrl, bits); break;
         default: return hipErrorInvalidValue;
     }
     return hipGetLastError();

@@ -92,7 +92,7 @@ __device__ __forceinline__ void load_tile(const int32_t* __restrict__ p, int64_t
 
 // Atomic-Hook climb (Fig. 3, top), cached loads; see atomic_hook in
 // kernels_core.hip for the argument.
-__device__ __forceinline__ void hot_climb(int32_t* pi, int32_t pu, int32_t pv) {
+__device__ __forceinline__ void hot_climb(int32_t* pi, int32_t pu, int32_t pv, bool halve) {
     while (pu != pv) {
         const int32_t H = pu > pv ? pu : pv;
         const int32_t L = pu > pv ? pv : pu;
@@ -103,6 +103,7 @@ __device__ __forceinline__ void hot_climb(int32_t* pi, int32_t pu, int32_t pv) {
         }
         pu = ld_tree<false>(pi + found);
         pv = ld_tree<false>(pi + L);
+        if (halve && pu != found) st_tree<false>(pi + H, pu);  // path halving
     }
 }
 
@@ -115,7 +116,7 @@ __global__ __launch_bounds__(1024) void k_ahook_hot(const int32_t* __restrict__ 
                                                     int64_t end, bool vec, int32_t* pi, int32_t n,
                                                     Ctrl* ctrl, const uint32_t* __restrict__ bits,
                                                     const uint32_t* __restrict__ gtags,
-                                                    const uint32_t* __restrict__ gvals) {
+                                                    const uint32_t* __restrict__ gvals, bool halve) {
     constexpr uint32_t kEmpty = (uint32_t)(TagT)(~(TagT)0);
     __shared__ TagT ltag[SLOTS];
     __shared__ uint32_t lval[SLOTS];
@@ -168,7 +169,7 @@ __global__ __launch_bounds__(1024) void k_ahook_hot(const int32_t* __restrict__ 
         }
 #pragma unroll
         for (int j = 0; j < EPT; ++j)
-            if (act >> j & 1) hot_climb(pi, pa[j], pb[j]);
+            if (act >> j & 1) hot_climb(pi, pa[j], pb[j], halve);
     }
     if (bad) atomicOr(&ctrl->status, kStatusRange);
 }
@@ -195,11 +196,11 @@ template <int SLOTS, typename TagT>
 static hipError_t ahook_hot_ept(int ept, int grid, int block, hipStream_t s, const int32_t* u,
                                 const int32_t* v, int64_t begin, int64_t end, bool vec, int32_t* pi,
                                 int32_t n, Ctrl* ctrl, const uint32_t* bits, const uint32_t* tags,
-                                const uint32_t* vals) {
+                                const uint32_t* vals, bool halve) {
     switch (ept) {
-        case 4: k_ahook_hot<4, SLOTS, TagT><<<grid, block, 0, s>>>(u, v, begin, end, vec, pi, n, ctrl, bits, tags, vals); break;
-        case 8: k_ahook_hot<8, SLOTS, TagT><<<grid, block, 0, s>>>(u, v, begin, end, vec, pi, n, ctrl, bits, tags, vals); break;
-        case 16: k_ahook_hot<16, SLOTS, TagT><<<grid, block, 0, s>>>(u, v, begin, end, vec, pi, n, ctrl, bits, tags, vals); break;
+        case 4: k_ahook_hot<4, SLOTS, TagT><<<grid, block, 0, s>>>(u, v, begin, end, vec, pi, n, ctrl, bits, tags, vals, halve); break;
+        case 8: k_ahook_hot<8, SLOTS, TagT><<<grid, block, 0, s>>>(u, v, begin, end, vec, pi, n, ctrl, bits, tags, vals, halve); break;
+        case 16: k_ahook_hot<16, SLOTS, TagT><<<grid, block, 0, s>>>(u, v, begin, end, vec, pi, n, ctrl, bits, tags, vals, halve); break;
         default: return hipErrorInvalidValue;
     }
     return hipGetLastError();
@@ -208,7 +209,7 @@ static hipError_t ahook_hot_ept(int ept, int grid, int block, hipStream_t s, con
 hipError_t launch_ahook_hot(const int32_t* u, const int32_t* v, int64_t begin, int64_t end,
                             int32_t* pi, int32_t n, Ctrl* ctrl, const uint32_t* bits,
                             const uint32_t* tags, const uint32_t* vals, int ept, int slots,
-                            hipStream_t s) {
+                            bool halve, hipStream_t s) {
     if (end <= begin) return hipSuccess;
     const int block = 1024;
     const int64_t tile = (int64_t)block * ept;
@@ -218,10 +219,10 @@ hipError_t launch_ahook_hot(const int32_t* u, const int32_t* v, int64_t begin, i
     const bool vec = (((uintptr_t)(u + begin) | (uintptr_t)(v + begin)) & 15) == 0;
     if (slots == 16384)
         return ahook_hot_ept<16384, uint16_t>(ept, grid, block, s, u, v, begin, end, vec, pi, n,
-                                              ctrl, bits, tags, vals);
+                                              ctrl, bits, tags, vals, halve);
     if (slots == 32768)
         return ahook_hot_ept<32768, uint8_t>(ept, grid, block, s, u, v, begin, end, vec, pi, n,
-                                             ctrl, bits, tags, vals);
+                                             ctrl, bits, tags, vals, halve);
     return hipErrorInvalidValue;
 }
 

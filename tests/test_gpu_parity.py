@@ -33,6 +33,9 @@ VARIANTS = {
     "plain": cc.Options(hook="plain"),
     "atomic": cc.Options(hook="atomic"),
     "s1": cc.Options(hook="atomic", segments=1, filter="off"),
+    "s3_nohalve": cc.Options(hook="atomic", segments=3, filter="off", path_halving="off"),
+    "s8_giant_nohalve": cc.Options(hook="atomic", segments=8, filter="giant", path_halving="off",
+                                   hot_cache="on"),
     "s7_b64_e4": cc.Options(hook="atomic", segments=7, filter="off", edges_per_thread=4, block=64),
     "s5_giant_b1024_e16": cc.Options(hook="atomic", segments=5, filter="giant", filter_after=1,
                                      edges_per_thread=16, block=1024),
@@ -324,7 +327,7 @@ def test_full_size_workloads_match_oracle_digest(dev, name):
     du, dv = to_dev(u, dev), to_dev(v, dev)
     del u, v
     for opt in ("default", "plain", "atomic", "s1", "coherent_giant", "s6_giant_nohot_e4",
-                "s12_giant_hotlarge_e16"):
+                "s12_giant_hotlarge_e16", "s8_giant_nohalve"):
         if name == "rmat24" and opt == "s1":
             opt = "s9_giant_after3"
         say("full size", name, opt)

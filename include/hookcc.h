@@ -58,9 +58,9 @@ extern "C" {
 #define CC_ERR_NOCONVERGE (-5) /* the atomic-free Hook hit opts->max_rounds       */
 
 /* ---------------------------------------------------------------- options */
-#define CC_HOOK_AUTO 0   /* library choice (the default): Atomic-Hook with the giant
-                            filter for large dense lists (m >= 2^22 entries and
-                            m / n >= 8), the atomic-free Hook otherwise                 */
+#define CC_HOOK_AUTO 0   /* library choice (the default): Atomic-Hook for lists of
+                            m >= 2^22 entries (with the giant filter when m / n >= 8),
+                            the atomic-free Hook for smaller lists                     */
 #define CC_HOOK_ATOMIC 1 /* Atomic-Hook (Fig. 3, CAS on roots) + segmentation (Fig. 4) */
 #define CC_HOOK_PLAIN 2  /* atomic-free Hook (Fig. 2) rounds until no change (Fig. 1),
                             convergence test and active-edge frontier on the device   */

@@ -84,18 +84,21 @@ int32_t make_plan(int32_t n, int64_t m, const cc_options* o, Plan& p, bool allow
     // Average-degree heuristic (Section 3.B, Fig. 4): s = 2|E|/|V| with |E|
     // counted once per undirected edge, i.e. s = (entries passed) / n.
     const int64_t s_paper = n > 0 ? std::max<int64_t>(1, (m + n / 2) / n) : 1;
-    // Automatic variant (measured on gfx950): on large lists of average degree
-    // >= 8 the giant filter turns most entries into two L2 bitmap tests and
-    // Atomic-Hook wins; on sparse or small lists (few rounds, long chains that
-    // a Compress per round flattens) the atomic-free rounds win.
-    const bool dense_large = m >= (int64_t(1) << 22) && n > 0 && m >= 8 * (int64_t)n;
+    // Automatic variant (measured on gfx950): on large lists Atomic-Hook with
+    // path halving wins (one pass over the entries; R-MAT 24 4.6 ms vs 38 ms,
+    // percolated 4096^2 grid 0.99 vs 1.25 ms), and from average degree 8 the
+    // giant filter turns most entries into two bitmap tests.  On small lists
+    // (< 2^22 entries) launch count dominates and the atomic-free rounds, with
+    // fewer kernels, win (ER 2^16: 0.10 vs 0.13 ms).
+    const bool large = m >= (int64_t(1) << 22);
+    const bool dense_large = large && n > 0 && m >= 8 * (int64_t)n;
     bool auto_filtered = false;
     if (op.hook == CC_HOOK_AUTO) {
-        if (dense_large && allow_plain) {
+        if (large || !allow_plain) {
             p.hook = CC_HOOK_ATOMIC;
-            auto_filtered = op.filter != CC_FILTER_OFF;
+            auto_filtered = dense_large && op.filter != CC_FILTER_OFF;
         } else {
-            p.hook = allow_plain ? CC_HOOK_PLAIN : CC_HOOK_ATOMIC;
+            p.hook = CC_HOOK_PLAIN;
         }
     } else {
         p.hook = op.hook;
@@ -114,6 +117,8 @@ int32_t make_plan(int32_t n, int64_t m, const cc_options* o, Plan& p, bool allow
     p.filter_after = op.filter_after ? op.filter_after : 1;
     if (p.hook != CC_HOOK_ATOMIC) {
         p.filter = CC_FILTER_OFF;
+    } else if (op.hook == CC_HOOK_AUTO && op.filter == CC_FILTER_AUTO) {
+        p.filter = auto_filtered ? CC_FILTER_GIANT : CC_FILTER_OFF;
     } else if (op.filter == CC_FILTER_AUTO) {
         // A giant component is near-certain at average degree >= 3.5, and the
         // sample + bitmap cost only pays off on large edge lists.

@@ -205,6 +205,26 @@ int32_t cc_labels_batch_ex(int32_t num_graphs, const int64_t* vtx_off, const int
                            const int32_t* edges_u, const int32_t* edges_v, int32_t* out_label,
                            void* stream, cc_stats* stats);
 
+/* Out-of-core solve: the edge lists stay in HOST memory and are streamed to
+ * the device in chunks while earlier chunks are hooked.  The Atomic-Hook
+ * reads every entry exactly once (Section 3.A), so each chunk is copied once
+ * into one of two device staging buffers and hooked, followed by a
+ * Multi-Jump (Fig. 4 with one segment per chunk; with the giant filter the
+ * first chunk's labels are sampled and later chunks are filtered).  Device
+ * memory holds only out_label, the bitmap and 2 x 2 x chunk_entries int32.
+ *   host_u, host_v  [host] int32[m]; pinned memory (hipHostMalloc / torch
+ *                   pin_memory) lets the copies overlap the hooks
+ *   out_label       [device] int32[n]
+ *   chunk_entries   entries per chunk (rounded down to a multiple of 4);
+ *                   0 = 2^24
+ *   opts            as cc_labels_ex; hook must be CC_HOOK_AUTO or CC_HOOK_ATOMIC
+ *   stream          hipStream_t for the hooks (NULL = null stream); copies run
+ *                   on a library stream ordered against it with events
+ * Returns after the labels are complete; same status codes as cc_labels_ex. */
+int32_t cc_labels_host(int32_t n, const int32_t* host_u, const int32_t* host_v, int64_t m,
+                       int32_t* out_label, int64_t chunk_entries, const cc_options* opts,
+                       void* stream, cc_stats* stats);
+
 /* One graph of a graph list: its own device arrays, local ids in [0, n). */
 typedef struct cc_graph {
     const int32_t* edges_u; /* [device] int32[m]                                          */

@@ -36,7 +36,7 @@ _HOST_LOOPS = {"off": 0, "jump": 1, "multijump": 2}
 
 # Every symbol include/hookcc.h declares.
 EXPORTS = ("cc_options_init", "cc_labels", "cc_labels_ex", "cc_workspace_bytes",
-           "cc_labels_batch", "cc_labels_batch_ex", "cc_labels_list", "cc_probe",
+           "cc_labels_batch", "cc_labels_batch_ex", "cc_labels_list", "cc_labels_host", "cc_probe",
            "cc_last_error", "cc_release", "cc_version", "cc_server_create",
            "cc_server_submit", "cc_server_wait", "cc_server_poll", "cc_server_stats",
            "cc_server_destroy", "cc_server_clock")
@@ -173,6 +173,9 @@ def load():
             lib.cc_server_destroy.restype = _i32
             lib.cc_server_clock.argtypes = []
             lib.cc_server_clock.restype = ctypes.c_double
+            lib.cc_labels_host.argtypes = [_i32, _vp, _vp, _i64, _vp, _i64,
+                                           ctypes.POINTER(_COptions), _vp, ctypes.POINTER(_CStats)]
+            lib.cc_labels_host.restype = _i32
             lib.cc_probe.argtypes = [_i32, _vp, _vp, _i64, _vp, _i32, _vp]
             lib.cc_probe.restype = _i32
             lib.cc_last_error.argtypes = []
@@ -283,6 +286,38 @@ def labels_batch(u, v, vtx_off, edge_off, *, out=None, stream=None, return_stats
         rc = load().cc_labels_batch_ex(len(vo) - 1, vo.ctypes.data, eo.ctypes.data, u.data_ptr(),
                                        v.data_ptr(), out.data_ptr(), _stream_handle(stream),
                                        ctypes.byref(st))
+    _check(rc)
+    if return_stats:
+        return out, {f: getattr(st, f) for f, _ in _CStats._fields_ if f != "reserved"}
+    return out
+
+
+def labels_host(u, v, n: int, *, chunk: int = 0, out=None, device=None,
+                options: Options | None = None, stream=None, return_stats: bool = False):
+    """Labels of a graph whose edge lists stay in host memory (numpy int32 or
+    CPU torch tensors; pinned memory lets copies overlap the hooks), streamed
+    to the device in chunks of ``chunk`` entries.  Returns a CUDA tensor."""
+    import numpy as np
+    import torch
+    if isinstance(u, torch.Tensor):
+        if u.dtype != torch.int32 or u.device.type != "cpu" or not u.is_contiguous():
+            raise TypeError("u must be a contiguous int32 CPU tensor")
+        up, vp, m = u.data_ptr(), v.data_ptr(), u.numel()
+    else:
+        u = np.ascontiguousarray(u, dtype=np.int32)
+        v = np.ascontiguousarray(v, dtype=np.int32)
+        up, vp, m = u.ctypes.data, v.ctypes.data, len(u)
+    if len(v) != m:
+        raise ValueError("u and v differ in length")
+    dev = torch.device(device) if device is not None else torch.device("cuda", torch.cuda.current_device())
+    if out is None:
+        out = torch.empty(max(int(n), 0), dtype=torch.int32, device=dev)
+    opts = (options or Options())._c()
+    st = _CStats()
+    with torch.cuda.device(out.device):
+        rc = load().cc_labels_host(int(n), up if m else None, vp if m else None, m,
+                                   out.data_ptr() if n else None, int(chunk), ctypes.byref(opts),
+                                   _stream_handle(stream), ctypes.byref(st))
     _check(rc)
     if return_stats:
         return out, {f: getattr(st, f) for f, _ in _CStats._fields_ if f != "reserved"}

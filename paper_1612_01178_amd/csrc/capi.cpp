@@ -46,6 +46,13 @@ int32_t cc_labels_list(int32_t count, const cc_graph* graphs, void* stream, cc_s
     return list_impl(count, graphs, static_cast<hipStream_t>(stream), stats);
 }
 
+int32_t cc_labels_host(int32_t n, const int32_t* host_u, const int32_t* host_v, int64_t m,
+                       int32_t* out_label, int64_t chunk_entries, const cc_options* opts,
+                       void* stream, cc_stats* stats) {
+    return stream_impl(n, host_u, host_v, m, out_label, chunk_entries, opts,
+                       static_cast<hipStream_t>(stream), stats);
+}
+
 int32_t cc_probe(int32_t mode, const int32_t* edges_u, const int32_t* edges_v, int64_t m,
                  const void* table, int32_t n, void* stream) {
     return probe_impl(mode, edges_u, edges_v, m, table, n, static_cast<hipStream_t>(stream));

@@ -196,6 +196,9 @@ struct PoolEntry {
     int64_t host_ctrl_count = 0;
     void* host_stage = nullptr; // pinned staging for batch descriptors
     size_t stage_bytes = 0;
+    hipStream_t copy_stream = nullptr;  // host-to-device staging of streamed solves
+    hipEvent_t copied[2] = {nullptr, nullptr};
+    hipEvent_t consumed[2] = {nullptr, nullptr};
 };
 
 std::mutex g_pool_mu;
@@ -570,6 +573,103 @@ int32_t labels_impl(int32_t n, const int32_t* u, const int32_t* v, int64_t m, in
 }
 
 
+// ---------------------------------------------------------------------- streamed solve
+// Edges in host memory, larger than one wants to (or can) hold in HBM.  The
+// Atomic-Hook reads every entry exactly once, so the list is cut into chunks
+// that are copied host-to-device on a copy stream into two staging buffers
+// (double buffering: chunk i+1 is copied while chunk i is hooked) and hooked
+// on the caller's stream, each chunk followed by a Multi-Jump (Fig. 4 with one
+// segment per chunk).  With the giant filter, the first chunk's Compress is
+// followed by the sample and the bitmap, which later chunks use and which is
+// rebuilt after each chunk's Compress.  Only pi, the bitmap and the staging
+// buffers (2 x 2 x chunk x 4 bytes) occupy device memory.
+int32_t stream_impl(int32_t n, const int32_t* hu, const int32_t* hv, int64_t m, int32_t* out,
+                    int64_t chunk, const cc_options* opts, hipStream_t s, cc_stats* st) {
+    int32_t rc = check_args(n, hu, hv, m, out);
+    if (rc != CC_OK) return rc;
+    if (chunk < 0) return fail(CC_ERR_ARG, "chunk_entries < 0");
+    if (chunk == 0) chunk = int64_t(1) << 24;
+    chunk = std::max<int64_t>(4, chunk & ~int64_t(3));
+    if (opts && opts->hook == CC_HOOK_PLAIN)
+        return fail(CC_ERR_ARG, "streamed solves use the Atomic-Hook (each entry is read once)");
+    Plan p;
+    rc = make_plan(n, m, opts, p, /*allow_plain=*/false);
+    if (rc != CC_OK) return rc;
+    // Giant filter: as asked, or (auto) for dense lists that span several chunks.
+    const int32_t fopt = opts ? opts->filter : CC_FILTER_AUTO;
+    const bool filter = fopt == CC_FILTER_GIANT ||
+                        (fopt == CC_FILTER_AUTO && m >= 8 * (int64_t)n && m > chunk);
+    if (st) {
+        std::memset(st, 0, sizeof *st);
+        st->hook = CC_HOOK_ATOMIC;
+        st->giant_label = -1;
+    }
+    if (n == 0) {
+        if (m > 0) return fail(CC_ERR_RANGE, "edge endpoint outside [0, n) (n == 0)");
+        return CC_OK;
+    }
+    const int64_t chunks = std::max<int64_t>(1, (m + chunk - 1) / chunk);
+    const size_t bits_bytes = filter ? align256(((size_t)n + 31) / 32 * 4) : 0;
+    const size_t stage = align256((size_t)chunk * 4);
+    const size_t total = 256 + bits_bytes + 4 * stage;
+    PoolEntry* pe = pool_entry(s);
+    std::lock_guard<std::mutex> lk(pe->mu);
+    rc = ensure_host(pe);
+    if (rc != CC_OK) return rc;
+    rc = ensure_dev(pe, total);
+    if (rc != CC_OK) return rc;
+    if (!pe->copy_stream) HIPCHK(hipStreamCreateWithFlags(&pe->copy_stream, hipStreamNonBlocking));
+    for (int i = 0; i < 2; ++i) {
+        if (!pe->copied[i]) HIPCHK(hipEventCreateWithFlags(&pe->copied[i], hipEventDisableTiming));
+        if (!pe->consumed[i]) HIPCHK(hipEventCreateWithFlags(&pe->consumed[i], hipEventDisableTiming));
+    }
+    char* ws = static_cast<char*>(pe->dev);
+    Ctrl* ctrl = reinterpret_cast<Ctrl*>(ws);
+    uint32_t* bits = filter ? reinterpret_cast<uint32_t*>(ws + 256) : nullptr;
+    int32_t* su[2] = {reinterpret_cast<int32_t*>(ws + 256 + bits_bytes),
+                      reinterpret_cast<int32_t*>(ws + 256 + bits_bytes + stage)};
+    int32_t* sv[2] = {reinterpret_cast<int32_t*>(ws + 256 + bits_bytes + 2 * stage),
+                      reinterpret_cast<int32_t*>(ws + 256 + bits_bytes + 3 * stage)};
+    hipStream_t cs = pe->copy_stream;
+    HIPCHK(launch_init(out, n, ctrl, s));
+    // The copy stream must not overwrite a staging buffer before the solve
+    // stream is done with it, nor start before init is queued (ordering only).
+    HIPCHK(hipEventRecord(pe->consumed[0], s));
+    HIPCHK(hipEventRecord(pe->consumed[1], s));
+    int hooks = 0, jumps = 0;
+    for (int64_t i = 0; i < chunks; ++i) {
+        const int b = (int)(i & 1);
+        const int64_t e0 = i * chunk, len = std::min<int64_t>(chunk, m - e0);
+        HIPCHK(hipStreamWaitEvent(cs, pe->consumed[b], 0));
+        if (len > 0) {
+            HIPCHK(hipMemcpyAsync(su[b], hu + e0, (size_t)len * 4, hipMemcpyHostToDevice, cs));
+            HIPCHK(hipMemcpyAsync(sv[b], hv + e0, (size_t)len * 4, hipMemcpyHostToDevice, cs));
+        }
+        HIPCHK(hipEventRecord(pe->copied[b], cs));
+        HIPCHK(hipStreamWaitEvent(s, pe->copied[b], 0));
+        const bool filtered = filter && i > 0;
+        HIPCHK(launch_ahook(su[b], sv[b], 0, len, out, n, ctrl, filtered ? bits : nullptr, p.block,
+                            p.ept, p.coherent, p.halve, s));
+        HIPCHK(launch_mj(out, n, nullptr, p.coherent, s));
+        ++hooks;
+        ++jumps;
+        if (filter && i == 0) HIPCHK(launch_sample_giant(su[b], len, out, n, ctrl, 2048, s));
+        if (filter && i + 1 < chunks) HIPCHK(launch_bitmap(out, n, ctrl, bits, s));
+        HIPCHK(hipEventRecord(pe->consumed[b], s));
+    }
+    rc = finish(s, ctrl, pe->host_ctrl, st);
+    if (rc != CC_OK) return rc;
+    if (st) {
+        st->segments = (int32_t)chunks;
+        st->hook_launches = hooks;
+        st->compress_launches = jumps;
+        st->filter_used = (filter && pe->host_ctrl->filter_on) ? 1 : 0;
+        st->giant_label = st->filter_used ? pe->host_ctrl->giant : -1;
+    }
+    if (pe->host_ctrl->status & kStatusRange) return fail(CC_ERR_RANGE, "edge endpoint outside [0, n)");
+    return CC_OK;
+}
+
 size_t workspace_bytes_impl(int32_t n, int64_t m, const cc_options* opts) {
     if (n < 0 || m < 0) return 0;
     Plan p;
@@ -745,6 +845,13 @@ void release_impl() {
     for (auto& kv : g_pool) {
         PoolEntry* e = kv.second.get();
         std::lock_guard<std::mutex> lk(e->mu);
+        for (int i = 0; i < 2; ++i) {
+            if (e->copied[i]) (void)hipEventDestroy(e->copied[i]);
+            if (e->consumed[i]) (void)hipEventDestroy(e->consumed[i]);
+            e->copied[i] = e->consumed[i] = nullptr;
+        }
+        if (e->copy_stream) (void)hipStreamDestroy(e->copy_stream);
+        e->copy_stream = nullptr;
         if (e->dev) (void)hipFree(e->dev);
         if (e->host_ctrl) (void)hipHostFree(e->host_ctrl);
         if (e->host_stage) (void)hipHostFree(e->host_stage);

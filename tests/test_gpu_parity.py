@@ -343,3 +343,37 @@ def test_full_size_batch_matches_oracle_digest(dev):
     say("full size batch10k")
     lab = cc.labels_batch(to_dev(u, dev), to_dev(v, dev), vo, eo).cpu().numpy()
     assert digest(lab) == rec["sha256"]
+
+
+# ----------------------------------------------------------------------------- streamed (host edges)
+@pytest.mark.parametrize("filt", ["auto", "off", "giant"])
+def test_streamed_host_edges_match_oracle(dev, filt):
+    """Edges stay in host memory (pinned and pageable) and are streamed in
+    chunks; ragged last chunk; labels equal the oracle's."""
+    cases = [graphgen.rmat(16, 16, seed=41, symmetrize=True),
+             graphgen.grid(300, 200, 3, 10, seed=42),
+             graphgen.er_planted(n=1 << 14, m_er=1 << 16, cliques=32, seed=43)[:3]]
+    for u, v, n in cases:
+        want = oracle.labels(u, v, n)
+        for chunk in (4, 1000, 65537, len(u) + 8):
+            say("streamed", filt, n, len(u), chunk)
+            got = cc.labels_host(u, v, n, chunk=chunk, options=cc.Options(filter=filt)).cpu().numpy()
+            assert np.array_equal(got, want), (n, chunk, filt)
+        pu = torch.from_numpy(u).pin_memory()
+        pv = torch.from_numpy(v).pin_memory()
+        got, st = cc.labels_host(pu, pv, n, chunk=1 << 15, options=cc.Options(filter=filt),
+                                 return_stats=True)
+        assert np.array_equal(got.cpu().numpy(), want)
+        assert st["segments"] == (len(u) + (1 << 15) - 1) // (1 << 15)
+
+
+def test_streamed_range_error_and_full_size(dev):
+    with pytest.raises(cc.CCError) as ei:
+        cc.labels_host(np.array([0, 7], np.int32), np.array([1, 2], np.int32), 5, chunk=4)
+    assert ei.value.code == cc.CC_ERR_RANGE
+    rec = _golden()["grid4k"]
+    u, v, n = graphgen.workload("grid4k")
+    pu = torch.from_numpy(u).pin_memory()
+    pv = torch.from_numpy(v).pin_memory()
+    lab = cc.labels_host(pu, pv, n, chunk=1 << 22).cpu().numpy()
+    assert digest(lab) == rec["sha256"]

@@ -55,6 +55,8 @@ def main():
     ap.add_argument("--profile-steps", type=int, default=3)
     ap.add_argument("--coherent", action="store_true", help="agent-scope tree loads (A/B only)")
     ap.add_argument("--hot", default="auto", choices=["auto", "on", "off", "large"])
+    ap.add_argument("--symmetric", action="store_true",
+                    help="flagged option: hook only u <= v of a symmetrised list (not the headline)")
     ap.add_argument("--skip-cpu", action="store_true")
     ap.add_argument("--skip-batch", action="store_true")
     ap.add_argument("--mode", default="solve", choices=["solve", "ablation", "serving", "tune"],
@@ -101,7 +103,7 @@ def main():
         return
     opts = cc.Options(hook=args.hook, filter=args.filter, segments=args.segments,
                       edges_per_thread=args.ept, block=args.block, coherent_loads=args.coherent,
-                      hot_cache=args.hot)
+                      hot_cache=args.hot, symmetric=args.symmetric)
 
     log("generating", args.workload)
     t = time.time()
@@ -149,7 +151,7 @@ def main():
         alg_bytes = 8.0 * m  # each int32 (u, v) entry read once across the Atomic-Hook launches
         kernel = "k_ahook + k_ahook_hot (all Atomic-Hook launches of one solve)"
         if args.hook == "auto" and args.filter == "auto" and args.hot == "auto" and not (
-                args.segments or args.ept or args.block or args.coherent):
+                args.segments or args.ept or args.block or args.coherent or args.symmetric):
             traffic = measured_traffic(args.workload, "atomic")
     else:
         alg_bytes = 8.0 * m  # first Hook pass over the input entries
@@ -173,6 +175,7 @@ def main():
         "dtype": "int32",
         "data": "synthetic (seeded generator, no dataset)",
         "config": {"workload": args.workload, "n": n, "m_entries": m,
+                   "symmetric_flag": bool(args.symmetric),
                    "hook": {1: "atomic", 2: "plain"}.get(st.get("hook"), args.hook),
                    "filter": args.filter,
                    "segments": st["segments"] if st else None,

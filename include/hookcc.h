@@ -112,7 +112,13 @@ typedef struct cc_options {
     int32_t path_halving;     /* Atomic-Hook climb: CC_HALVE_AUTO (default, on), CC_HALVE_ON
                                  or CC_HALVE_OFF (Fig. 3 exactly) -- re-point each non-root
                                  passed on the way up at its grandparent                  */
-    int32_t reserved[3];      /* must be zero                                           */
+    int32_t symmetric;        /* 1 = the caller guarantees that every pair (u, v) of the list
+                                 also appears as (v, u) (a symmetrised list); the Atomic-Hook
+                                 then skips the entries with u > v, which changes nothing in
+                                 the result for such lists and halves the tree accesses.
+                                 Wrong labels if the guarantee does not hold.  Never on by
+                                 default; with CC_HOOK_AUTO it forces the Atomic-Hook.    */
+    int32_t reserved[2];      /* must be zero                                           */
 } cc_options;
 
 #define CC_HOT_AUTO 0

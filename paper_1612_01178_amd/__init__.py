@@ -57,7 +57,8 @@ class _COptions(ctypes.Structure):
                 ("max_rounds", ctypes.c_int32), ("rounds_per_check", ctypes.c_int32),
                 ("profile", ctypes.c_int32), ("host_loop", ctypes.c_int32),
                 ("coherent_loads", ctypes.c_int32), ("hot_cache", ctypes.c_int32),
-                ("path_halving", ctypes.c_int32), ("reserved", ctypes.c_int32 * 3)]
+                ("path_halving", ctypes.c_int32), ("symmetric", ctypes.c_int32),
+                ("reserved", ctypes.c_int32 * 2)]
 
 
 class _CStats(ctypes.Structure):
@@ -105,6 +106,7 @@ class Options:
     coherent_loads: bool = False
     hot_cache: str = "auto"
     path_halving: str = "auto"
+    symmetric: bool = False
 
     def _c(self) -> _COptions:
         o = _COptions()
@@ -121,6 +123,7 @@ class Options:
         o.coherent_loads = 1 if self.coherent_loads else 0
         o.hot_cache = {"auto": 0, "on": 1, "off": 2, "large": 3}[self.hot_cache]
         o.path_halving = {"auto": 0, "on": 1, "off": 2}[self.path_halving]
+        o.symmetric = 1 if self.symmetric else 0
         return o
 
 

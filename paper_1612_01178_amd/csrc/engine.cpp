@@ -60,6 +60,7 @@ struct Plan {
     bool hot = false;  // hot-word LDS cache of the giant bitmap
     int hot_slots = 32768;
     bool halve = true;  // path halving in the Atomic-Hook climb
+    bool symmetric = false;  // caller promises both orientations of every pair
 };
 
 int32_t make_plan(int32_t n, int64_t m, const cc_options* o, Plan& p, bool allow_plain = true) {
@@ -67,8 +68,11 @@ int32_t make_plan(int32_t n, int64_t m, const cc_options* o, Plan& p, bool allow
     std::memset(&d, 0, sizeof d);
     d.filter = CC_FILTER_AUTO;
     const cc_options& op = o ? *o : d;
-    for (int i = 0; i < 3; ++i)
+    for (int i = 0; i < 2; ++i)
         if (op.reserved[i] != 0) return fail(CC_ERR_ARG, "cc_options.reserved must be zero");
+    if (op.symmetric != 0 && op.symmetric != 1)
+        return fail(CC_ERR_ARG, "cc_options.symmetric must be 0 or 1");
+    p.symmetric = op.symmetric == 1;
     if (op.hot_cache < CC_HOT_AUTO || op.hot_cache > CC_HOT_LARGE)
         return fail(CC_ERR_ARG, "unknown cc_options.hot_cache");
     p.hot_slots = op.hot_cache == CC_HOT_ON ? 16384 : 32768;
@@ -94,7 +98,7 @@ int32_t make_plan(int32_t n, int64_t m, const cc_options* o, Plan& p, bool allow
     const bool dense_large = large && n > 0 && m >= 8 * (int64_t)n;
     bool auto_filtered = false;
     if (op.hook == CC_HOOK_AUTO) {
-        if (large || !allow_plain) {
+        if (large || !allow_plain || op.symmetric == 1) {
             p.hook = CC_HOOK_ATOMIC;
             auto_filtered = dense_large && op.filter != CC_FILTER_OFF;
         } else {
@@ -149,6 +153,8 @@ int32_t make_plan(int32_t n, int64_t m, const cc_options* o, Plan& p, bool allow
     if (op.host_loop != CC_HOST_LOOP_OFF && op.hook != CC_HOOK_PLAIN)
         return fail(CC_ERR_ARG, "cc_options.host_loop needs hook = CC_HOOK_PLAIN");
     p.host_loop = op.host_loop;
+    if (p.symmetric && p.hook != CC_HOOK_ATOMIC)
+        return fail(CC_ERR_ARG, "cc_options.symmetric needs the Atomic-Hook");
     if (p.hook == CC_HOOK_PLAIN && m >= (int64_t(1) << 32))
         return fail(CC_ERR_ARG, "atomic-free Hook supports m < 2^32 entries");
     return CC_OK;
@@ -348,7 +354,7 @@ int32_t enqueue_atomic(int32_t n, const int32_t* u, const int32_t* v, int64_t m,
         // Fig. 4: for each segment, Atomic-Hook the segment, then Multi-Jump all of V.
         for (int i = 0; i < S; ++i) {
             TIMED(kPhaseHook, launch_ahook(u, v, bound(i), bound(i + 1), pi, n, ctrl, nullptr,
-                                           p.block, p.ept, p.coherent, p.halve, s));
+                                           p.block, p.ept, p.coherent, p.halve, p.symmetric, s));
             TIMED(kPhaseCompress, launch_mj(pi, n, nullptr, p.coherent, s));
             ++hooks;
             ++jumps;
@@ -357,7 +363,7 @@ int32_t enqueue_atomic(int32_t n, const int32_t* u, const int32_t* v, int64_t m,
         const int fa = p.filter_after;
         for (int i = 0; i < fa; ++i) {
             TIMED(kPhaseHook, launch_ahook(u, v, bound(i), bound(i + 1), pi, n, ctrl, nullptr,
-                                           p.block, p.ept, p.coherent, p.halve, s));
+                                           p.block, p.ept, p.coherent, p.halve, p.symmetric, s));
             TIMED(kPhaseCompress, launch_mj(pi, n, nullptr, p.coherent, s));
             ++hooks;
             ++jumps;
@@ -378,10 +384,10 @@ int32_t enqueue_atomic(int32_t n, const int32_t* u, const int32_t* v, int64_t m,
             if (hot)
                 TIMED(kPhaseHook, launch_ahook_hot(u, v, bound(g), bound(h), pi, n, ctrl, bits,
                                                    fb.hot_tags, fb.hot_vals, p.ept, p.hot_slots,
-                                                   p.halve, s));
+                                                   p.halve, p.symmetric, s));
             else
                 TIMED(kPhaseHook, launch_ahook(u, v, bound(g), bound(h), pi, n, ctrl, bits,
-                                               p.block, p.ept, p.coherent, p.halve, s));
+                                               p.block, p.ept, p.coherent, p.halve, p.symmetric, s));
             TIMED(kPhaseCompress, launch_mj(pi, n, nullptr, p.coherent, s));
             ++hooks;
             ++jumps;
@@ -649,7 +655,7 @@ int32_t stream_impl(int32_t n, const int32_t* hu, const int32_t* hv, int64_t m, 
         HIPCHK(hipStreamWaitEvent(s, pe->copied[b], 0));
         const bool filtered = filter && i > 0;
         HIPCHK(launch_ahook(su[b], sv[b], 0, len, out, n, ctrl, filtered ? bits : nullptr, p.block,
-                            p.ept, p.coherent, p.halve, s));
+                            p.ept, p.coherent, p.halve, p.symmetric, s));
         HIPCHK(launch_mj(out, n, nullptr, p.coherent, s));
         ++hooks;
         ++jumps;

@@ -10,10 +10,11 @@ hipError_t launch_init(int32_t* pi, int32_t n, Ctrl* ctrl, hipStream_t s);
 
 // Atomic-Hook (Fig. 3) of entries [begin, end).  When `bits` is non-null the
 // giant-component filter is applied (only if ctrl->filter_on is set);
-// `halve` adds path halving to the climb.
+// `halve` adds path halving to the climb; `sym` hooks only entries with
+// u <= v (valid when every pair is present in both orientations).
 hipError_t launch_ahook(const int32_t* u, const int32_t* v, int64_t begin, int64_t end,
                         int32_t* pi, int32_t n, Ctrl* ctrl, const uint32_t* bits, int block,
-                        int ept, bool coherent, bool halve, hipStream_t s);
+                        int ept, bool coherent, bool halve, bool sym, hipStream_t s);
 
 // Multi-Jump (Fig. 3) over all n vertices.  When `gate` is non-null the
 // kernel does nothing if *gate == 0.  `coherent` selects agent-scope tree
@@ -68,7 +69,7 @@ hipError_t launch_hot_values(const uint32_t* bits, const uint32_t* tags, uint32_
 hipError_t launch_ahook_hot(const int32_t* u, const int32_t* v, int64_t begin, int64_t end,
                             int32_t* pi, int32_t n, Ctrl* ctrl, const uint32_t* bits,
                             const uint32_t* tags, const uint32_t* vals, int ept, int slots,
-                            bool halve, hipStream_t s);
+                            bool halve, bool sym, hipStream_t s);
 
 // Streaming and gather probes used to measure the memory ceilings.
 hipError_t launch_probe_stream(const int32_t* u, const int32_t* v, int64_t m, uint32_t* sink,

@@ -129,7 +129,7 @@ template <int EPT, bool VEC, bool FILTER, bool COH, bool HALVE>
 __global__ __launch_bounds__(1024) void k_ahook(const int32_t* __restrict__ eu,
                                                 const int32_t* __restrict__ ev, int64_t begin,
                                                 int64_t end, int32_t* pi, int32_t n, Ctrl* ctrl,
-                                                const uint32_t* __restrict__ bits) {
+                                                const uint32_t* __restrict__ bits, bool sym) {
     const int64_t stride = (int64_t)blockDim.x * 4;
     const int64_t e0 = begin + (int64_t)blockIdx.x * blockDim.x * EPT + (int64_t)threadIdx.x * 4;
     int32_t a[EPT], b[EPT];
@@ -142,7 +142,8 @@ __global__ __launch_bounds__(1024) void k_ahook(const int32_t* __restrict__ eu,
     for (int j = 0; j < EPT; ++j) {
         const bool in = (uint32_t)a[j] < (uint32_t)n && (uint32_t)b[j] < (uint32_t)n;
         bad |= !in;
-        if (in && a[j] != b[j]) act |= 1u << j;
+        // sym: the caller's list holds every pair in both orientations; hook one
+        if (in && a[j] != b[j] && !(sym && a[j] > b[j])) act |= 1u << j;
     }
     if (bad) atomicOr(&ctrl->status, kStatusRange);
 
@@ -179,27 +180,28 @@ __global__ __launch_bounds__(1024) void k_ahook(const int32_t* __restrict__ eu,
 template <int EPT, bool FILTER, bool COH>
 static void ahook_dispatch(bool vec, bool halve, int grid, int block, hipStream_t s,
                            const int32_t* u, const int32_t* v, int64_t begin, int64_t end,
-                           int32_t* pi, int32_t n, Ctrl* ctrl, const uint32_t* bits) {
+                           int32_t* pi, int32_t n, Ctrl* ctrl, const uint32_t* bits, bool sym) {
     if (vec && halve)
-        k_ahook<EPT, true, FILTER, COH, true><<<grid, block, 0, s>>>(u, v, begin, end, pi, n, ctrl, bits);
+        k_ahook<EPT, true, FILTER, COH, true><<<grid, block, 0, s>>>(u, v, begin, end, pi, n, ctrl, bits, sym);
     else if (vec)
-        k_ahook<EPT, true, FILTER, COH, false><<<grid, block, 0, s>>>(u, v, begin, end, pi, n, ctrl, bits);
+        k_ahook<EPT, true, FILTER, COH, false><<<grid, block, 0, s>>>(u, v, begin, end, pi, n, ctrl, bits, sym);
     else if (halve)
-        k_ahook<EPT, false, FILTER, COH, true><<<grid, block, 0, s>>>(u, v, begin, end, pi, n, ctrl, bits);
+        k_ahook<EPT, false, FILTER, COH, true><<<grid, block, 0, s>>>(u, v, begin, end, pi, n, ctrl, bits, sym);
     else
-        k_ahook<EPT, false, FILTER, COH, false><<<grid, block, 0, s>>>(u, v, begin, end, pi, n, ctrl, bits);
+        k_ahook<EPT, false, FILTER, COH, false><<<grid, block, 0, s>>>(u, v, begin, end, pi, n, ctrl, bits, sym);
 }
 
 template <int EPT>
 static void ahook_dispatch2(bool vec, bool filter, bool coh, bool halve, int grid, int block,
                             hipStream_t s, const int32_t* u, const int32_t* v, int64_t begin,
-                            int64_t end, int32_t* pi, int32_t n, Ctrl* ctrl, const uint32_t* bits) {
+                            int64_t end, int32_t* pi, int32_t n, Ctrl* ctrl, const uint32_t* bits,
+                            bool sym) {
     if (filter) {
-        if (coh) ahook_dispatch<EPT, true, true>(vec, halve, grid, block, s, u, v, begin, end, pi, n, ctrl, bits);
-        else ahook_dispatch<EPT, true, false>(vec, halve, grid, block, s, u, v, begin, end, pi, n, ctrl, bits);
+        if (coh) ahook_dispatch<EPT, true, true>(vec, halve, grid, block, s, u, v, begin, end, pi, n, ctrl, bits, sym);
+        else ahook_dispatch<EPT, true, false>(vec, halve, grid, block, s, u, v, begin, end, pi, n, ctrl, bits, sym);
     } else {
-        if (coh) ahook_dispatch<EPT, false, true>(vec, halve, grid, block, s, u, v, begin, end, pi, n, ctrl, bits);
-        else ahook_dispatch<EPT, false, false>(vec, halve, grid, block, s, u, v, begin, end, pi, n, ctrl, bits);
+        if (coh) ahook_dispatch<EPT, false, true>(vec, halve, grid, block, s, u, v, begin, end, pi, n, ctrl, bits, sym);
+        else ahook_dispatch<EPT, false, false>(vec, halve, grid, block, s, u, v, begin, end, pi, n, ctrl, bits, sym);
     }
 }
 
@@ -207,7 +209,7 @@ static bool aligned16(const void* p) { return ((uintptr_t)p & 15) == 0; }
 
 hipError_t launch_ahook(const int32_t* u, const int32_t* v, int64_t begin, int64_t end,
                         int32_t* pi, int32_t n, Ctrl* ctrl, const uint32_t* bits, int block,
-                        int ept, bool coherent, bool halve, hipStream_t s) {
+                        int ept, bool coherent, bool halve, bool sym, hipStream_t s) {
     if (end <= begin) return hipSuccess;
     const int64_t tile = (int64_t)block * ept;
     const int64_t grid64 = (end - begin + tile - 1) / tile;
@@ -216,9 +218,9 @@ hipError_t launch_ahook(const int32_t* u, const int32_t* v, int64_t begin, int64
     const bool vec = aligned16(u + begin) && aligned16(v + begin);
     const bool f = bits != nullptr;
     switch (ept) {
-        case 4: ahook_dispatch2<4>(vec, f, coherent, halve, grid, block, s, u, v, begin, end, pi, n, ctrl, bits); break;
-        case 8: ahook_dispatch2<8>(vec, f, coherent, halve, grid, block, s, u, v, begin, end, pi, n, ctrl, bits); break;
-        case 16: ahook_dispatch2<16>(vec, f, coherent, halve, grid, block, s, u, v, begin, end, pi, n, ctrl, bits); break;
+        case 4: ahook_dispatch2<4>(vec, f, coherent, halve, grid, block, s, u, v, begin, end, pi, n, ctrl, bits, sym); break;
+        case 8: ahook_dispatch2<8>(vec, f, coherent, halve, grid, block, s, u, v, begin, end, pi, n, ctrl, bits, sym); break;
+        case 16: ahook_dispatch2<16>(vec, f, coherent, halve, grid, block, s, u, v, begin, end, pi, n, ctrl, bits, sym); break;
         default: return hipErrorInvalidValue;
     }
     return hipGetLastError();

@@ -116,7 +116,8 @@ __global__ __launch_bounds__(1024) void k_ahook_hot(const int32_t* __restrict__ 
                                                     int64_t end, bool vec, int32_t* pi, int32_t n,
                                                     Ctrl* ctrl, const uint32_t* __restrict__ bits,
                                                     const uint32_t* __restrict__ gtags,
-                                                    const uint32_t* __restrict__ gvals, bool halve) {
+                                                    const uint32_t* __restrict__ gvals, bool halve,
+                                                    bool sym) {
     constexpr uint32_t kEmpty = (uint32_t)(TagT)(~(TagT)0);
     __shared__ TagT ltag[SLOTS];
     __shared__ uint32_t lval[SLOTS];
@@ -143,7 +144,7 @@ __global__ __launch_bounds__(1024) void k_ahook_hot(const int32_t* __restrict__ 
         for (int j = 0; j < EPT; ++j) {
             const bool in = (uint32_t)a[j] < (uint32_t)n && (uint32_t)b[j] < (uint32_t)n;
             bad |= !in;
-            if (in && a[j] != b[j]) act |= 1u << j;
+            if (in && a[j] != b[j] && !(sym && a[j] > b[j])) act |= 1u << j;
         }
         int32_t pa[EPT], pb[EPT];
 #pragma unroll
@@ -196,11 +197,11 @@ template <int SLOTS, typename TagT>
 static hipError_t ahook_hot_ept(int ept, int grid, int block, hipStream_t s, const int32_t* u,
                                 const int32_t* v, int64_t begin, int64_t end, bool vec, int32_t* pi,
                                 int32_t n, Ctrl* ctrl, const uint32_t* bits, const uint32_t* tags,
-                                const uint32_t* vals, bool halve) {
+                                const uint32_t* vals, bool halve, bool sym) {
     switch (ept) {
-        case 4: k_ahook_hot<4, SLOTS, TagT><<<grid, block, 0, s>>>(u, v, begin, end, vec, pi, n, ctrl, bits, tags, vals, halve); break;
-        case 8: k_ahook_hot<8, SLOTS, TagT><<<grid, block, 0, s>>>(u, v, begin, end, vec, pi, n, ctrl, bits, tags, vals, halve); break;
-        case 16: k_ahook_hot<16, SLOTS, TagT><<<grid, block, 0, s>>>(u, v, begin, end, vec, pi, n, ctrl, bits, tags, vals, halve); break;
+        case 4: k_ahook_hot<4, SLOTS, TagT><<<grid, block, 0, s>>>(u, v, begin, end, vec, pi, n, ctrl, bits, tags, vals, halve, sym); break;
+        case 8: k_ahook_hot<8, SLOTS, TagT><<<grid, block, 0, s>>>(u, v, begin, end, vec, pi, n, ctrl, bits, tags, vals, halve, sym); break;
+        case 16: k_ahook_hot<16, SLOTS, TagT><<<grid, block, 0, s>>>(u, v, begin, end, vec, pi, n, ctrl, bits, tags, vals, halve, sym); break;
         default: return hipErrorInvalidValue;
     }
     return hipGetLastError();
@@ -209,7 +210,7 @@ static hipError_t ahook_hot_ept(int ept, int grid, int block, hipStream_t s, con
 hipError_t launch_ahook_hot(const int32_t* u, const int32_t* v, int64_t begin, int64_t end,
                             int32_t* pi, int32_t n, Ctrl* ctrl, const uint32_t* bits,
                             const uint32_t* tags, const uint32_t* vals, int ept, int slots,
-                            bool halve, hipStream_t s) {
+                            bool halve, bool sym, hipStream_t s) {
     if (end <= begin) return hipSuccess;
     const int block = 1024;
     const int64_t tile = (int64_t)block * ept;
@@ -219,10 +220,10 @@ hipError_t launch_ahook_hot(const int32_t* u, const int32_t* v, int64_t begin, i
     const bool vec = (((uintptr_t)(u + begin) | (uintptr_t)(v + begin)) & 15) == 0;
     if (slots == 16384)
         return ahook_hot_ept<16384, uint16_t>(ept, grid, block, s, u, v, begin, end, vec, pi, n,
-                                              ctrl, bits, tags, vals, halve);
+                                              ctrl, bits, tags, vals, halve, sym);
     if (slots == 32768)
         return ahook_hot_ept<32768, uint8_t>(ept, grid, block, s, u, v, begin, end, vec, pi, n,
-                                             ctrl, bits, tags, vals, halve);
+                                             ctrl, bits, tags, vals, halve, sym);
     return hipErrorInvalidValue;
 }
 

@@ -377,3 +377,24 @@ def test_streamed_range_error_and_full_size(dev):
     pv = torch.from_numpy(v).pin_memory()
     lab = cc.labels_host(pu, pv, n, chunk=1 << 22).cpu().numpy()
     assert digest(lab) == rec["sha256"]
+
+
+# ----------------------------------------------------------------------------- symmetric flag
+def test_symmetric_flag_on_symmetrised_lists(dev):
+    """cc_options.symmetric hooks only entries with u <= v; on a list that
+    holds every pair in both orientations the labels are unchanged."""
+    for u, v, n in [graphgen.rmat(16, 8, seed=61, symmetrize=True),
+                    graphgen.rmat(12, 4, seed=62, symmetrize=True)]:
+        want = oracle.labels(u, v, n)
+        for opt in (cc.Options(symmetric=True), cc.Options(symmetric=True, hook="atomic",
+                                                           filter="giant", segments=16),
+                    cc.Options(symmetric=True, hook="atomic", filter="off", segments=3)):
+            assert np.array_equal(solve(u, v, n, dev, opt), want)
+        got = cc.labels_host(u, v, n, chunk=10000, options=cc.Options(symmetric=True))
+        assert np.array_equal(got.cpu().numpy(), want)
+    rec = _golden()["rmat24"]
+    u, v, n = graphgen.workload("rmat24")
+    du, dv = to_dev(u, dev), to_dev(v, dev)
+    del u, v
+    lab = cc.labels(du, dv, n, options=cc.Options(symmetric=True)).cpu().numpy()
+    assert digest(lab) == rec["sha256"]

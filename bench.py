@@ -198,6 +198,7 @@ def main():
 
     if not args.skip_batch:
         result["streamed"] = streamed(cc, torch, u_np, v_np, n, out, args.workload)
+        result["csr"] = csr_leg(cc, torch, u, v, n, out, args.workload)
 
     if not args.skip_cpu:
         import oracle
@@ -283,6 +284,35 @@ def ablation(cc, torch, dev, args, reps=5):
         del u, v, out
         torch.cuda.empty_cache()
     print(json.dumps({"mode": "ablation", "results": results}), flush=True)
+
+
+def csr_leg(cc, torch, u, v, n, out, workload, reps=5):
+    """The same graph as a CSR adjacency (rows sorted; built with torch on the
+    device, untimed): cc_labels_csr, plain and with the flagged symmetric
+    option."""
+    key, order = torch.sort(u.to(torch.int64) * n + v.to(torch.int64))
+    del key
+    col = v[order].contiguous()
+    del order
+    rp = torch.zeros(n + 1, dtype=torch.int64, device=u.device)
+    rp[1:] = torch.cumsum(torch.bincount(u, minlength=n), 0)
+    golden = json.load(open(os.path.join(ROOT, "tests", "golden", "oracle_digests.json")))
+    res = {}
+    m = col.numel()
+    for name, opt in (("csr", cc.Options()), ("csr_symmetric_flag", cc.Options(symmetric=True))):
+        cc.labels_csr(rp, col, n, out=out, options=opt)
+        torch.cuda.synchronize()
+        t = time.perf_counter()
+        for _ in range(reps):
+            cc.labels_csr(rp, col, n, out=out, options=opt)
+        torch.cuda.synchronize()
+        dt = (time.perf_counter() - t) / reps
+        ok = digest(out.cpu().numpy()) == golden.get(workload, {}).get("sha256")
+        res[name] = {"ms_per_solve": dt * 1e3, "edges_per_s": m / dt, "parity_vs_oracle_digest": ok}
+        log("%s: %.3f ms" % (name, dt * 1e3))
+    del rp, col
+    torch.cuda.empty_cache()
+    return res
 
 
 def streamed(cc, torch, u_np, v_np, n, out, workload, reps=3, chunk=1 << 24):

@@ -231,6 +231,22 @@ int32_t cc_labels_host(int32_t n, const int32_t* host_u, const int32_t* host_v, 
                        int32_t* out_label, int64_t chunk_entries, const cc_options* opts,
                        void* stream, cc_stats* stats);
 
+/* CSR adjacency input: entry i of row r is the pair (r, col[i]).  The
+ * Atomic-Hook works on any subsets of E (Fig. 4), so the solve is the same as
+ * for a pair list of m entries; the row of an entry is found on the fly (an
+ * LDS window of row_ptr per tile), and with the giant filter the row's bit is
+ * tested once per group of four consecutive entries.
+ *   row_ptr    [device] int64[n+1]: row_ptr[0] == 0, non-decreasing, row_ptr[n] == m
+ *   col        [device] int32[m], ids in [0, n)
+ *   out_label  [device] int32[n]
+ *   opts       as cc_labels_ex (hook must be CC_HOOK_AUTO or CC_HOOK_ATOMIC);
+ *              opts->symmetric = 1 promises a symmetric adjacency (every pair in
+ *              both rows) and hooks only the entries with col < row
+ * Synchronous on `stream` (NULL = null stream).  A malformed row_ptr or a
+ * column id outside [0, n) returns CC_ERR_RANGE (checked on the device). */
+int32_t cc_labels_csr(int32_t n, const int64_t* row_ptr, const int32_t* col, int64_t m,
+                      int32_t* out_label, const cc_options* opts, void* stream, cc_stats* stats);
+
 /* One graph of a graph list: its own device arrays, local ids in [0, n). */
 typedef struct cc_graph {
     const int32_t* edges_u; /* [device] int32[m]                                          */

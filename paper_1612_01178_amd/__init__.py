@@ -36,7 +36,7 @@ _HOST_LOOPS = {"off": 0, "jump": 1, "multijump": 2}
 
 # Every symbol include/hookcc.h declares.
 EXPORTS = ("cc_options_init", "cc_labels", "cc_labels_ex", "cc_workspace_bytes",
-           "cc_labels_batch", "cc_labels_batch_ex", "cc_labels_list", "cc_labels_host", "cc_probe",
+           "cc_labels_batch", "cc_labels_batch_ex", "cc_labels_list", "cc_labels_host", "cc_labels_csr", "cc_probe",
            "cc_last_error", "cc_release", "cc_version", "cc_server_create",
            "cc_server_submit", "cc_server_wait", "cc_server_poll", "cc_server_stats",
            "cc_server_destroy", "cc_server_clock")
@@ -179,6 +179,9 @@ def load():
             lib.cc_labels_host.argtypes = [_i32, _vp, _vp, _i64, _vp, _i64,
                                            ctypes.POINTER(_COptions), _vp, ctypes.POINTER(_CStats)]
             lib.cc_labels_host.restype = _i32
+            lib.cc_labels_csr.argtypes = [_i32, _vp, _vp, _i64, _vp, ctypes.POINTER(_COptions),
+                                          _vp, ctypes.POINTER(_CStats)]
+            lib.cc_labels_csr.restype = _i32
             lib.cc_probe.argtypes = [_i32, _vp, _vp, _i64, _vp, _i32, _vp]
             lib.cc_probe.restype = _i32
             lib.cc_last_error.argtypes = []
@@ -321,6 +324,29 @@ def labels_host(u, v, n: int, *, chunk: int = 0, out=None, device=None,
         rc = load().cc_labels_host(int(n), up if m else None, vp if m else None, m,
                                    out.data_ptr() if n else None, int(chunk), ctypes.byref(opts),
                                    _stream_handle(stream), ctypes.byref(st))
+    _check(rc)
+    if return_stats:
+        return out, {f: getattr(st, f) for f, _ in _CStats._fields_ if f != "reserved"}
+    return out
+
+
+def labels_csr(row_ptr, col, n: int, *, out=None, options: Options | None = None, stream=None,
+               return_stats: bool = False):
+    """Labels of a graph given as a CSR adjacency: ``row_ptr`` int64 CUDA
+    tensor of n+1 offsets, ``col`` int32 CUDA tensor of m column ids."""
+    import torch
+    col = _edge_tensor(col, "col")
+    if not isinstance(row_ptr, torch.Tensor) or row_ptr.dtype != torch.int64 or \
+            row_ptr.device.type != "cuda" or not row_ptr.is_contiguous() or row_ptr.numel() != n + 1:
+        raise TypeError("row_ptr must be a contiguous int64 CUDA tensor of length n + 1")
+    if out is None:
+        out = torch.empty(max(int(n), 0), dtype=torch.int32, device=col.device)
+    opts = (options or Options())._c()
+    st = _CStats()
+    with torch.cuda.device(col.device):
+        rc = load().cc_labels_csr(int(n), row_ptr.data_ptr(), col.data_ptr() if col.numel() else None,
+                                  col.numel(), out.data_ptr() if n else None, ctypes.byref(opts),
+                                  _stream_handle(stream), ctypes.byref(st))
     _check(rc)
     if return_stats:
         return out, {f: getattr(st, f) for f, _ in _CStats._fields_ if f != "reserved"}

@@ -15,7 +15,7 @@ ROOT = os.path.dirname(HERE)
 CSRC = os.path.join(HERE, "csrc")
 BUILD = os.path.join(ROOT, "_build")
 LIB = os.path.join(HERE, "libhookcc.so")
-SOURCES = ["kernels_core.hip", "kernels_hot.hip", "kernels_batch.hip", "kernels_probe.hip", "engine.cpp", "capi.cpp", "server.cpp"]
+SOURCES = ["kernels_core.hip", "kernels_hot.hip", "kernels_csr.hip", "kernels_batch.hip", "kernels_probe.hip", "engine.cpp", "capi.cpp", "server.cpp"]
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 FLAGS = ["-O3", "-std=c++17", "-fPIC", "--offload-arch=gfx950",
          "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",

@@ -53,6 +53,11 @@ int32_t cc_labels_host(int32_t n, const int32_t* host_u, const int32_t* host_v, 
                        static_cast<hipStream_t>(stream), stats);
 }
 
+int32_t cc_labels_csr(int32_t n, const int64_t* row_ptr, const int32_t* col, int64_t m,
+                      int32_t* out_label, const cc_options* opts, void* stream, cc_stats* stats) {
+    return csr_impl(n, row_ptr, col, m, out_label, opts, static_cast<hipStream_t>(stream), stats);
+}
+
 int32_t cc_probe(int32_t mode, const int32_t* edges_u, const int32_t* edges_v, int64_t m,
                  const void* table, int32_t n, void* stream) {
     return probe_impl(mode, edges_u, edges_v, m, table, n, static_cast<hipStream_t>(stream));

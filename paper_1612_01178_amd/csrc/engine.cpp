@@ -676,6 +676,97 @@ int32_t stream_impl(int32_t n, const int32_t* hu, const int32_t* hv, int64_t m, 
     return CC_OK;
 }
 
+// ---------------------------------------------------------------------- CSR input
+// Same plan as a pair list of m entries (segments of the col[] array, each
+// followed by a Multi-Jump; with the giant filter the doubling super-segments
+// of enqueue_atomic); the first endpoint of an entry is its row.
+int32_t csr_impl(int32_t n, const int64_t* row_ptr, const int32_t* col, int64_t m, int32_t* out,
+                 const cc_options* opts, hipStream_t s, cc_stats* st) {
+    if (n < 0 || m < 0) return fail(CC_ERR_ARG, "n < 0 or m < 0");
+    if (!row_ptr) return fail(CC_ERR_ARG, "null row_ptr");
+    if (m > 0 && !col) return fail(CC_ERR_ARG, "null col with m > 0");
+    if (n > 0 && !out) return fail(CC_ERR_ARG, "null out_label with n > 0");
+    if (opts && opts->hook == CC_HOOK_PLAIN)
+        return fail(CC_ERR_ARG, "CSR input uses the Atomic-Hook");
+    Plan p;
+    int32_t rc = make_plan(n, m, opts, p, /*allow_plain=*/false);
+    if (rc != CC_OK) return rc;
+    if (st) {
+        std::memset(st, 0, sizeof *st);
+        st->hook = CC_HOOK_ATOMIC;
+        st->segments = p.segments;
+        st->giant_label = -1;
+    }
+    if (n == 0) {
+        if (m > 0) return fail(CC_ERR_RANGE, "entries in a graph with no vertices");
+        return CC_OK;
+    }
+    const bool filter = p.filter == CC_FILTER_GIANT;
+    const size_t bits_bytes = filter ? align256(((size_t)n + 31) / 32 * 4) : 0;
+    PoolEntry* pe = pool_entry(s);
+    std::lock_guard<std::mutex> lk(pe->mu);
+    rc = ensure_host(pe);
+    if (rc != CC_OK) return rc;
+    rc = ensure_dev(pe, 256 + bits_bytes);
+    if (rc != CC_OK) return rc;
+    char* ws = static_cast<char*>(pe->dev);
+    Ctrl* ctrl = reinterpret_cast<Ctrl*>(ws);
+    uint32_t* bits = filter ? reinterpret_cast<uint32_t*>(ws + 256) : nullptr;
+    const int S = p.segments;
+    auto bound = [&](int64_t i) -> int64_t { return i >= S ? m : (m * i / S) & ~int64_t(3); };
+    Timer tm;
+    tm.on = p.profile;
+    tm.s = s;
+    int hooks = 0, jumps = 0;
+    TIMED(kPhaseOther, launch_init(out, n, ctrl, s));
+    TIMED(kPhaseOther, launch_csr_check(row_ptr, n, m, ctrl, s));
+    if (!filter) {
+        for (int i = 0; i < S; ++i) {
+            TIMED(kPhaseHook, launch_ahook_csr(row_ptr, col, n, bound(i), bound(i + 1), out, ctrl,
+                                               nullptr, p.symmetric, p.halve, s));
+            TIMED(kPhaseCompress, launch_mj(out, n, nullptr, false, s));
+            ++hooks;
+            ++jumps;
+        }
+    } else {
+        const int fa = p.filter_after;
+        for (int i = 0; i < fa; ++i) {
+            TIMED(kPhaseHook, launch_ahook_csr(row_ptr, col, n, bound(i), bound(i + 1), out, ctrl,
+                                               nullptr, p.symmetric, p.halve, s));
+            TIMED(kPhaseCompress, launch_mj(out, n, nullptr, false, s));
+            ++hooks;
+            ++jumps;
+        }
+        // endpoints sampled from col[] (the second endpoints of the entries)
+        TIMED(kPhaseOther, launch_sample_giant(col, m, out, n, ctrl, 2048, s));
+        TIMED(kPhaseOther, launch_bitmap(out, n, ctrl, bits, s));
+        int64_t g = fa, step = fa;
+        while (g < S) {
+            const int64_t h = std::min<int64_t>(S, g + step);
+            TIMED(kPhaseHook, launch_ahook_csr(row_ptr, col, n, bound(g), bound(h), out, ctrl, bits,
+                                               p.symmetric, p.halve, s));
+            TIMED(kPhaseCompress, launch_mj(out, n, nullptr, false, s));
+            ++hooks;
+            ++jumps;
+            if (h < S) TIMED(kPhaseOther, launch_bitmap(out, n, ctrl, bits, s));
+            g = h;
+            step *= 2;
+        }
+    }
+    rc = finish(s, ctrl, pe->host_ctrl, st);
+    if (rc != CC_OK) return rc;
+    tm.collect(st);
+    if (st) {
+        st->hook_launches = hooks;
+        st->compress_launches = jumps;
+        st->filter_used = (filter && pe->host_ctrl->filter_on) ? 1 : 0;
+        st->giant_label = st->filter_used ? pe->host_ctrl->giant : -1;
+    }
+    if (pe->host_ctrl->status & kStatusRange)
+        return fail(CC_ERR_RANGE, "column id outside [0, n) or malformed row_ptr");
+    return CC_OK;
+}
+
 size_t workspace_bytes_impl(int32_t n, int64_t m, const cc_options* opts) {
     if (n < 0 || m < 0) return 0;
     Plan p;

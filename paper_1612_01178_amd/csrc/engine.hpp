@@ -30,6 +30,10 @@ int32_t batch_impl(int32_t B, const int64_t* vo, const int64_t* eo, const int32_
 int32_t stream_impl(int32_t n, const int32_t* hu, const int32_t* hv, int64_t m, int32_t* out,
                     int64_t chunk, const cc_options* opts, hipStream_t s, cc_stats* st);
 
+// CSR adjacency input (see engine.cpp).
+int32_t csr_impl(int32_t n, const int64_t* row_ptr, const int32_t* col, int64_t m, int32_t* out,
+                 const cc_options* opts, hipStream_t s, cc_stats* st);
+
 int32_t probe_impl(int32_t mode, const int32_t* u, const int32_t* v, int64_t m, const void* table,
                    int32_t n, hipStream_t s);
 void release_impl();

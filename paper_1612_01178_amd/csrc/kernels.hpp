@@ -71,6 +71,17 @@ hipError_t launch_ahook_hot(const int32_t* u, const int32_t* v, int64_t begin, i
                             const uint32_t* tags, const uint32_t* vals, int ept, int slots,
                             bool halve, bool sym, hipStream_t s);
 
+// CSR adjacency (kernels_csr.hip): Atomic-Hook of entries [begin, end) of
+// col[], the first endpoint of entry i being its row; `bits` non-null applies
+// the giant filter; `sym` hooks only col < row.
+hipError_t launch_ahook_csr(const int64_t* row_ptr, const int32_t* col, int32_t n, int64_t begin,
+                            int64_t end, int32_t* pi, Ctrl* ctrl, const uint32_t* bits, bool sym,
+                            bool halve, hipStream_t s);
+// Sets the range bit unless row_ptr[0] == 0, row_ptr[n] == m and row_ptr is
+// non-decreasing.
+hipError_t launch_csr_check(const int64_t* row_ptr, int32_t n, int64_t m, Ctrl* ctrl,
+                            hipStream_t s);
+
 // Streaming and gather probes used to measure the memory ceilings.
 hipError_t launch_probe_stream(const int32_t* u, const int32_t* v, int64_t m, uint32_t* sink,
                                hipStream_t s);

@@ -1,0 +1,181 @@
+// Atomic-Hook over a CSR adjacency (row_ptr[n+1], col[m]): entry i of row r
+// is the pair (r, col[i]).  The paper's hook works on any subsets of E
+// (Fig. 4), so the solve is the same as for pair lists; only the way an
+// entry's first endpoint is found differs.
+//
+// Row ids are expanded on the fly.  Each workgroup takes a tile of
+// consecutive entries, finds the rows spanning it with one binary search
+// per tile end (row_ptr is int64 and non-decreasing), loads that window of
+// row_ptr into LDS, and every thread finds the row of its first entry by a
+// binary search in LDS, advancing linearly for its following entries.  A
+// tile whose window exceeds the LDS budget (many empty rows) searches
+// row_ptr in device memory instead.
+//
+// With the giant filter, the row's bit is tested once per group of four
+// consecutive entries (they nearly always share the row) instead of once
+// per entry: on a skewed CSR graph the per-entry cost drops to one bit test.
+// `sym`: the adjacency is symmetric (every pair stored in both rows), so
+// only the entries with col < row are hooked.
+#include "kernels.hpp"
+
+namespace hookcc {
+
+constexpr int kCsrWindow = 4096;  // rows of row_ptr held in LDS per tile
+
+__device__ __forceinline__ int64_t upper_row(const int64_t* __restrict__ rp, int64_t lo, int64_t hi,
+                                             int64_t e) {
+    // largest r in [lo, hi] with rp[r] <= e (rp[lo] <= e assumed)
+    while (lo < hi) {
+        const int64_t mid = (lo + hi + 1) >> 1;
+        if (rp[mid] <= e) lo = mid;
+        else hi = mid - 1;
+    }
+    return lo;
+}
+
+template <int EPT>
+__global__ __launch_bounds__(256) void k_ahook_csr(const int64_t* __restrict__ row_ptr,
+                                                   const int32_t* __restrict__ col, int32_t n,
+                                                   int64_t begin, int64_t end, int32_t* pi,
+                                                   Ctrl* ctrl, const uint32_t* __restrict__ bits,
+                                                   bool filter, bool sym, bool halve) {
+    __shared__ int64_t win[kCsrWindow + 1];
+    __shared__ int64_t r_lo_sh, r_hi_sh;
+    const int64_t tile = (int64_t)blockDim.x * EPT;
+    const int64_t t0 = begin + (int64_t)blockIdx.x * tile;
+    const int64_t t1 = min(end, t0 + tile);  // exclusive
+    if (threadIdx.x == 0) {
+        r_lo_sh = upper_row(row_ptr, 0, n - 1, t0);
+        r_hi_sh = upper_row(row_ptr, r_lo_sh, n - 1, t1 - 1);
+    }
+    __syncthreads();
+    const int64_t r_lo = r_lo_sh, r_hi = r_hi_sh;
+    const bool in_lds = r_hi - r_lo + 1 <= kCsrWindow;
+    if (in_lds)
+        for (int64_t r = r_lo + threadIdx.x; r <= r_hi + 1; r += blockDim.x) win[r - r_lo] = row_ptr[r];
+    __syncthreads();
+    const bool use_filter = filter && ctrl->filter_on;
+    const int32_t g = use_filter ? ctrl->giant : 0;
+    bool bad = false;
+#pragma unroll
+    for (int k = 0; k < EPT / 4; ++k) {
+        const int64_t e0 = t0 + (int64_t)k * blockDim.x * 4 + (int64_t)threadIdx.x * 4;
+        if (e0 >= t1) continue;
+        // row of e0, then of the next three entries
+        int64_t r;
+        if (in_lds) {
+            int64_t lo = 0, hi = r_hi - r_lo;
+            while (lo < hi) {
+                const int64_t mid = (lo + hi + 1) >> 1;
+                if (win[mid] <= e0) lo = mid;
+                else hi = mid - 1;
+            }
+            r = r_lo + lo;
+        } else {
+            r = upper_row(row_ptr, r_lo, r_hi, e0);
+        }
+        int32_t a[4], b[4];
+        uint32_t act = 0;
+#pragma unroll
+        for (int j = 0; j < 4; ++j) {
+            const int64_t e = e0 + j;
+            if (e >= t1) {
+                a[j] = b[j] = 0;
+                continue;
+            }
+            // advance to the row that owns e (rows may be empty)
+            // (stays inside the window even if row_ptr is malformed)
+            while (r < (in_lds ? r_hi : (int64_t)n - 1) &&
+                   (in_lds ? win[r + 1 - r_lo] : row_ptr[r + 1]) <= e)
+                ++r;
+            a[j] = (int32_t)r;
+            b[j] = __builtin_nontemporal_load(col + e);
+            const bool in = (uint32_t)b[j] < (uint32_t)n;
+            bad |= !in;
+            if (in && a[j] != b[j] && !(sym && b[j] > a[j])) act |= 1u << j;
+        }
+        if (!act) continue;
+        int32_t pa[4], pb[4];
+        uint32_t inga = 0, ingb = 0;
+        if (use_filter) {
+            // the row's bit once per group (the group spans at most a few rows)
+            const uint32_t ra = (uint32_t)a[0];
+            const uint32_t ba0 = bits[ra >> 5] >> (ra & 31) & 1;
+            uint32_t wb[4];
+#pragma unroll
+            for (int j = 0; j < 4; ++j) wb[j] = bits[(act >> j & 1) ? ((uint32_t)b[j] >> 5) : 0u];
+#pragma unroll
+            for (int j = 0; j < 4; ++j) {
+                const uint32_t x = (uint32_t)a[j];
+                const uint32_t bax = (x == ra) ? ba0 : (bits[x >> 5] >> (x & 31) & 1);
+                inga |= bax << j;
+                ingb |= (wb[j] >> ((uint32_t)b[j] & 31) & 1u) << j;
+            }
+            act &= ~(inga & ingb);
+        }
+#pragma unroll
+        for (int j = 0; j < 4; ++j) {
+            const bool na = (act >> j & 1) && !(inga >> j & 1);
+            const bool nb = (act >> j & 1) && !(ingb >> j & 1);
+            const int32_t xa = ld_tree<false>(pi + (na ? a[j] : 0));
+            const int32_t xb = ld_tree<false>(pi + (nb ? b[j] : 0));
+            pa[j] = na ? xa : g;
+            pb[j] = nb ? xb : g;
+        }
+#pragma unroll
+        for (int j = 0; j < 4; ++j) {
+            if (!(act >> j & 1)) continue;
+            int32_t pu = pa[j], pv = pb[j];
+            // Atomic-Hook climb (Fig. 3, top) with optional path halving; see
+            // atomic_hook in kernels_core.hip for why it is correct and finite.
+            while (pu != pv) {
+                const int32_t H = pu > pv ? pu : pv;
+                const int32_t L = pu > pv ? pv : pu;
+                int32_t found = ld_tree<false>(pi + H);
+                if (found == H) {
+                    found = cas_root(pi + H, H, L);
+                    if (found == H) break;
+                }
+                pu = ld_tree<false>(pi + found);
+                pv = ld_tree<false>(pi + L);
+                if (halve && pu != found) st_tree<false>(pi + H, pu);
+            }
+        }
+    }
+    if (bad) atomicOr(&ctrl->status, kStatusRange);
+}
+
+// Entry-count check of a CSR adjacency: status bit kStatusRange when
+// row_ptr is not non-decreasing from 0 to m (done on the device, one pass).
+__global__ __launch_bounds__(256) void k_csr_check(const int64_t* __restrict__ row_ptr, int32_t n,
+                                                   int64_t m, Ctrl* ctrl) {
+    const int64_t r = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (r > n) return;
+    bool bad = false;
+    if (r == 0) bad = row_ptr[0] != 0;
+    if (r == n) bad = row_ptr[n] != m;
+    if (r < n) bad = bad || row_ptr[r + 1] < row_ptr[r];
+    if (bad) atomicOr(&ctrl->status, kStatusRange);
+}
+
+hipError_t launch_csr_check(const int64_t* row_ptr, int32_t n, int64_t m, Ctrl* ctrl,
+                            hipStream_t s) {
+    const int grid = (int)(((int64_t)n + 1 + 255) / 256);
+    k_csr_check<<<grid, 256, 0, s>>>(row_ptr, n, m, ctrl);
+    return hipGetLastError();
+}
+
+hipError_t launch_ahook_csr(const int64_t* row_ptr, const int32_t* col, int32_t n, int64_t begin,
+                            int64_t end, int32_t* pi, Ctrl* ctrl, const uint32_t* bits, bool sym,
+                            bool halve, hipStream_t s) {
+    if (end <= begin || n <= 0) return hipSuccess;
+    constexpr int EPT = 8;
+    const int64_t tile = 256 * EPT;
+    const int64_t grid64 = (end - begin + tile - 1) / tile;
+    if (grid64 > 0x7fffffff) return hipErrorInvalidValue;
+    k_ahook_csr<EPT><<<(int)grid64, 256, 0, s>>>(row_ptr, col, n, begin, end, pi, ctrl, bits,
+                                                 bits != nullptr, sym, halve);
+    return hipGetLastError();
+}
+
+}  // namespace hookcc

@@ -398,3 +398,67 @@ def test_symmetric_flag_on_symmetrised_lists(dev):
     del u, v
     lab = cc.labels(du, dv, n, options=cc.Options(symmetric=True)).cpu().numpy()
     assert digest(lab) == rec["sha256"]
+
+
+# ----------------------------------------------------------------------------- CSR input
+def _to_csr(u, v, n):
+    """CSR adjacency of the pair list (rows sorted, column order within a row kept)."""
+    order = np.argsort(u, kind="stable")
+    col = np.ascontiguousarray(v[order].astype(np.int32))
+    row_ptr = np.zeros(n + 1, np.int64)
+    np.cumsum(np.bincount(u, minlength=n), out=row_ptr[1:])
+    return row_ptr, col
+
+
+def test_csr_input_matches_oracle(dev):
+    cases = {
+        "rmat_sym": graphgen.rmat(15, 16, seed=71, symmetrize=True),
+        "grid": graphgen.grid(200, 150, 3, 10, seed=72),
+        "sparse_many_empty_rows": (lambda p: (p[0], p[1], 200000))(graphgen.uniform_pairs(30000, 200000, 73, 0)),
+        "hub_rows": (np.concatenate([np.zeros(50000, np.int32), np.arange(1, 4000, dtype=np.int32)]),
+                     np.concatenate([np.arange(50000, dtype=np.int32) % 9000, np.arange(1, 4000, dtype=np.int32)]),
+                     9000),
+        "empty": (np.zeros(0, np.int32), np.zeros(0, np.int32), 17),
+    }
+    for name, (u, v, n) in cases.items():
+        want = oracle.labels(u, v, n)
+        rp, col = _to_csr(u, v, n)
+        drp = torch.from_numpy(rp).to(dev)
+        dcol = to_dev(col, dev)
+        for opt in (cc.Options(), cc.Options(filter="giant", segments=8),
+                    cc.Options(filter="off", segments=3, path_halving="off")):
+            say("csr", name, opt.filter, opt.segments)
+            got = cc.labels_csr(drp, dcol, n, options=opt).cpu().numpy()
+            assert np.array_equal(got, want), (name, opt)
+        if name == "rmat_sym":
+            got = cc.labels_csr(drp, dcol, n, options=cc.Options(symmetric=True)).cpu().numpy()
+            assert np.array_equal(got, want)
+
+
+def test_csr_rejects_malformed_input(dev):
+    col = to_dev(np.array([1, 2, 0], np.int32), dev)
+    for rp in ([0, 2, 1, 3], [1, 2, 3, 3], [0, 1, 2, 4]):
+        with pytest.raises(cc.CCError) as ei:
+            cc.labels_csr(torch.tensor(rp, dtype=torch.int64, device=dev), col, 3)
+        assert ei.value.code == cc.CC_ERR_RANGE
+    with pytest.raises(cc.CCError) as ei:
+        cc.labels_csr(torch.tensor([0, 1, 2, 3], dtype=torch.int64, device=dev),
+                      to_dev(np.array([1, 5, 0], np.int32), dev), 3)
+    assert ei.value.code == cc.CC_ERR_RANGE
+
+
+def test_csr_full_size_rmat24(dev):
+    rec = _golden()["rmat24"]
+    u, v, n = graphgen.workload("rmat24")
+    du, dv = to_dev(u, dev), to_dev(v, dev)
+    del u, v
+    key, order = torch.sort(du.to(torch.int64) * n + dv.to(torch.int64))
+    del key
+    col = dv[order].contiguous()
+    counts = torch.bincount(du, minlength=n)
+    rp = torch.zeros(n + 1, dtype=torch.int64, device=dev)
+    rp[1:] = torch.cumsum(counts, 0)
+    del du, dv, order
+    for opt in (cc.Options(), cc.Options(symmetric=True)):
+        lab = cc.labels_csr(rp, col, n, options=opt).cpu().numpy()
+        assert digest(lab) == rec["sha256"]

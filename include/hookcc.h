@@ -206,10 +206,14 @@ int32_t cc_labels_batch(int32_t num_graphs, const int64_t* vtx_off, const int64_
                         const int32_t* edges_u, const int32_t* edges_v, int32_t* out_label);
 
 /* As cc_labels_batch on `stream` (hipStream_t, NULL = null stream), using the
- * library's workspace pool; `stats` may be NULL. */
+ * library's workspace pool; `opts` and `stats` may be NULL.  Of `opts` only
+ * `segments` is used: 0 gives every LDS-solved graph the paper's
+ * round(m_g / n_g) segments, S > 0 caps that at S (in LDS a climb is cheap,
+ * so fewer segments -- fewer workgroup barriers -- are often faster; the
+ * autotuner picks it).  Larger graphs use the default device-memory plan. */
 int32_t cc_labels_batch_ex(int32_t num_graphs, const int64_t* vtx_off, const int64_t* edge_off,
                            const int32_t* edges_u, const int32_t* edges_v, int32_t* out_label,
-                           void* stream, cc_stats* stats);
+                           const cc_options* opts, void* stream, cc_stats* stats);
 
 /* Out-of-core solve: the edge lists stay in HOST memory and are streamed to
  * the device in chunks while earlier chunks are hooked.  The Atomic-Hook
@@ -263,9 +267,10 @@ typedef struct cc_graph {
  * CC_BATCH_LDS_MAX_N vertices share one persistent LDS launch, larger ones
  * are each solved in device memory on the same stream, and the call ends
  * with a single synchronisation.  Descriptors may point anywhere (the
- * graphs need not be packed).  Returns CC_OK, CC_ERR_ARG, CC_ERR_RANGE,
- * CC_ERR_NOMEM or CC_ERR_HIP. */
-int32_t cc_labels_list(int32_t count, const cc_graph* graphs, void* stream, cc_stats* stats);
+ * graphs need not be packed).  `opts` as for cc_labels_batch_ex (nullable).
+ * Returns CC_OK, CC_ERR_ARG, CC_ERR_RANGE, CC_ERR_NOMEM or CC_ERR_HIP. */
+int32_t cc_labels_list(int32_t count, const cc_graph* graphs, const cc_options* opts, void* stream,
+                       cc_stats* stats);
 
 /* ------------------------------------------------------------------ serving */
 

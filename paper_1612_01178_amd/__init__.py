@@ -154,11 +154,12 @@ def load():
             lib.cc_workspace_bytes.restype = ctypes.c_size_t
             lib.cc_labels_batch.argtypes = [_i32, _vp, _vp, _vp, _vp, _vp]
             lib.cc_labels_batch.restype = _i32
-            lib.cc_labels_batch_ex.argtypes = [_i32, _vp, _vp, _vp, _vp, _vp, _vp,
+            lib.cc_labels_batch_ex.argtypes = [_i32, _vp, _vp, _vp, _vp, _vp,
+                                               ctypes.POINTER(_COptions), _vp,
                                                ctypes.POINTER(_CStats)]
             lib.cc_labels_batch_ex.restype = _i32
-            lib.cc_labels_list.argtypes = [_i32, ctypes.POINTER(_CGraph), _vp,
-                                           ctypes.POINTER(_CStats)]
+            lib.cc_labels_list.argtypes = [_i32, ctypes.POINTER(_CGraph), ctypes.POINTER(_COptions),
+                                           _vp, ctypes.POINTER(_CStats)]
             lib.cc_labels_list.restype = _i32
             lib.cc_server_create.argtypes = [ctypes.POINTER(_CServerConfig),
                                              ctypes.POINTER(ctypes.c_void_p)]
@@ -268,7 +269,8 @@ def workspace_bytes(n: int, m: int, options: Options | None = None) -> int:
     return int(load().cc_workspace_bytes(int(n), int(m), ctypes.byref(opts)))
 
 
-def labels_batch(u, v, vtx_off, edge_off, *, out=None, stream=None, return_stats: bool = False):
+def labels_batch(u, v, vtx_off, edge_off, *, out=None, options: Options | None = None,
+                 stream=None, return_stats: bool = False):
     """Per-graph local min-id labels of graphs packed back to back.
 
     ``u``/``v`` are int32 CUDA tensors of local ids; ``vtx_off``/``edge_off``
@@ -289,9 +291,10 @@ def labels_batch(u, v, vtx_off, edge_off, *, out=None, stream=None, return_stats
         out = torch.empty(total, dtype=torch.int32, device=u.device)
     st = _CStats()
     with torch.cuda.device(u.device):
+        opts = (options or Options())._c()
         rc = load().cc_labels_batch_ex(len(vo) - 1, vo.ctypes.data, eo.ctypes.data, u.data_ptr(),
-                                       v.data_ptr(), out.data_ptr(), _stream_handle(stream),
-                                       ctypes.byref(st))
+                                       v.data_ptr(), out.data_ptr(), ctypes.byref(opts),
+                                       _stream_handle(stream), ctypes.byref(st))
     _check(rc)
     if return_stats:
         return out, {f: getattr(st, f) for f, _ in _CStats._fields_ if f != "reserved"}
@@ -353,7 +356,8 @@ def labels_csr(row_ptr, col, n: int, *, out=None, options: Options | None = None
     return out
 
 
-def labels_list(graphs, *, stream=None, return_stats: bool = False):
+def labels_list(graphs, *, options: Options | None = None, stream=None,
+                return_stats: bool = False):
     """Labels of independent graphs, each given as (u, v, n) or (u, v, n, out)
     with its own int32 CUDA tensors.  Returns the list of label tensors."""
     import torch
@@ -379,7 +383,9 @@ def labels_list(graphs, *, stream=None, return_stats: bool = False):
     if dev is None:
         return ([], {}) if return_stats else []
     with torch.cuda.device(dev):
-        rc = load().cc_labels_list(len(graphs), descs, _stream_handle(stream), ctypes.byref(st))
+        opts = (options or Options())._c()
+        rc = load().cc_labels_list(len(graphs), descs, ctypes.byref(opts), _stream_handle(stream),
+                                   ctypes.byref(st))
     _check(rc)
     if return_stats:
         return outs, {f: getattr(st, f) for f, _ in _CStats._fields_ if f != "reserved"}

@@ -25,7 +25,7 @@ import os
 import threading
 import time
 
-from . import Options, labels
+from . import Options, labels, labels_batch
 
 _CACHE_PATH = os.environ.get("HOOKCC_TUNE_CACHE",
                              os.path.join(os.path.expanduser("~"), ".cache", "hookcc", "tune.json"))
@@ -120,3 +120,25 @@ def tune(u, v, n: int, *, reps: int = 3, cache: bool = True, path: str | None = 
         _store(path or _CACHE_PATH, shape_key(n, m),
                {"options": best.__dict__, "ms": best_t, "n": n, "m": m})
     return best, table
+
+
+def tune_batch(u, v, vtx_off, edge_off, *, reps: int = 3, log=None):
+    """Per-graph segment cap of the batched LDS solver (0 = the paper's
+    round(m_g / n_g) per graph, else min(S, that)); returns (Options, table)."""
+    import torch
+    out = torch.empty(int(vtx_off[-1]), dtype=torch.int32, device=u.device)
+    table = []
+    for seg in (0, 1, 2, 4, 8):
+        opt = Options(segments=seg)
+        labels_batch(u, v, vtx_off, edge_off, out=out, options=opt)
+        best = float("inf")
+        for _ in range(reps):
+            torch.cuda.synchronize()
+            t = time.perf_counter()
+            labels_batch(u, v, vtx_off, edge_off, out=out, options=opt)
+            best = min(best, time.perf_counter() - t)
+        table.append((best * 1e3, seg))
+        if log:
+            log("tune batch segments cap %d: %.3f ms" % (seg, best * 1e3))
+    table.sort()
+    return Options(segments=table[0][1]), table

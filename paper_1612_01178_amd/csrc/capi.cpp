@@ -32,18 +32,20 @@ size_t cc_workspace_bytes(int32_t n, int64_t m, const cc_options* opts) {
 
 int32_t cc_labels_batch(int32_t num_graphs, const int64_t* vtx_off, const int64_t* edge_off,
                         const int32_t* edges_u, const int32_t* edges_v, int32_t* out_label) {
-    return batch_impl(num_graphs, vtx_off, edge_off, edges_u, edges_v, out_label, nullptr, nullptr);
+    return batch_impl(num_graphs, vtx_off, edge_off, edges_u, edges_v, out_label, nullptr, nullptr,
+                      nullptr);
 }
 
 int32_t cc_labels_batch_ex(int32_t num_graphs, const int64_t* vtx_off, const int64_t* edge_off,
                            const int32_t* edges_u, const int32_t* edges_v, int32_t* out_label,
-                           void* stream, cc_stats* stats) {
-    return batch_impl(num_graphs, vtx_off, edge_off, edges_u, edges_v, out_label,
+                           const cc_options* opts, void* stream, cc_stats* stats) {
+    return batch_impl(num_graphs, vtx_off, edge_off, edges_u, edges_v, out_label, opts,
                       static_cast<hipStream_t>(stream), stats);
 }
 
-int32_t cc_labels_list(int32_t count, const cc_graph* graphs, void* stream, cc_stats* stats) {
-    return list_impl(count, graphs, static_cast<hipStream_t>(stream), stats);
+int32_t cc_labels_list(int32_t count, const cc_graph* graphs, const cc_options* opts, void* stream,
+                       cc_stats* stats) {
+    return list_impl(count, graphs, opts, static_cast<hipStream_t>(stream), stats);
 }
 
 int32_t cc_labels_host(int32_t n, const int32_t* host_u, const int32_t* host_v, int64_t m,

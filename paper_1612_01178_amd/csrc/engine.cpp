@@ -779,8 +779,14 @@ size_t workspace_bytes_impl(int32_t n, int64_t m, const cc_options* opts) {
 // workgroups take them largest first; every larger graph gets the device-memory
 // Atomic-Hook solve with its own control block.  Everything is enqueued on `s`
 // and the call ends with one synchronisation and one read of all control blocks.
-int32_t list_impl(int32_t count, const cc_graph* graphs, hipStream_t s, cc_stats* st) {
+int32_t list_impl(int32_t count, const cc_graph* graphs, const cc_options* opts, hipStream_t s,
+                  cc_stats* st) {
     if (count < 0) return fail(CC_ERR_ARG, "graph count < 0");
+    // Per-graph segment count of the LDS solver: 0 = the paper's round(m/n);
+    // S > 0 = min(S, that).  In LDS a climb costs LDS latency, not a trip to
+    // device memory, so fewer segments (fewer barriers) usually pay.
+    const int32_t seg_cap = opts ? opts->segments : 0;
+    if (seg_cap < 0) return fail(CC_ERR_ARG, "cc_options.segments < 0");
     if (st) {
         std::memset(st, 0, sizeof *st);
         st->giant_label = -1;
@@ -853,8 +859,9 @@ int32_t list_impl(int32_t count, const cc_graph* graphs, hipStream_t s, cc_stats
             d.out = G.out_label;
             d.m = G.m;
             d.n = G.n;
-            // average-degree segmentation per graph (Section 3.B)
+            // average-degree segmentation per graph (Section 3.B), capped
             d.segments = (int32_t)std::max<int64_t>(1, (G.m + G.n / 2) / G.n);
+            if (seg_cap > 0) d.segments = std::min<int32_t>(d.segments, seg_cap);
             hd[i] = d;
             ho[i] = i;
         }
@@ -882,7 +889,8 @@ int32_t list_impl(int32_t count, const cc_graph* graphs, hipStream_t s, cc_stats
 }
 
 int32_t batch_impl(int32_t B, const int64_t* vo, const int64_t* eo, const int32_t* u,
-                   const int32_t* v, int32_t* out, hipStream_t s, cc_stats* st) {
+                   const int32_t* v, int32_t* out, const cc_options* opts, hipStream_t s,
+                   cc_stats* st) {
     if (B < 0) return fail(CC_ERR_ARG, "num_graphs < 0");
     if (B == 0) {
         if (st) {
@@ -911,7 +919,7 @@ int32_t batch_impl(int32_t B, const int64_t* vo, const int64_t* eo, const int32_
         G.n = (int32_t)(vo[g + 1] - vo[g]);
         G.reserved = 0;
     }
-    return list_impl(B, list.data(), s, st);
+    return list_impl(B, list.data(), opts, s, st);
 }
 
 // ---------------------------------------------------------------------- probes, release

@@ -21,10 +21,14 @@ int32_t labels_impl(int32_t n, const int32_t* u, const int32_t* v, int64_t m, in
 size_t workspace_bytes_impl(int32_t n, int64_t m, const cc_options* opts);
 
 // Independent graphs given by descriptors (device arrays); synchronous on s.
-int32_t list_impl(int32_t count, const cc_graph* graphs, hipStream_t s, cc_stats* st);
+// opts (nullable): only `segments` is used (per-graph segment cap of the LDS
+// solver).
+int32_t list_impl(int32_t count, const cc_graph* graphs, const cc_options* opts, hipStream_t s,
+                  cc_stats* st);
 // Graphs packed back to back with host offsets; synchronous on s.
 int32_t batch_impl(int32_t B, const int64_t* vo, const int64_t* eo, const int32_t* u,
-                   const int32_t* v, int32_t* out, hipStream_t s, cc_stats* st);
+                   const int32_t* v, int32_t* out, const cc_options* opts, hipStream_t s,
+                   cc_stats* st);
 
 // Edges in host memory, streamed in chunks (see engine.cpp).
 int32_t stream_impl(int32_t n, const int32_t* hu, const int32_t* hv, int64_t m, int32_t* out,

@@ -75,23 +75,40 @@ __global__ __launch_bounds__(1024) void k_batch_lds(const GraphDesc* __restrict_
         for (int32_t seg = 0; seg < s; ++seg) {
             const int64_t b0 = d.m * seg / s, b1 = d.m * (seg + 1) / s;
             // kBatchEPT entries per thread per step, all loads issued before
-            // any hook so that the HBM latency of the edge stream overlaps.
-            for (int64_t e0 = b0 + tid; e0 < b1; e0 += (int64_t)nthr * kBatchEPT) {
-                int32_t a[kBatchEPT], b[kBatchEPT];
+            // any hook, and the next step's loads issued before this step's
+            // hooks (software pipelining), so the edge stream's latency
+            // overlaps the LDS work.
+            const int64_t step = (int64_t)nthr * kBatchEPT;
+            int32_t a[kBatchEPT], b[kBatchEPT], na[kBatchEPT], nb[kBatchEPT];
+            int64_t e0 = b0 + tid;
+#pragma unroll
+            for (int j = 0; j < kBatchEPT; ++j) {
+                const int64_t e = e0 + (int64_t)j * nthr;
+                a[j] = e < b1 ? __builtin_nontemporal_load(d.u + e) : 0;
+                b[j] = e < b1 ? __builtin_nontemporal_load(d.v + e) : 0;
+            }
+            for (; e0 < b1; e0 += step) {
+                const int64_t e1 = e0 + step;
 #pragma unroll
                 for (int j = 0; j < kBatchEPT; ++j) {
-                    const int64_t e = e0 + (int64_t)j * nthr;
-                    a[j] = e < b1 ? __builtin_nontemporal_load(d.u + e) : 0;
-                    b[j] = e < b1 ? __builtin_nontemporal_load(d.v + e) : 0;
+                    const int64_t e = e1 + (int64_t)j * nthr;
+                    na[j] = e < b1 ? __builtin_nontemporal_load(d.u + e) : 0;
+                    nb[j] = e < b1 ? __builtin_nontemporal_load(d.v + e) : 0;
                 }
 #pragma unroll
                 for (int j = 0; j < kBatchEPT; ++j) {
+                    if (e0 + (int64_t)j * nthr >= b1) continue;
                     if ((uint32_t)a[j] >= n || (uint32_t)b[j] >= n) {
                         bad = true;
                         continue;
                     }
                     if (a[j] == b[j]) continue;
                     lds_atomic_hook(spi, lds_ld16(spi, a[j]), lds_ld16(spi, b[j]));
+                }
+#pragma unroll
+                for (int j = 0; j < kBatchEPT; ++j) {
+                    a[j] = na[j];
+                    b[j] = nb[j];
                 }
             }
             __syncthreads();

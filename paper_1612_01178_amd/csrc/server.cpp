@@ -166,13 +166,13 @@ int32_t run_wave(std::vector<Request*>& wave, hipStream_t s) {
         list[i].n = r->n;
         list[i].reserved = 0;
     }
-    int32_t rc = list_impl((int32_t)list.size(), list.data(), s, nullptr);
+    int32_t rc = list_impl((int32_t)list.size(), list.data(), nullptr, s, nullptr);
     const double t = now_s();
     for (Request* r : wave) r->info.t_device_done = t;
     if (rc == CC_ERR_RANGE && wave.size() > 1) {
         // attribute the error: solve each request of the wave on its own
         for (size_t i = 0; i < wave.size(); ++i) {
-            int32_t ri = list_impl(1, &list[i], s, nullptr);
+            int32_t ri = list_impl(1, &list[i], nullptr, s, nullptr);
             wave[i]->info.status = ri;
         }
         rc = CC_OK;

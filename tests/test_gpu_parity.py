@@ -300,6 +300,10 @@ def test_batch_mixed_sizes_against_oracle(dev):
     want = oracle.labels_batch(u, v, vo, eo)
     got, st = cc.labels_batch(to_dev(u, dev), to_dev(v, dev), vo, eo, return_stats=True)
     assert np.array_equal(got.cpu().numpy(), want)
+    for cap in (1, 2, 5):
+        got = cc.labels_batch(to_dev(u, dev), to_dev(v, dev), vo, eo,
+                              options=cc.Options(segments=cap))
+        assert np.array_equal(got.cpu().numpy(), want), cap
 
 
 def test_batch_range_error(dev):
@@ -341,8 +345,10 @@ def test_full_size_batch_matches_oracle_digest(dev):
     u, v, vo, eo = graphgen.batch_er(10000, seed=1004)
     assert (int(vo[-1]), len(u)) == (rec["n"], rec["m"])
     say("full size batch10k")
-    lab = cc.labels_batch(to_dev(u, dev), to_dev(v, dev), vo, eo).cpu().numpy()
-    assert digest(lab) == rec["sha256"]
+    du, dv = to_dev(u, dev), to_dev(v, dev)
+    for cap in (0, 1, 3):
+        lab = cc.labels_batch(du, dv, vo, eo, options=cc.Options(segments=cap)).cpu().numpy()
+        assert digest(lab) == rec["sha256"], cap
 
 
 # ----------------------------------------------------------------------------- streamed (host edges)

@@ -137,6 +137,9 @@ int32_t make_plan(int32_t n, int64_t m, const cc_options* o, Plan& p, bool allow
             return fail(CC_ERR_ARG, "cc_options.block must be a multiple of 64 in [64, 1024]");
         p.block = op.block;
     }
+    // Tile: 16 entries per thread for the plain Atomic-Hook (measured best on
+    // sparse lists, e.g. the percolated grid), 8 where the filter runs.
+    p.ept = (p.filter == CC_FILTER_GIANT || p.hook != CC_HOOK_ATOMIC) ? 8 : 16;
     if (op.edges_per_thread != 0) {
         if (op.edges_per_thread != 4 && op.edges_per_thread != 8 && op.edges_per_thread != 16)
             return fail(CC_ERR_ARG, "cc_options.edges_per_thread must be 4, 8 or 16");

@@ -133,22 +133,12 @@ __global__ __launch_bounds__(1024) void k_ahook_hot(const int32_t* __restrict__ 
     }
     const int64_t stride = (int64_t)blockDim.x * 4;
     const int64_t tile = (int64_t)blockDim.x * EPT;
-    const int64_t step = (int64_t)gridDim.x * tile;
     bool bad = false;
-    // Software pipelining: the next tile's entries are loaded while the
-    // current tile's bit tests and climbs run.
-    int32_t a[EPT], b[EPT], na[EPT], nb[EPT];
-    int64_t t0 = begin + (int64_t)blockIdx.x * tile;
-    if (t0 < end) {
-        load_tile<EPT>(eu, t0 + (int64_t)threadIdx.x * 4, stride, end, vec, a);
-        load_tile<EPT>(ev, t0 + (int64_t)threadIdx.x * 4, stride, end, vec, b);
-    }
-    for (; t0 < end; t0 += step) {
-        const int64_t t1 = t0 + step;
-        if (t1 < end) {
-            load_tile<EPT>(eu, t1 + (int64_t)threadIdx.x * 4, stride, end, vec, na);
-            load_tile<EPT>(ev, t1 + (int64_t)threadIdx.x * 4, stride, end, vec, nb);
-        }
+    for (int64_t t0 = begin + (int64_t)blockIdx.x * tile; t0 < end; t0 += (int64_t)gridDim.x * tile) {
+        const int64_t e0 = t0 + (int64_t)threadIdx.x * 4;
+        int32_t a[EPT], b[EPT];
+        load_tile<EPT>(eu, e0, stride, end, vec, a);
+        load_tile<EPT>(ev, e0, stride, end, vec, b);
         uint32_t act = 0;
 #pragma unroll
         for (int j = 0; j < EPT; ++j) {
@@ -156,61 +146,31 @@ __global__ __launch_bounds__(1024) void k_ahook_hot(const int32_t* __restrict__ 
             bad |= !in;
             if (in && a[j] != b[j] && !(sym && a[j] > b[j])) act |= 1u << j;
         }
-        // Bit tests, branch-free so that all of them are in flight at once:
-        // every tag read, then every bitmap word load (an entry that is
-        // inactive, or whose word is in LDS, loads word 0 instead, one hot
-        // line), then the selection.
-        uint32_t inga = 0, ingb = 0;  // giant-membership bits per entry
-        if (filter) {
-            uint32_t xa[EPT], xb[EPT], ta[EPT], tb[EPT];
-#pragma unroll
-            for (int j = 0; j < EPT; ++j) {
-                xa[j] = (act >> j & 1) ? (uint32_t)a[j] : 0u;
-                xb[j] = (act >> j & 1) ? (uint32_t)b[j] : 0u;
-                ta[j] = ltag[(xa[j] >> 5) & (SLOTS - 1)];
-                tb[j] = ltag[(xb[j] >> 5) & (SLOTS - 1)];
-            }
-            uint32_t wa[EPT], wb[EPT], la[EPT], lb[EPT], hit = 0;
-#pragma unroll
-            for (int j = 0; j < EPT; ++j) {
-                const uint32_t ka = (xa[j] >> 5) / SLOTS, kb = (xb[j] >> 5) / SLOTS;
-                const bool ha = ka < kEmpty && ta[j] == ka, hb = kb < kEmpty && tb[j] == kb;
-                hit |= (ha ? 1u : 0u) << (2 * j);
-                hit |= (hb ? 1u : 0u) << (2 * j + 1);
-                wa[j] = bits[ha ? 0u : (xa[j] >> 5)];
-                wb[j] = bits[hb ? 0u : (xb[j] >> 5)];
-                la[j] = lval[(xa[j] >> 5) & (SLOTS - 1)];
-                lb[j] = lval[(xb[j] >> 5) & (SLOTS - 1)];
-            }
-#pragma unroll
-            for (int j = 0; j < EPT; ++j) {
-                const uint32_t worda = (hit >> (2 * j) & 1) ? la[j] : wa[j];
-                const uint32_t wordb = (hit >> (2 * j + 1) & 1) ? lb[j] : wb[j];
-                inga |= (worda >> (xa[j] & 31) & 1u) << j;
-                ingb |= (wordb >> (xb[j] & 31) & 1u) << j;
-            }
-            act &= ~(inga & ingb);  // both ends in the giant: already satisfied
-        }
-        // Parents of the endpoints outside the giant (again all issued at once;
-        // an endpoint that needs none reads pi[0]).
         int32_t pa[EPT], pb[EPT];
 #pragma unroll
         for (int j = 0; j < EPT; ++j) {
-            const bool na_ = (act >> j & 1) && !(inga >> j & 1);
-            const bool nb_ = (act >> j & 1) && !(ingb >> j & 1);
-            const int32_t ra = ld_tree<false>(pi + (na_ ? a[j] : 0));
-            const int32_t rb = ld_tree<false>(pi + (nb_ ? b[j] : 0));
-            pa[j] = na_ ? ra : g;
-            pb[j] = nb_ ? rb : g;
+            if (!(act >> j & 1)) continue;
+            uint32_t ba = 0, bb = 0;
+            if (filter) {
+                const uint32_t wa = (uint32_t)a[j] >> 5, wb = (uint32_t)b[j] >> 5;
+                const uint32_t sa = wa & (SLOTS - 1), sb = wb & (SLOTS - 1);
+                const uint32_t ka = wa / SLOTS, kb = wb / SLOTS;
+                // ka == kEmpty can never be cached (it is the empty marker)
+                const uint32_t worda = (ka < kEmpty && ltag[sa] == ka) ? lval[sa] : bits[wa];
+                const uint32_t wordb = (kb < kEmpty && ltag[sb] == kb) ? lval[sb] : bits[wb];
+                ba = worda >> (a[j] & 31) & 1;
+                bb = wordb >> (b[j] & 31) & 1;
+            }
+            if (ba & bb) {
+                act &= ~(1u << j);
+            } else {
+                pa[j] = ba ? g : ld_tree<false>(pi + a[j]);
+                pb[j] = bb ? g : ld_tree<false>(pi + b[j]);
+            }
         }
 #pragma unroll
         for (int j = 0; j < EPT; ++j)
             if (act >> j & 1) hot_climb(pi, pa[j], pb[j], halve);
-#pragma unroll
-        for (int j = 0; j < EPT; ++j) {
-            a[j] = na[j];
-            b[j] = nb[j];
-        }
     }
     if (bad) atomicOr(&ctrl->status, kStatusRange);
 }
@@ -241,7 +201,7 @@ static hipError_t ahook_hot_ept(int ept, int grid, int block, hipStream_t s, con
     switch (ept) {
         case 4: k_ahook_hot<4, SLOTS, TagT><<<grid, block, 0, s>>>(u, v, begin, end, vec, pi, n, ctrl, bits, tags, vals, halve, sym); break;
         case 8:
-        case 16:  // 16 would spill registers with the pipelined tile; run 8
+        case 16:  // the 16-entry tile does not fit the registers next to the LDS table; run 8
             k_ahook_hot<8, SLOTS, TagT><<<grid, block, 0, s>>>(u, v, begin, end, vec, pi, n, ctrl, bits, tags, vals, halve, sym); break;
         default: return hipErrorInvalidValue;
     }

@@ -104,3 +104,39 @@ def test_server_errors_stay_with_their_request(dev):
         for (u, v, n), t in zip(good, tg):
             lab, info = srv.wait(t)
             assert np.array_equal(lab, oracle.labels(u, v, n))
+
+
+def test_concurrent_calls_from_host_threads(dev):
+    """Calls from several host threads on their own streams at once (the
+    workspace cache is per stream) give the same labels as alone."""
+    import threading
+    reqs = _requests(12, seed=31, scale_hi=17)
+    want = [oracle.labels(u, v, n) for u, v, n in reqs]
+    tens = [(torch.from_numpy(u).to(dev), torch.from_numpy(v).to(dev), n) for u, v, n in reqs]
+    torch.cuda.synchronize()
+    results = [None] * len(reqs)
+    errors = []
+
+    def work(k):
+        try:
+            s = torch.cuda.Stream()
+            with torch.cuda.stream(s):
+                for rep in range(3):
+                    for i in range(k, len(tens), 4):
+                        du, dv, n = tens[i]
+                        lab = cc.labels(du, dv, n, stream=s,
+                                        options=cc.Options(hook=("atomic", "plain", "auto")[rep]))
+                        s.synchronize()
+                        results[i] = lab.cpu().numpy()
+                        assert np.array_equal(results[i], want[i]), (i, rep)
+        except Exception as e:  # surfaced below
+            errors.append(e)
+
+    threads = [threading.Thread(target=work, args=(k,)) for k in range(4)]
+    for t in threads:
+        t.start()
+    for t in threads:
+        t.join()
+    assert not errors, errors
+    for i in range(len(reqs)):
+        assert np.array_equal(results[i], want[i])

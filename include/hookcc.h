@@ -118,7 +118,12 @@ typedef struct cc_options {
                                  the result for such lists and halves the tree accesses.
                                  Wrong labels if the guarantee does not hold.  Never on by
                                  default; with CC_HOOK_AUTO it forces the Atomic-Hook.    */
-    int32_t reserved[2];      /* must be zero                                           */
+    int32_t graph;            /* 1 = capture the call's launch sequence in a hipGraph on the
+                                 call's stream the first time and replay it on later
+                                 calls with the same arrays, sizes and plan (Atomic-Hook
+                                 single solves, graph lists and batches; needs a stream
+                                 other than the null stream, else ignored)             */
+    int32_t reserved[1];      /* must be zero                                           */
 } cc_options;
 
 #define CC_HOT_AUTO 0

@@ -58,7 +58,7 @@ class _COptions(ctypes.Structure):
                 ("profile", ctypes.c_int32), ("host_loop", ctypes.c_int32),
                 ("coherent_loads", ctypes.c_int32), ("hot_cache", ctypes.c_int32),
                 ("path_halving", ctypes.c_int32), ("symmetric", ctypes.c_int32),
-                ("reserved", ctypes.c_int32 * 2)]
+                ("graph", ctypes.c_int32), ("reserved", ctypes.c_int32 * 1)]
 
 
 class _CStats(ctypes.Structure):
@@ -107,6 +107,7 @@ class Options:
     hot_cache: str = "auto"
     path_halving: str = "auto"
     symmetric: bool = False
+    graph: bool = False
 
     def _c(self) -> _COptions:
         o = _COptions()
@@ -124,6 +125,7 @@ class Options:
         o.hot_cache = {"auto": 0, "on": 1, "off": 2, "large": 3}[self.hot_cache]
         o.path_halving = {"auto": 0, "on": 1, "off": 2}[self.path_halving]
         o.symmetric = 1 if self.symmetric else 0
+        o.graph = 1 if self.graph else 0
         return o
 
 

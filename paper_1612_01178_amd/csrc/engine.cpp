@@ -61,6 +61,7 @@ struct Plan {
     int hot_slots = 32768;
     bool halve = true;  // path halving in the Atomic-Hook climb
     bool symmetric = false;  // caller promises both orientations of every pair
+    bool graph = false;      // capture the launch sequence in a hipGraph and replay it
 };
 
 int32_t make_plan(int32_t n, int64_t m, const cc_options* o, Plan& p, bool allow_plain = true) {
@@ -68,8 +69,9 @@ int32_t make_plan(int32_t n, int64_t m, const cc_options* o, Plan& p, bool allow
     std::memset(&d, 0, sizeof d);
     d.filter = CC_FILTER_AUTO;
     const cc_options& op = o ? *o : d;
-    for (int i = 0; i < 2; ++i)
-        if (op.reserved[i] != 0) return fail(CC_ERR_ARG, "cc_options.reserved must be zero");
+    if (op.reserved[0] != 0) return fail(CC_ERR_ARG, "cc_options.reserved must be zero");
+    if (op.graph != 0 && op.graph != 1) return fail(CC_ERR_ARG, "cc_options.graph must be 0 or 1");
+    p.graph = op.graph == 1;
     if (op.symmetric != 0 && op.symmetric != 1)
         return fail(CC_ERR_ARG, "cc_options.symmetric must be 0 or 1");
     p.symmetric = op.symmetric == 1;
@@ -208,6 +210,37 @@ struct PoolEntry {
     hipStream_t copy_stream = nullptr;  // host-to-device staging of streamed solves
     hipEvent_t copied[2] = {nullptr, nullptr};
     hipEvent_t consumed[2] = {nullptr, nullptr};
+    // captured launch sequences of recent calls, most recent last
+    struct Captured {
+        uint64_t key;
+        hipGraph_t graph;
+        hipGraphExec_t exec;
+    };
+    std::vector<Captured> graphs;
+};
+
+void drop_graphs(PoolEntry* e) {
+    for (auto& c : e->graphs) {
+        (void)hipGraphExecDestroy(c.exec);
+        (void)hipGraphDestroy(c.graph);
+    }
+    e->graphs.clear();
+}
+
+// FNV-1a over the bytes that determine a launch sequence.
+struct KeyHash {
+    uint64_t h = 1469598103934665603ULL;
+    template <class T>
+    KeyHash& add(const T& x) {
+        const unsigned char* p = reinterpret_cast<const unsigned char*>(&x);
+        for (size_t i = 0; i < sizeof(T); ++i) h = (h ^ p[i]) * 1099511628211ULL;
+        return *this;
+    }
+    KeyHash& bytes(const void* b, size_t n) {
+        const unsigned char* p = static_cast<const unsigned char*>(b);
+        for (size_t i = 0; i < n; ++i) h = (h ^ p[i]) * 1099511628211ULL;
+        return *this;
+    }
 };
 
 std::mutex g_pool_mu;
@@ -224,6 +257,7 @@ PoolEntry* pool_entry(hipStream_t s) {
 
 int32_t ensure_dev(PoolEntry* e, size_t bytes) {
     if (e->bytes >= bytes && e->dev) return CC_OK;
+    drop_graphs(e);  // captured graphs point into the old buffer
     if (e->dev) {
         HIPCHK(hipFree(e->dev));
         e->dev = nullptr;
@@ -250,6 +284,7 @@ int32_t ensure_host(PoolEntry* e, int64_t count = 1) {
 
 int32_t ensure_stage(PoolEntry* e, size_t bytes) {
     if (e->stage_bytes >= bytes && e->host_stage) return CC_OK;
+    drop_graphs(e);  // captured copies read from the old staging buffer
     if (e->host_stage) {
         HIPCHK(hipHostFree(e->host_stage));
         e->host_stage = nullptr;
@@ -311,6 +346,43 @@ enum { kPhaseHook = 0, kPhaseCompress = 1, kPhaseOther = 2 };
         HIPCHK(expr);                      \
         HIPCHK(tm.end());                  \
     } while (0)
+
+// Runs `enqueue` on s through a cached hipGraph keyed by `key`: the first
+// call with a key captures the launch sequence, later calls replay it.  Up
+// to 8 graphs are kept per pool entry.  Needs a stream other than the null
+// stream (the legacy null stream cannot be captured).
+template <class F>
+int32_t run_graph(PoolEntry* pe, uint64_t key, hipStream_t s, F&& enqueue) {
+    PoolEntry::Captured* hit = nullptr;
+    for (auto& c : pe->graphs)
+        if (c.key == key) hit = &c;
+    if (!hit) {
+        HIPCHK(hipStreamBeginCapture(s, hipStreamCaptureModeThreadLocal));
+        int32_t rc = enqueue();
+        hipGraph_t g = nullptr;
+        hipError_t e = hipStreamEndCapture(s, &g);
+        if (rc != CC_OK) {
+            if (g) (void)hipGraphDestroy(g);
+            return rc;
+        }
+        if (e != hipSuccess) return fail(CC_ERR_HIP, std::string("graph capture: ") + hipGetErrorString(e));
+        hipGraphExec_t x = nullptr;
+        e = hipGraphInstantiate(&x, g, nullptr, nullptr, 0);
+        if (e != hipSuccess) {
+            (void)hipGraphDestroy(g);
+            return fail(CC_ERR_HIP, std::string("graph instantiate: ") + hipGetErrorString(e));
+        }
+        if (pe->graphs.size() >= 8) {
+            (void)hipGraphExecDestroy(pe->graphs.front().exec);
+            (void)hipGraphDestroy(pe->graphs.front().graph);
+            pe->graphs.erase(pe->graphs.begin());
+        }
+        pe->graphs.push_back({key, g, x});
+        hit = &pe->graphs.back();
+    }
+    HIPCHK(hipGraphLaunch(hit->exec, s));
+    return CC_OK;
+}
 
 // ---------------------------------------------------------------------- single solve
 int32_t finish(hipStream_t s, Ctrl* dctrl, Ctrl* hctrl, cc_stats* st) {
@@ -557,8 +629,20 @@ int32_t labels_impl(int32_t n, const int32_t* u, const int32_t* v, int64_t m, in
     tm.s = s;
     int64_t rounds = 0;
     if (p.hook == CC_HOOK_ATOMIC) {
-        rc = enqueue_atomic(n, u, v, m, out, p, reinterpret_cast<Ctrl*>(ws), filter_bufs(ws, L), s,
-                            tm, st);
+        if (p.graph && s != nullptr && !p.profile) {
+            KeyHash k;
+            k.add(n).add(m).add(u).add(v).add(out).add(ws).add(s).add(p.segments).add(p.filter)
+                .add(p.filter_after).add(p.block).add(p.ept).add(p.coherent).add(p.hot)
+                .add(p.hot_slots).add(p.halve).add(p.symmetric);
+            cc_stats* st_capture = st;
+            rc = run_graph(pe, k.h, s, [&]() {
+                return enqueue_atomic(n, u, v, m, out, p, reinterpret_cast<Ctrl*>(ws),
+                                      filter_bufs(ws, L), s, tm, st_capture);
+            });
+        } else {
+            rc = enqueue_atomic(n, u, v, m, out, p, reinterpret_cast<Ctrl*>(ws), filter_bufs(ws, L),
+                                s, tm, st);
+        }
         if (rc == CC_OK) rc = finish(s, reinterpret_cast<Ctrl*>(ws), pe->host_ctrl, st);
     } else if (p.host_loop != CC_HOST_LOOP_OFF) {
         rc = solve_host_loop(n, u, v, m, out, p, ws, s, pe->host_ctrl, tm, st);
@@ -840,18 +924,20 @@ int32_t list_impl(int32_t count, const cc_graph* graphs, const cc_options* opts,
         region_off[i] = off;
         off += align256(layouts[i].total);
     }
+    if (ns > 0) HIPCHK(prepare_batch_lds());
     PoolEntry* pe = pool_entry(s);
     std::lock_guard<std::mutex> lk(pe->mu);
     int32_t rc = ensure_host(pe, 1 + nl);
     if (rc != CC_OK) return rc;
     rc = ensure_dev(pe, off);
     if (rc != CC_OK) return rc;
-    char* ws = static_cast<char*>(pe->dev);
-    Ctrl* ctrls = reinterpret_cast<Ctrl*>(ws);
-    HIPCHK(hipMemsetAsync(ctrls, 0, sizeof(Ctrl), s));
     if (ns > 0) {
         rc = ensure_stage(pe, desc_bytes + order_bytes);
         if (rc != CC_OK) return rc;
+    }
+    char* ws = static_cast<char*>(pe->dev);
+    Ctrl* ctrls = reinterpret_cast<Ctrl*>(ws);
+    if (ns > 0) {
         GraphDesc* hd = static_cast<GraphDesc*>(pe->host_stage);
         int32_t* ho = reinterpret_cast<int32_t*>(static_cast<char*>(pe->host_stage) + desc_bytes);
         for (int32_t i = 0; i < ns; ++i) {
@@ -868,20 +954,44 @@ int32_t list_impl(int32_t count, const cc_graph* graphs, const cc_options* opts,
             hd[i] = d;
             ho[i] = i;
         }
-        HIPCHK(hipMemcpyAsync(ws + desc_off, pe->host_stage, desc_bytes + order_bytes,
-                              hipMemcpyHostToDevice, s));
-        HIPCHK(launch_batch_lds(reinterpret_cast<GraphDesc*>(ws + desc_off),
-                                reinterpret_cast<int32_t*>(ws + order_off), ns, (int32_t)maxn_small,
-                                &ctrls[0].queue_head, &ctrls[0].status, device_cu_count(), s));
-        if (st) st->hook_launches += 1;
     }
+    // The launch sequence: clear the LDS solver's control block, upload the
+    // descriptors, one persistent LDS launch, then every large graph's solve.
     Timer tm;
-    for (int32_t i = 0; i < nl; ++i) {
-        const cc_graph& G = graphs[large[i]];
-        rc = enqueue_atomic(G.n, G.edges_u, G.edges_v, G.m, G.out_label, plans[i], &ctrls[1 + i],
-                            filter_bufs(ws + region_off[i], layouts[i]), s, tm, st);
-        if (rc != CC_OK) return rc;
+    auto enqueue = [&]() -> int32_t {
+        HIPCHK(launch_zero(ctrls, sizeof(Ctrl) / 4, s));
+        if (ns > 0) {
+            HIPCHK(hipMemcpyAsync(ws + desc_off, pe->host_stage, desc_bytes + order_bytes,
+                                  hipMemcpyHostToDevice, s));
+            HIPCHK(launch_batch_lds(reinterpret_cast<GraphDesc*>(ws + desc_off),
+                                    reinterpret_cast<int32_t*>(ws + order_off), ns,
+                                    (int32_t)maxn_small, &ctrls[0].queue_head, &ctrls[0].status,
+                                    device_cu_count(), s));
+        }
+        for (int32_t i = 0; i < nl; ++i) {
+            const cc_graph& G = graphs[large[i]];
+            int32_t r2 = enqueue_atomic(G.n, G.edges_u, G.edges_v, G.m, G.out_label, plans[i],
+                                        &ctrls[1 + i], filter_bufs(ws + region_off[i], layouts[i]),
+                                        s, tm, nullptr);
+            if (r2 != CC_OK) return r2;
+        }
+        return CC_OK;
+    };
+    const bool use_graph = opts && opts->graph == 1 && s != nullptr;
+    if (use_graph) {
+        KeyHash k;
+        k.add(count).add(ws).add(s).add(seg_cap).add(maxn_small).add(ns).add(nl);
+        if (ns > 0) k.bytes(pe->host_stage, (size_t)ns * sizeof(GraphDesc));
+        for (int32_t i = 0; i < nl; ++i) {
+            const cc_graph& G = graphs[large[i]];
+            k.add(G.edges_u).add(G.edges_v).add(G.out_label).add(G.m).add(G.n);
+        }
+        rc = run_graph(pe, k.h, s, enqueue);
+    } else {
+        rc = enqueue();
     }
+    if (rc != CC_OK) return rc;
+    if (st) st->hook_launches += (ns > 0 ? 1 : 0);
     HIPCHK(hipMemcpyAsync(pe->host_ctrl, ctrls, sizeof(Ctrl) * (1 + nl), hipMemcpyDeviceToHost, s));
     HIPCHK(hipStreamSynchronize(s));
     if (st) st->host_syncs += 1;
@@ -953,6 +1063,7 @@ void release_impl() {
     for (auto& kv : g_pool) {
         PoolEntry* e = kv.second.get();
         std::lock_guard<std::mutex> lk(e->mu);
+        drop_graphs(e);
         for (int i = 0; i < 2; ++i) {
             if (e->copied[i]) (void)hipEventDestroy(e->copied[i]);
             if (e->consumed[i]) (void)hipEventDestroy(e->consumed[i]);

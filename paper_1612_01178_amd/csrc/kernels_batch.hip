@@ -131,19 +131,20 @@ __global__ __launch_bounds__(1024) void k_batch_lds(const GraphDesc* __restrict_
     }
 }
 
+hipError_t prepare_batch_lds() {
+    // Allows up to 128 KiB of dynamic LDS; set once, outside any capture.
+    static hipError_t once = hipFuncSetAttribute(reinterpret_cast<const void*>(&k_batch_lds),
+                                                 hipFuncAttributeMaxDynamicSharedMemorySize,
+                                                 65536 * 2);
+    return once;
+}
+
 hipError_t launch_batch_lds(const GraphDesc* descs, const int32_t* order, int32_t count,
                             int32_t max_n, int32_t* queue_head, int32_t* status, int grid,
                             hipStream_t s) {
     if (count <= 0) return hipSuccess;
     if (max_n < 1 || max_n > 65536) return hipErrorInvalidValue;
     const size_t lds = (((size_t)max_n + 1) / 2) * 4;  // whole 32-bit words
-    static bool attr_set = false;
-    if (!attr_set) {
-        hipError_t e = hipFuncSetAttribute(reinterpret_cast<const void*>(&k_batch_lds),
-                                           hipFuncAttributeMaxDynamicSharedMemorySize, 65536 * 2);
-        if (e != hipSuccess) return e;
-        attr_set = true;
-    }
     k_batch_lds<<<grid, 1024, lds, s>>>(descs, order, count, queue_head, status);
     return hipGetLastError();
 }

@@ -697,6 +697,22 @@ hipError_t launch_jump(int32_t* pi, int32_t n, Ctrl* ctrl, hipStream_t s) {
     return hipGetLastError();
 }
 
+// ----------------------------------------------------------------------------- zero fill
+// Clears `words` 32-bit words (used instead of a memset so that a captured
+// graph holds kernel nodes only).
+__global__ __launch_bounds__(256) void k_zero(uint32_t* __restrict__ p, int64_t words) {
+    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < words;
+         i += (int64_t)gridDim.x * blockDim.x)
+        p[i] = 0;
+}
+
+hipError_t launch_zero(void* p, int64_t words, hipStream_t s) {
+    if (words <= 0) return hipSuccess;
+    const int grid = (int)std::min<int64_t>(1024, (words + 255) / 256);
+    k_zero<<<grid, 256, 0, s>>>(static_cast<uint32_t*>(p), words);
+    return hipGetLastError();
+}
+
 int device_cu_count() {
     int dev = 0, cus = 0;
     if (hipGetDevice(&dev) != hipSuccess) return 256;

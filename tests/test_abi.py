@@ -93,7 +93,7 @@ def test_host_side_argument_errors(lib):
     assert lib.cc_labels_ex(4, dummy, dummy, 1, dummy, ctypes.byref(bad), None, 0, None,
                             None) == cc.CC_ERR_ARG
     bad = cc._COptions()
-    bad.reserved[1] = 1
+    bad.reserved[0] = 1
     assert lib.cc_labels_ex(4, dummy, dummy, 1, dummy, ctypes.byref(bad), None, 0, None,
                             None) == cc.CC_ERR_ARG
     # batches: offsets are validated on the host

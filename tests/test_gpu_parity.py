@@ -468,3 +468,40 @@ def test_csr_full_size_rmat24(dev):
     for opt in (cc.Options(), cc.Options(symmetric=True)):
         lab = cc.labels_csr(rp, col, n, options=opt).cpu().numpy()
         assert digest(lab) == rec["sha256"]
+
+
+# ----------------------------------------------------------------------------- hipGraph replay
+def test_graph_capture_replays_match_eager(dev):
+    """cc_options.graph captures the launch sequence once and replays it; every
+    replay (with eager work and synchronisations in between) equals the eager
+    result, for single solves (with and without the filter) and for batches."""
+    s = torch.cuda.Stream()
+    u, v, n = graphgen.rmat(17, 16, seed=81, symmetrize=True)
+    want = oracle.labels(u, v, n)
+    du, dv = to_dev(u, dev), to_dev(v, dev)
+    out = torch.empty(n, dtype=torch.int32, device=dev)
+    for opt in (cc.Options(hook="atomic", graph=True),
+                cc.Options(hook="atomic", filter="giant", segments=64, graph=True),
+                cc.Options(hook="atomic", filter="off", segments=3, graph=True)):
+        for rep in range(4):
+            with torch.cuda.stream(s):
+                out.fill_(-1)
+                cc.labels(du, dv, n, out=out, options=opt, stream=s)
+                got = out.cpu().numpy()
+            assert np.array_equal(got, want), rep
+            # eager work between replays
+            assert np.array_equal(cc.labels(du, dv, n).cpu().numpy(), want)
+            torch.cuda.synchronize()
+    bu, bv, vo, eo = graphgen.batch_er(300, seed=82, lo_exp=6, hi_exp=17)
+    bwant = oracle.labels_batch(bu, bv, vo, eo)
+    dbu, dbv = to_dev(bu, dev), to_dev(bv, dev)
+    bout = torch.empty(int(vo[-1]), dtype=torch.int32, device=dev)
+    for rep in range(4):
+        with torch.cuda.stream(s):
+            bout.fill_(-1)
+            cc.labels_batch(dbu, dbv, vo, eo, out=bout, options=cc.Options(graph=True, segments=2),
+                            stream=s)
+            got = bout.cpu().numpy()
+        assert np.array_equal(got, bwant), rep
+        assert np.array_equal(cc.labels_batch(dbu, dbv, vo, eo).cpu().numpy(), bwant)
+        torch.cuda.synchronize()

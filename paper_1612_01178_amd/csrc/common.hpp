@@ -72,5 +72,15 @@ __device__ __forceinline__ int32_t cas_root(int32_t* p, int32_t expected, int32_
                                          __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
     return expected;  // the value found (== the old expected on success)
 }
+// Path-halving re-point of a non-root x to an ancestor a < pi[x] during a
+// kernel that also hooks roots by cas_root.  Every write to pi in such a
+// kernel is an agent-scope read-modify-write: a workgroup-scope store there
+// leaves a dirty line in one XCD's L2 beside roots that other XCDs take by
+// CAS, and on gfx950 that mix has lost hooks (wrong labels, at random, on
+// deep trees).  A minimum never raises the slot, so concurrent re-points of
+// one slot commute and each keeps the slot an ancestor in the same tree.
+__device__ __forceinline__ void halve_to(int32_t* p, int32_t a) {
+    (void)__hip_atomic_fetch_min(p, a, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
 
 }  // namespace hookcc

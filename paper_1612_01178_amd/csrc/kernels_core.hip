@@ -65,9 +65,10 @@ __device__ __forceinline__ void load_edges(const int32_t* __restrict__ p, int64_
 //
 // HALVE (not in the paper): on the way up, a non-root H whose grandparent
 // differs from its parent is re-pointed at the grandparent (path halving, as
-// in sequential union-find).  H is already a non-root, so no CAS on it can
-// succeed any more, and the value stored is an ancestor of H, smaller than
-// H: the tree relation is unchanged and later climbs through H are shorter.
+// in sequential union-find) by an agent-scope atomic minimum (halve_to).  H
+// is already a non-root, so no CAS on it can succeed any more, and the value
+// written is in H's tree and smaller than H: the partition into trees is
+// unchanged and later climbs through H are shorter.
 template <bool COH, bool HALVE>
 __device__ __forceinline__ void atomic_hook(int32_t* pi, int32_t pu, int32_t pv) {
     while (pu != pv) {
@@ -80,7 +81,7 @@ __device__ __forceinline__ void atomic_hook(int32_t* pi, int32_t pu, int32_t pv)
         }
         pu = ld_tree<COH>(pi + found);
         pv = ld_tree<COH>(pi + L);
-        if (HALVE && pu != found) st_tree<COH>(pi + H, pu);
+        if (HALVE && pu != found) halve_to(pi + H, pu);
     }
 }
 

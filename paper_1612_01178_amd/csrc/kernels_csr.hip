@@ -138,7 +138,7 @@ __global__ __launch_bounds__(256) void k_ahook_csr(const int64_t* __restrict__ r
                 }
                 pu = ld_tree<false>(pi + found);
                 pv = ld_tree<false>(pi + L);
-                if (halve && pu != found) st_tree<false>(pi + H, pu);
+                if (halve && pu != found) halve_to(pi + H, pu);
             }
         }
     }

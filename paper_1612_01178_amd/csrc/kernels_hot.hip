@@ -103,7 +103,7 @@ __device__ __forceinline__ void hot_climb(int32_t* pi, int32_t pu, int32_t pv, b
         }
         pu = ld_tree<false>(pi + found);
         pv = ld_tree<false>(pi + L);
-        if (halve && pu != found) st_tree<false>(pi + H, pu);  // path halving
+        if (halve && pu != found) halve_to(pi + H, pu);  // path halving
     }
 }
 

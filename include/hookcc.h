@@ -110,8 +110,10 @@ typedef struct cc_options {
                                  that sampled endpoints hit most often in LDS and answer
                                  those bit tests there                                   */
     int32_t path_halving;     /* Atomic-Hook climb: CC_HALVE_AUTO (default, on), CC_HALVE_ON
-                                 or CC_HALVE_OFF (Fig. 3 exactly) -- re-point each non-root
-                                 passed on the way up at its grandparent                  */
+                                 or CC_HALVE_OFF (Fig. 3 exactly) -- re-point a non-root
+                                 passed on the way up at its grandparent, on every 4th
+                                 such step of a climb (every 8th in the giant-filtered
+                                 and CSR kernels)                                       */
     int32_t symmetric;        /* 1 = the caller guarantees that every pair (u, v) of the list
                                  also appears as (v, u) (a symmetrised list); the Atomic-Hook
                                  then skips the entries with u > v, which changes nothing in
@@ -123,6 +125,14 @@ typedef struct cc_options {
                                  calls with the same arrays, sizes and plan (Atomic-Hook
                                  single solves, graph lists and batches; needs a stream
                                  other than the null stream, else ignored)             */
+    int32_t no_sync;          /* cc_labels_ex and cc_labels_csr only: 1 = enqueue the whole
+                                 solve on the call's stream and return without waiting
+                                 (Atomic-Hook only: CC_HOOK_AUTO then picks it, and
+                                 CC_HOOK_PLAIN or profile = 1 is CC_ERR_ARG).  Argument
+                                 errors still return at once; the device-detected status
+                                 (CC_ERR_RANGE) is read with cc_stream_status.  The
+                                 caller keeps every array alive and unchanged until the
+                                 stream has passed the call.  0 = synchronous (default) */
     int32_t reserved[1];      /* must be zero                                           */
 } cc_options;
 
@@ -182,10 +192,23 @@ int32_t cc_labels(int32_t n, const int32_t* edges_u, const int32_t* edges_v, int
  *   stats            [host] optional statistics output, or NULL
  * The call returns after the labels are complete on `stream` (it ends with
  * one stream synchronisation; the atomic-free Hook also reads the device
- * convergence word once every opts->rounds_per_check rounds). */
+ * convergence word once every opts->rounds_per_check rounds), unless
+ * opts->no_sync = 1: then it returns once the work is enqueued, and the
+ * device-detected status is read with cc_stream_status. */
 int32_t cc_labels_ex(int32_t n, const int32_t* edges_u, const int32_t* edges_v, int64_t m,
                      int32_t* out_label, const cc_options* opts, void* workspace,
                      size_t workspace_bytes, void* stream, cc_stats* stats);
+
+/* Device-detected status of the last cc_labels_ex / cc_labels_csr call made on
+ * `stream` (NULL = null stream) of the current device with opts->no_sync = 1:
+ * CC_PENDING while that call's work has not finished, then CC_OK or
+ * CC_ERR_RANGE (an endpoint outside [0, n) or a malformed row_ptr; the labels
+ * are then unspecified).  Non-blocking.  CC_ERR_ARG when no such call was made
+ * since the last cc_release.  Calls that fail before enqueuing work leave the
+ * recorded status unchanged.  One status per stream: a later no-sync call on
+ * the stream replaces it, so read it before the next one if it matters. */
+#define CC_PENDING 1
+int32_t cc_stream_status(void* stream);
 
 /* Device scratch bytes cc_labels_ex needs for (n, m, opts); 0 on bad input. */
 size_t cc_workspace_bytes(int32_t n, int64_t m, const cc_options* opts);
@@ -250,9 +273,10 @@ int32_t cc_labels_host(int32_t n, const int32_t* host_u, const int32_t* host_v, 
  *   out_label  [device] int32[n]
  *   opts       as cc_labels_ex (hook must be CC_HOOK_AUTO or CC_HOOK_ATOMIC);
  *              opts->symmetric = 1 promises a symmetric adjacency (every pair in
- *              both rows) and hooks only the entries with col < row
- * Synchronous on `stream` (NULL = null stream).  A malformed row_ptr or a
- * column id outside [0, n) returns CC_ERR_RANGE (checked on the device). */
+ *              both rows) and hooks only the entries with col > row
+ * Synchronous on `stream` (NULL = null stream) unless opts->no_sync = 1 (as
+ * for cc_labels_ex).  A malformed row_ptr or a column id outside [0, n)
+ * returns CC_ERR_RANGE (checked on the device). */
 int32_t cc_labels_csr(int32_t n, const int64_t* row_ptr, const int32_t* col, int64_t m,
                       int32_t* out_label, const cc_options* opts, void* stream, cc_stats* stats);
 

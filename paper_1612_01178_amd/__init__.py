@@ -37,7 +37,7 @@ _HOST_LOOPS = {"off": 0, "jump": 1, "multijump": 2}
 # Every symbol include/hookcc.h declares.
 EXPORTS = ("cc_options_init", "cc_labels", "cc_labels_ex", "cc_workspace_bytes",
            "cc_labels_batch", "cc_labels_batch_ex", "cc_labels_list", "cc_labels_host", "cc_labels_csr", "cc_probe",
-           "cc_last_error", "cc_release", "cc_version", "cc_server_create",
+           "cc_last_error", "cc_release", "cc_version", "cc_stream_status", "cc_server_create",
            "cc_server_submit", "cc_server_wait", "cc_server_poll", "cc_server_stats",
            "cc_server_destroy", "cc_server_clock")
 CC_REQ_HOST_EDGES = 1
@@ -58,7 +58,8 @@ class _COptions(ctypes.Structure):
                 ("profile", ctypes.c_int32), ("host_loop", ctypes.c_int32),
                 ("coherent_loads", ctypes.c_int32), ("hot_cache", ctypes.c_int32),
                 ("path_halving", ctypes.c_int32), ("symmetric", ctypes.c_int32),
-                ("graph", ctypes.c_int32), ("reserved", ctypes.c_int32 * 1)]
+                ("graph", ctypes.c_int32), ("no_sync", ctypes.c_int32),
+                ("reserved", ctypes.c_int32 * 1)]
 
 
 class _CStats(ctypes.Structure):
@@ -108,6 +109,7 @@ class Options:
     path_halving: str = "auto"
     symmetric: bool = False
     graph: bool = False
+    no_sync: bool = False
 
     def _c(self) -> _COptions:
         o = _COptions()
@@ -126,6 +128,7 @@ class Options:
         o.path_halving = {"auto": 0, "on": 1, "off": 2}[self.path_halving]
         o.symmetric = 1 if self.symmetric else 0
         o.graph = 1 if self.graph else 0
+        o.no_sync = 1 if self.no_sync else 0
         return o
 
 
@@ -191,6 +194,8 @@ def load():
             lib.cc_last_error.restype = ctypes.c_char_p
             lib.cc_release.argtypes = []
             lib.cc_release.restype = None
+            lib.cc_stream_status.argtypes = [_vp]
+            lib.cc_stream_status.restype = _i32
             lib.cc_version.argtypes = []
             lib.cc_version.restype = ctypes.c_char_p
             _lib = lib
@@ -207,6 +212,20 @@ def version() -> str:
 
 def release() -> None:
     load().cc_release()
+
+
+CC_PENDING = 1
+
+
+def stream_status(stream=None) -> int:
+    """Status of the last ``no_sync`` call on ``stream`` (default: the current
+    torch stream): CC_PENDING while its work runs, then 0; raises CCError for
+    a device-detected error (CC_ERR_RANGE) or when no such call was made."""
+    rc = int(load().cc_stream_status(_stream_handle(stream)))
+    if rc == CC_PENDING:
+        return rc
+    _check(rc)
+    return rc
 
 
 def _check(rc: int) -> None:

@@ -69,6 +69,8 @@ const char* cc_last_error(void) { return last_error(); }
 
 void cc_release(void) { release_impl(); }
 
+int32_t cc_stream_status(void* stream) { return stream_status_impl(static_cast<hipStream_t>(stream)); }
+
 const char* cc_version(void) { return "hookcc 0.2 (gfx950)"; }
 
 }  // extern "C"

@@ -72,15 +72,26 @@ __device__ __forceinline__ int32_t cas_root(int32_t* p, int32_t expected, int32_
                                          __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
     return expected;  // the value found (== the old expected on success)
 }
-// Path-halving re-point of a non-root x to an ancestor a < pi[x] during a
-// kernel that also hooks roots by cas_root.  Every write to pi in such a
-// kernel is an agent-scope read-modify-write: a workgroup-scope store there
-// leaves a dirty line in one XCD's L2 beside roots that other XCDs take by
-// CAS, and on gfx950 that mix has lost hooks (wrong labels, at random, on
-// deep trees).  A minimum never raises the slot, so concurrent re-points of
-// one slot commute and each keeps the slot an ancestor in the same tree.
+// Path-halving re-point of a non-root x to a vertex a < x of its tree during
+// a kernel that also hooks roots by cas_root.  Every write to pi in such a
+// kernel is of agent scope, like the CAS: a workgroup-scope store there (a
+// write-back line in one XCD's L2) races with the agent-scope CAS of other
+// XCDs on the same words, and on gfx950 that mix has lost hooks (wrong
+// labels, at random, on deep trees).  Concurrent re-points of one slot may
+// land in any order: each value is in the slot's tree and below its index,
+// so the partition into trees and the termination argument do not depend on
+// which one stays.
 __device__ __forceinline__ void halve_to(int32_t* p, int32_t a) {
-    (void)__hip_atomic_fetch_min(p, a, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    __hip_atomic_store(p, a, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
 }
+// A climb re-points on one of every kHalveEvery* of its steps that can
+// re-point (steps 1, 1 + k, 1 + 2k, ...): an agent-scope store goes past
+// the L2, so fewer of them is faster until the trees grow deep enough to
+// lengthen the climbs and the Multi-Jump.  Measured on gfx950: every 4th
+// step for the unfiltered Atomic-Hook (percolated 4096^2 grid: 1.10 ms
+// against 1.17 every 2nd and 1.33 every 16th), every 8th for the filtered
+// kernels, whose climbs start from stars (R-MAT 24: 4.63 ms against 4.67).
+constexpr uint32_t kHalveEveryCore = 4;
+constexpr uint32_t kHalveEveryFiltered = 8;
 
 }  // namespace hookcc

@@ -62,6 +62,7 @@ struct Plan {
     bool halve = true;  // path halving in the Atomic-Hook climb
     bool symmetric = false;  // caller promises both orientations of every pair
     bool graph = false;      // capture the launch sequence in a hipGraph and replay it
+    bool no_sync = false;    // enqueue only; status read later by cc_stream_status
 };
 
 int32_t make_plan(int32_t n, int64_t m, const cc_options* o, Plan& p, bool allow_plain = true) {
@@ -72,6 +73,9 @@ int32_t make_plan(int32_t n, int64_t m, const cc_options* o, Plan& p, bool allow
     if (op.reserved[0] != 0) return fail(CC_ERR_ARG, "cc_options.reserved must be zero");
     if (op.graph != 0 && op.graph != 1) return fail(CC_ERR_ARG, "cc_options.graph must be 0 or 1");
     p.graph = op.graph == 1;
+    if (op.no_sync != 0 && op.no_sync != 1)
+        return fail(CC_ERR_ARG, "cc_options.no_sync must be 0 or 1");
+    p.no_sync = op.no_sync == 1;
     if (op.symmetric != 0 && op.symmetric != 1)
         return fail(CC_ERR_ARG, "cc_options.symmetric must be 0 or 1");
     p.symmetric = op.symmetric == 1;
@@ -100,7 +104,7 @@ int32_t make_plan(int32_t n, int64_t m, const cc_options* o, Plan& p, bool allow
     const bool dense_large = large && n > 0 && m >= 8 * (int64_t)n;
     bool auto_filtered = false;
     if (op.hook == CC_HOOK_AUTO) {
-        if (large || !allow_plain || op.symmetric == 1) {
+        if (large || !allow_plain || op.symmetric == 1 || op.no_sync == 1) {
             p.hook = CC_HOOK_ATOMIC;
             auto_filtered = dense_large && op.filter != CC_FILTER_OFF;
         } else {
@@ -162,6 +166,10 @@ int32_t make_plan(int32_t n, int64_t m, const cc_options* o, Plan& p, bool allow
         return fail(CC_ERR_ARG, "cc_options.symmetric needs the Atomic-Hook");
     if (p.hook == CC_HOOK_PLAIN && m >= (int64_t(1) << 32))
         return fail(CC_ERR_ARG, "atomic-free Hook supports m < 2^32 entries");
+    if (p.no_sync && (p.hook != CC_HOOK_ATOMIC || p.profile))
+        return fail(CC_ERR_ARG,
+                    "cc_options.no_sync needs the Atomic-Hook (the atomic-free Hook reads the "
+                    "device convergence word from the host) and profile = 0");
     return CC_OK;
 }
 
@@ -210,6 +218,10 @@ struct PoolEntry {
     hipStream_t copy_stream = nullptr;  // host-to-device staging of streamed solves
     hipEvent_t copied[2] = {nullptr, nullptr};
     hipEvent_t consumed[2] = {nullptr, nullptr};
+    // status word of the last no-sync call (pinned) and the event after its copy
+    int32_t* async_slot = nullptr;
+    hipEvent_t async_done = nullptr;
+    bool async_called = false;
     // captured launch sequences of recent calls, most recent last
     struct Captured {
         uint64_t key;
@@ -219,7 +231,14 @@ struct PoolEntry {
     std::vector<Captured> graphs;
 };
 
+// Waits for the work of earlier no-sync calls on this entry's stream (before
+// a buffer or a graph that work may still use is freed).
+void drain_async(PoolEntry* e) {
+    if (e->async_called && e->async_done) (void)hipEventSynchronize(e->async_done);
+}
+
 void drop_graphs(PoolEntry* e) {
+    if (!e->graphs.empty()) drain_async(e);
     for (auto& c : e->graphs) {
         (void)hipGraphExecDestroy(c.exec);
         (void)hipGraphDestroy(c.graph);
@@ -258,6 +277,7 @@ PoolEntry* pool_entry(hipStream_t s) {
 int32_t ensure_dev(PoolEntry* e, size_t bytes) {
     if (e->bytes >= bytes && e->dev) return CC_OK;
     drop_graphs(e);  // captured graphs point into the old buffer
+    drain_async(e);
     if (e->dev) {
         HIPCHK(hipFree(e->dev));
         e->dev = nullptr;
@@ -373,6 +393,7 @@ int32_t run_graph(PoolEntry* pe, uint64_t key, hipStream_t s, F&& enqueue) {
             return fail(CC_ERR_HIP, std::string("graph instantiate: ") + hipGetErrorString(e));
         }
         if (pe->graphs.size() >= 8) {
+            drain_async(pe);
             (void)hipGraphExecDestroy(pe->graphs.front().exec);
             (void)hipGraphDestroy(pe->graphs.front().graph);
             pe->graphs.erase(pe->graphs.begin());
@@ -391,6 +412,18 @@ int32_t finish(hipStream_t s, Ctrl* dctrl, Ctrl* hctrl, cc_stats* st) {
     if (st) st->host_syncs += 1;
     return CC_OK;
 }
+
+// No-sync end of a call: the status word is copied to the entry's pinned slot
+// and an event recorded after it; cc_stream_status reads both later.
+int32_t post_async(PoolEntry* e, hipStream_t s, const Ctrl* dctrl) {
+    if (!e->async_slot) HIPCHK(hipHostMalloc((void**)&e->async_slot, 256, hipHostMallocDefault));
+    if (!e->async_done) HIPCHK(hipEventCreateWithFlags(&e->async_done, hipEventDisableTiming));
+    HIPCHK(hipMemcpyAsync(e->async_slot, &dctrl->status, sizeof(int32_t), hipMemcpyDeviceToHost, s));
+    HIPCHK(hipEventRecord(e->async_done, s));
+    e->async_called = true;
+    return CC_OK;
+}
+
 
 // Enqueues the Atomic-Hook solve (Fig. 4) of one graph on s; no synchronisation.
 // `ctrl` is the graph's control block, `bits` its giant bitmap (filter plans).
@@ -643,6 +676,11 @@ int32_t labels_impl(int32_t n, const int32_t* u, const int32_t* v, int64_t m, in
             rc = enqueue_atomic(n, u, v, m, out, p, reinterpret_cast<Ctrl*>(ws), filter_bufs(ws, L),
                                 s, tm, st);
         }
+        if (rc == CC_OK && p.no_sync) {
+            rc = post_async(pe, s, reinterpret_cast<const Ctrl*>(ws));
+            if (st) st->giant_label = -1;  // not known without a synchronisation
+            return rc;
+        }
         if (rc == CC_OK) rc = finish(s, reinterpret_cast<Ctrl*>(ws), pe->host_ctrl, st);
     } else if (p.host_loop != CC_HOST_LOOP_OFF) {
         rc = solve_host_loop(n, u, v, m, out, p, ws, s, pe->host_ctrl, tm, st);
@@ -685,6 +723,8 @@ int32_t stream_impl(int32_t n, const int32_t* hu, const int32_t* hv, int64_t m, 
     chunk = std::max<int64_t>(4, chunk & ~int64_t(3));
     if (opts && opts->hook == CC_HOOK_PLAIN)
         return fail(CC_ERR_ARG, "streamed solves use the Atomic-Hook (each entry is read once)");
+    if (opts && opts->no_sync)
+        return fail(CC_ERR_ARG, "cc_options.no_sync is for cc_labels_ex and cc_labels_csr only");
     Plan p;
     rc = make_plan(n, m, opts, p, /*allow_plain=*/false);
     if (rc != CC_OK) return rc;
@@ -840,6 +880,13 @@ int32_t csr_impl(int32_t n, const int64_t* row_ptr, const int32_t* col, int64_t 
             step *= 2;
         }
     }
+    if (p.no_sync) {
+        if (st) {
+            st->hook_launches = hooks;
+            st->compress_launches = jumps;
+        }
+        return post_async(pe, s, ctrl);
+    }
     rc = finish(s, ctrl, pe->host_ctrl, st);
     if (rc != CC_OK) return rc;
     tm.collect(st);
@@ -869,6 +916,8 @@ size_t workspace_bytes_impl(int32_t n, int64_t m, const cc_options* opts) {
 int32_t list_impl(int32_t count, const cc_graph* graphs, const cc_options* opts, hipStream_t s,
                   cc_stats* st) {
     if (count < 0) return fail(CC_ERR_ARG, "graph count < 0");
+    if (opts && opts->no_sync)
+        return fail(CC_ERR_ARG, "cc_options.no_sync is for cc_labels_ex and cc_labels_csr only");
     // Per-graph segment count of the LDS solver: 0 = the paper's round(m/n);
     // S > 0 = min(S, that).  In LDS a climb costs LDS latency, not a trip to
     // device memory, so fewer segments (fewer barriers) usually pay.
@@ -1005,6 +1054,8 @@ int32_t batch_impl(int32_t B, const int64_t* vo, const int64_t* eo, const int32_
                    const int32_t* v, int32_t* out, const cc_options* opts, hipStream_t s,
                    cc_stats* st) {
     if (B < 0) return fail(CC_ERR_ARG, "num_graphs < 0");
+    if (opts && opts->no_sync)
+        return fail(CC_ERR_ARG, "cc_options.no_sync is for cc_labels_ex and cc_labels_csr only");
     if (B == 0) {
         if (st) {
             std::memset(st, 0, sizeof *st);
@@ -1063,7 +1114,13 @@ void release_impl() {
     for (auto& kv : g_pool) {
         PoolEntry* e = kv.second.get();
         std::lock_guard<std::mutex> lk(e->mu);
+        drain_async(e);
         drop_graphs(e);
+        if (e->async_done) (void)hipEventDestroy(e->async_done);
+        if (e->async_slot) (void)hipHostFree(e->async_slot);
+        e->async_done = nullptr;
+        e->async_slot = nullptr;
+        e->async_called = false;
         for (int i = 0; i < 2; ++i) {
             if (e->copied[i]) (void)hipEventDestroy(e->copied[i]);
             if (e->consumed[i]) (void)hipEventDestroy(e->consumed[i]);
@@ -1081,6 +1138,27 @@ void release_impl() {
         e->host_ctrl_count = 0;
     }
     g_pool.clear();
+}
+
+int32_t stream_status_impl(hipStream_t s) {
+    int dev = 0;
+    if (hipGetDevice(&dev) != hipSuccess) dev = -1;
+    PoolEntry* e = nullptr;
+    {
+        std::lock_guard<std::mutex> g(g_pool_mu);
+        auto it = g_pool.find({dev, s});
+        if (it != g_pool.end()) e = it->second.get();
+    }
+    if (!e) return fail(CC_ERR_ARG, "no no-sync call on this stream and device");
+    std::lock_guard<std::mutex> lk(e->mu);
+    if (!e->async_called) return fail(CC_ERR_ARG, "no no-sync call on this stream and device");
+    const hipError_t q = hipEventQuery(e->async_done);
+    if (q == hipErrorNotReady) return CC_PENDING;
+    if (q != hipSuccess) return fail(CC_ERR_HIP, std::string("hipEventQuery: ") + hipGetErrorString(q));
+    const int32_t status = *reinterpret_cast<volatile int32_t*>(e->async_slot);
+    if (status & kStatusRange) return fail(CC_ERR_RANGE, "edge endpoint outside [0, n)");
+    if (status & kStatusOverflow) return fail(CC_ERR_NOMEM, "frontier capacity exceeded");
+    return CC_OK;
 }
 
 }  // namespace hookcc

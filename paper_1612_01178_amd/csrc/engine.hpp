@@ -41,5 +41,7 @@ int32_t csr_impl(int32_t n, const int64_t* row_ptr, const int32_t* col, int64_t 
 int32_t probe_impl(int32_t mode, const int32_t* u, const int32_t* v, int64_t m, const void* table,
                    int32_t n, hipStream_t s);
 void release_impl();
+// Status of the last no-sync call on s (see cc_stream_status).
+int32_t stream_status_impl(hipStream_t s);
 
 }  // namespace hookcc

@@ -65,12 +65,14 @@ __device__ __forceinline__ void load_edges(const int32_t* __restrict__ p, int64_
 //
 // HALVE (not in the paper): on the way up, a non-root H whose grandparent
 // differs from its parent is re-pointed at the grandparent (path halving, as
-// in sequential union-find) by an agent-scope atomic minimum (halve_to).  H
+// in sequential union-find; here on every kHalveEveryCore-th such step) by an
+// agent-scope store (halve_to).  H
 // is already a non-root, so no CAS on it can succeed any more, and the value
 // written is in H's tree and smaller than H: the partition into trees is
 // unchanged and later climbs through H are shorter.
 template <bool COH, bool HALVE>
 __device__ __forceinline__ void atomic_hook(int32_t* pi, int32_t pu, int32_t pv) {
+    uint32_t step = 0;
     while (pu != pv) {
         const int32_t H = pu > pv ? pu : pv;
         const int32_t L = pu > pv ? pv : pu;
@@ -81,7 +83,7 @@ __device__ __forceinline__ void atomic_hook(int32_t* pi, int32_t pu, int32_t pv)
         }
         pu = ld_tree<COH>(pi + found);
         pv = ld_tree<COH>(pi + L);
-        if (HALVE && pu != found) halve_to(pi + H, pu);
+        if (HALVE && pu != found && step++ % kHalveEveryCore == 0) halve_to(pi + H, pu);
     }
 }
 

@@ -15,7 +15,12 @@
 // consecutive entries (they nearly always share the row) instead of once
 // per entry: on a skewed CSR graph the per-entry cost drops to one bit test.
 // `sym`: the adjacency is symmetric (every pair stored in both rows), so
-// only the entries with col < row are hooked.
+// only the entries with col > row are hooked: the copy of each pair kept is
+// the one in the smaller endpoint's row, so the first segments (the first
+// rows) already join the low ids to the whole graph and the giant component
+// forms before the filter samples for it.  Keeping col < row instead hooks
+// only pairs inside the row prefix seen so far, and the filter finds no
+// giant until late.
 #include "kernels.hpp"
 
 namespace hookcc {
@@ -92,7 +97,7 @@ __global__ __launch_bounds__(256) void k_ahook_csr(const int64_t* __restrict__ r
             b[j] = __builtin_nontemporal_load(col + e);
             const bool in = (uint32_t)b[j] < (uint32_t)n;
             bad |= !in;
-            if (in && a[j] != b[j] && !(sym && b[j] > a[j])) act |= 1u << j;
+            if (in && a[j] != b[j] && !(sym && b[j] < a[j])) act |= 1u << j;
         }
         if (!act) continue;
         int32_t pa[4], pb[4];
@@ -126,6 +131,7 @@ __global__ __launch_bounds__(256) void k_ahook_csr(const int64_t* __restrict__ r
         for (int j = 0; j < 4; ++j) {
             if (!(act >> j & 1)) continue;
             int32_t pu = pa[j], pv = pb[j];
+            uint32_t step = 0;
             // Atomic-Hook climb (Fig. 3, top) with optional path halving; see
             // atomic_hook in kernels_core.hip for why it is correct and finite.
             while (pu != pv) {
@@ -138,7 +144,8 @@ __global__ __launch_bounds__(256) void k_ahook_csr(const int64_t* __restrict__ r
                 }
                 pu = ld_tree<false>(pi + found);
                 pv = ld_tree<false>(pi + L);
-                if (halve && pu != found) halve_to(pi + H, pu);
+                if (halve && pu != found && step++ % kHalveEveryFiltered == 0)
+                    halve_to(pi + H, pu);
             }
         }
     }

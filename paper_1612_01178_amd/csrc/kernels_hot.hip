@@ -93,6 +93,7 @@ __device__ __forceinline__ void load_tile(const int32_t* __restrict__ p, int64_t
 // Atomic-Hook climb (Fig. 3, top), cached loads; see atomic_hook in
 // kernels_core.hip for the argument.
 __device__ __forceinline__ void hot_climb(int32_t* pi, int32_t pu, int32_t pv, bool halve) {
+    uint32_t step = 0;
     while (pu != pv) {
         const int32_t H = pu > pv ? pu : pv;
         const int32_t L = pu > pv ? pv : pu;
@@ -103,7 +104,8 @@ __device__ __forceinline__ void hot_climb(int32_t* pi, int32_t pu, int32_t pv, b
         }
         pu = ld_tree<false>(pi + found);
         pv = ld_tree<false>(pi + L);
-        if (halve && pu != found) halve_to(pi + H, pu);  // path halving
+        if (halve && pu != found && step++ % kHalveEveryFiltered == 0)
+            halve_to(pi + H, pu);  // path halving
     }
 }
 

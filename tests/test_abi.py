@@ -96,6 +96,24 @@ def test_host_side_argument_errors(lib):
     bad.reserved[0] = 1
     assert lib.cc_labels_ex(4, dummy, dummy, 1, dummy, ctypes.byref(bad), None, 0, None,
                             None) == cc.CC_ERR_ARG
+    # no_sync: Atomic-Hook only, no profiling, single solves only
+    for field, value in (("hook", 2), ("profile", 1)):
+        bad = cc._COptions()
+        bad.no_sync = 1
+        setattr(bad, field, value)
+        assert lib.cc_labels_ex(4, dummy, dummy, 1, dummy, ctypes.byref(bad), None, 0, None,
+                                None) == cc.CC_ERR_ARG, field
+    bad = cc._COptions()
+    bad.no_sync = 2
+    assert lib.cc_labels_ex(4, dummy, dummy, 1, dummy, ctypes.byref(bad), None, 0, None,
+                            None) == cc.CC_ERR_ARG
+    bad = cc._COptions()
+    bad.no_sync = 1
+    assert lib.cc_labels_host(4, dummy, dummy, 1, dummy, 0, ctypes.byref(bad), None,
+                              None) == cc.CC_ERR_ARG
+    assert lib.cc_labels_list(0, None, ctypes.byref(bad), None, None) == cc.CC_ERR_ARG
+    # no no-sync call was made on this stream
+    assert lib.cc_stream_status(None) == cc.CC_ERR_ARG
     # batches: offsets are validated on the host
     import numpy as np
     vo = np.array([0, 4, 3], dtype=np.int64)

@@ -472,7 +472,16 @@ def test_csr_input_matches_oracle(dev):
             got = cc.labels_csr(drp, dcol, n, options=opt).cpu().numpy()
             assert np.array_equal(got, want), (name, opt)
         if name == "rmat_sym":
-            got = cc.labels_csr(drp, dcol, n, options=cc.Options(symmetric=True)).cpu().numpy()
+            for opt in (cc.Options(symmetric=True),
+                        cc.Options(symmetric=True, filter="giant", segments=8)):
+                got = cc.labels_csr(drp, dcol, n, options=opt).cpu().numpy()
+                assert np.array_equal(got, want)
+            # the flag hooks exactly the entries with col > row: an adjacency
+            # holding only those gives the same labels
+            keep = v > u
+            rp2, col2 = _to_csr(u[keep], v[keep], n)
+            got = cc.labels_csr(torch.from_numpy(rp2).to(dev), to_dev(col2, dev), n,
+                                options=cc.Options(symmetric=True)).cpu().numpy()
             assert np.array_equal(got, want)
 
 
@@ -503,6 +512,59 @@ def test_csr_full_size_rmat24(dev):
     for opt in (cc.Options(), cc.Options(symmetric=True)):
         lab = cc.labels_csr(rp, col, n, options=opt).cpu().numpy()
         assert digest(lab) == rec["sha256"]
+
+
+# ----------------------------------------------------------------------------- no-sync calls
+def test_no_sync_calls_queue_on_the_stream(dev):
+    """opts.no_sync enqueues the solve and returns; several solves queued on one
+    stream give the oracle's labels once the stream has passed them, and the
+    device-detected status is read with cc_stream_status."""
+    graphs = [graphgen.rmat(14, 8, seed=500 + i) for i in range(3)]
+    graphs.append(graphgen.grid(300, 200, 1, 2, seed=510))
+    want = [oracle.labels(u, v, n) for u, v, n in graphs]
+    tens = [(to_dev(u, dev), to_dev(v, dev), n) for u, v, n in graphs]
+    outs = [torch.empty(n, dtype=torch.int32, device=dev) for _, _, n in graphs]
+    s = torch.cuda.Stream()
+    torch.cuda.synchronize()
+    with torch.cuda.stream(s):
+        for opt in (cc.Options(no_sync=True),
+                    cc.Options(no_sync=True, filter="giant", segments=8),
+                    cc.Options(no_sync=True, graph=True)):
+            for o in outs:
+                o.fill_(-7)
+            torch.cuda.synchronize()
+            for (du, dv, n), o in zip(tens, outs):
+                cc.labels(du, dv, n, out=o, options=opt, stream=s)
+            assert cc.stream_status(s) in (0, cc.CC_PENDING)
+            s.synchronize()
+            assert cc.stream_status(s) == 0
+            for o, w in zip(outs, want):
+                assert np.array_equal(o.cpu().numpy(), w)
+        # a range error is reported by the status, and the next call clears it
+        bad_u = to_dev(np.array([0, 1, 9], np.int32), dev)
+        bad_v = to_dev(np.array([1, 2, 3], np.int32), dev)
+        o5 = torch.empty(5, dtype=torch.int32, device=dev)
+        cc.labels(bad_u, bad_v, 5, out=o5, options=cc.Options(no_sync=True), stream=s)
+        s.synchronize()
+        with pytest.raises(cc.CCError) as ei:
+            cc.stream_status(s)
+        assert ei.value.code == cc.CC_ERR_RANGE
+        du, dv, n = tens[0]
+        cc.labels(du, dv, n, out=outs[0], options=cc.Options(no_sync=True), stream=s)
+        s.synchronize()
+        assert cc.stream_status(s) == 0
+        assert np.array_equal(outs[0].cpu().numpy(), want[0])
+        # CSR input
+        u, v, n = graphs[0]
+        rp, col = _to_csr(u, v, n)
+        o = torch.empty(n, dtype=torch.int32, device=dev)
+        drp, dcol = torch.from_numpy(rp).to(dev), to_dev(col, dev)  # alive until the sync
+        cc.labels_csr(drp, dcol, n, out=o, options=cc.Options(no_sync=True), stream=s)
+        s.synchronize()
+        assert cc.stream_status(s) == 0
+        assert np.array_equal(o.cpu().numpy(), want[0])
+        with pytest.raises(cc.CCError):
+            cc.labels(du, dv, n, options=cc.Options(no_sync=True, hook="plain"), stream=s)
 
 
 # ----------------------------------------------------------------------------- hipGraph replay

@@ -237,6 +237,8 @@ ABLATION = [
                                    hot_cache="off")),
     ("giant_filter_hot_halving", dict(hook="atomic", filter="giant")),
     ("plain_device_convergence", dict(hook="plain")),
+    ("plain_tau500", dict(hook="plain", compact_threshold=500)),
+    ("plain_tau100", dict(hook="plain", compact_threshold=100)),
     ("library_auto", dict()),
 ]
 SEGMENT_SWEEP = [1, 2, 4, 8, 16, 32, 64, 128]

@@ -133,6 +133,14 @@ typedef struct cc_options {
                                  (CC_ERR_RANGE) is read with cc_stream_status.  The
                                  caller keeps every array alive and unchanged until the
                                  stream has passed the call.  0 = synchronous (default) */
+    int32_t compact_threshold; /* atomic-free Hook: frontier compaction threshold tau in
+                                 thousandths, 0..1000.  Every round counts the entries
+                                 still active after its Compress; round 1 always writes
+                                 them to a frontier of root pairs, and a later round
+                                 rewrites them only when the previous round's surviving
+                                 fraction (active entries / entries read) was below
+                                 tau / 1000 -- otherwise the next round reads the same
+                                 frontier again.  0 = default: rewrite every round     */
     int32_t reserved[1];      /* must be zero                                           */
 } cc_options;
 

@@ -59,7 +59,7 @@ class _COptions(ctypes.Structure):
                 ("coherent_loads", ctypes.c_int32), ("hot_cache", ctypes.c_int32),
                 ("path_halving", ctypes.c_int32), ("symmetric", ctypes.c_int32),
                 ("graph", ctypes.c_int32), ("no_sync", ctypes.c_int32),
-                ("reserved", ctypes.c_int32 * 1)]
+                ("compact_threshold", ctypes.c_int32), ("reserved", ctypes.c_int32 * 1)]
 
 
 class _CStats(ctypes.Structure):
@@ -110,6 +110,7 @@ class Options:
     symmetric: bool = False
     graph: bool = False
     no_sync: bool = False
+    compact_threshold: int = 0
 
     def _c(self) -> _COptions:
         o = _COptions()
@@ -129,6 +130,7 @@ class Options:
         o.symmetric = 1 if self.symmetric else 0
         o.graph = 1 if self.graph else 0
         o.no_sync = 1 if self.no_sync else 0
+        o.compact_threshold = self.compact_threshold
         return o
 
 

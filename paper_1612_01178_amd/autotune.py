@@ -10,7 +10,10 @@ coordinate by coordinate from the library's default:
    s = round(m / n) (Section 3.B) and multiples of it, with and without the
    giant-component filter, plus the atomic-free Hook;
 2. edge entries per thread (4, 8, 16);
-3. threads per workgroup (256, 512, 1024).
+3. threads per workgroup (256, 512, 1024);
+4. when the atomic-free Hook wins, the frontier compaction threshold tau
+   (rewrite the frontier every round, or only below a surviving fraction of
+   50 %, 25 %, 10 %).
 
 Results are cached in a JSON file keyed by device architecture and a shape
 bucket (log2 n, m/n rounded to a power of two), so graphs of a similar shape
@@ -108,8 +111,12 @@ def tune(u, v, n: int, *, reps: int = 3, cache: bool = True, path: str | None = 
         t = run(c)
         if t < best_t:
             best_t, best = t, c
-    # 2. entries per thread, 3. workgroup size
-    for field, values in (("edges_per_thread", (4, 8, 16)), ("block", (256, 512, 1024))):
+    # 2. entries per thread, 3. workgroup size, 4. (atomic-free Hook) frontier
+    # compaction threshold tau in thousandths (0 = rewrite every round)
+    sweeps = [("edges_per_thread", (4, 8, 16)), ("block", (256, 512, 1024))]
+    if best.hook == "plain" or (best.hook == "auto" and m < (1 << 22)):
+        sweeps.append(("compact_threshold", (0, 500, 250, 100)))
+    for field, values in sweeps:
         for val in values:
             c = Options(**{**best.__dict__, field: val})
             t = run(c)

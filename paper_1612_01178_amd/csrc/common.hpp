@@ -22,7 +22,11 @@ struct Ctrl {
     int64_t active_round1;  // atomic-free Hook: frontier size after round 1
     int32_t hook_changed;   // host-loop form of Fig. 1: a Hook pass found an active edge
     int32_t jump_changed;   // host-loop form of Fig. 1: a Jump pass moved a pointer
-    int32_t pad[52];
+    // atomic-free Hook, by round parity r & 1 (written by round r's compaction):
+    int32_t fsel[2];        // where round r's source is: frontier buffer 0 / 1, or 2 = input lists
+    uint32_t fsize[2];      // round r's source size
+    int32_t fwrote[2];      // 1 = round r wrote its survivors to the other buffer
+    int32_t pad[46];
 };
 static_assert(sizeof(Ctrl) == 256, "control block is one 256-byte line");
 

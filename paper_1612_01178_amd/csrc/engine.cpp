@@ -63,6 +63,7 @@ struct Plan {
     bool symmetric = false;  // caller promises both orientations of every pair
     bool graph = false;      // capture the launch sequence in a hipGraph and replay it
     bool no_sync = false;    // enqueue only; status read later by cc_stream_status
+    uint32_t tau = 0xffffffffu;  // atomic-free Hook: frontier rewrite threshold (1/1000)
 };
 
 int32_t make_plan(int32_t n, int64_t m, const cc_options* o, Plan& p, bool allow_plain = true) {
@@ -76,6 +77,9 @@ int32_t make_plan(int32_t n, int64_t m, const cc_options* o, Plan& p, bool allow
     if (op.no_sync != 0 && op.no_sync != 1)
         return fail(CC_ERR_ARG, "cc_options.no_sync must be 0 or 1");
     p.no_sync = op.no_sync == 1;
+    if (op.compact_threshold < 0 || op.compact_threshold > 1000)
+        return fail(CC_ERR_ARG, "cc_options.compact_threshold must be in [0, 1000]");
+    p.tau = op.compact_threshold ? (uint32_t)op.compact_threshold : 0xffffffffu;
     if (op.symmetric != 0 && op.symmetric != 1)
         return fail(CC_ERR_ARG, "cc_options.symmetric must be 0 or 1");
     p.symmetric = op.symmetric == 1;
@@ -520,7 +524,8 @@ int32_t solve_plain(int32_t n, const int32_t* u, const int32_t* v, int64_t m, in
                     const Plan& p, char* ws, const Layout& L, hipStream_t s, Ctrl* hctrl,
                     Timer& tm, cc_stats* st, int64_t* rounds_run) {
     Ctrl* ctrl = reinterpret_cast<Ctrl*>(ws);
-    int2* F[2] = {reinterpret_cast<int2*>(ws + L.f0), reinterpret_cast<int2*>(ws + L.f1)};
+    int2* F0 = reinterpret_cast<int2*>(ws + L.f0);
+    int2* F1 = reinterpret_cast<int2*>(ws + L.f1);
     const int grid_cap = device_cu_count() * 8;
     TIMED(kPhaseOther, launch_init(pi, n, ctrl, s));
     int64_t r = 0;
@@ -528,15 +533,15 @@ int32_t solve_plain(int32_t n, const int32_t* u, const int32_t* v, int64_t m, in
     while (true) {
         for (int k = 0; k < p.rounds_per_check; ++k) {
             ++r;
-            const int2* src = F[(r - 1) & 1];
-            int2* dst = F[r & 1];
+            // sources and sizes are chosen on the device (round_src); the
+            // grid covers the capacity and loops over what is there
             const int64_t work = (r == 1) ? m : L.cap;
-            TIMED(kPhaseHook, launch_hook_plain((int)r, u, v, work, src, pi, n, ctrl, p.block,
+            TIMED(kPhaseHook, launch_hook_plain((int)r, u, v, work, F0, F1, pi, n, ctrl, p.block,
                                                 p.ept, grid_cap, s));
             TIMED(kPhaseCompress,
                   launch_mj(pi, n, r == 1 ? nullptr : &ctrl->count[(r - 1) & 1], false, s));
-            TIMED(kPhaseHook, launch_compact((int)r, u, v, work, src, dst, L.cap, pi, n, ctrl,
-                                             p.block, p.ept, grid_cap, s));
+            TIMED(kPhaseHook, launch_compact((int)r, u, v, work, F0, F1, L.cap, pi, n, ctrl,
+                                             p.tau, p.block, p.ept, grid_cap, s));
             hooks += 2;
             ++jumps;
         }

@@ -35,15 +35,16 @@ hipError_t launch_bitmap(const int32_t* pi, int32_t n, Ctrl* ctrl, uint32_t* bit
 // input entries [0, m) and checks ranges; later rounds read the frontier of
 // root pairs written by the previous round's compaction (size in ctrl->count).
 hipError_t launch_hook_plain(int round, const int32_t* u, const int32_t* v, int64_t m,
-                             const int2* frontier, int32_t* pi, int32_t n, Ctrl* ctrl, int block,
-                             int ept, int grid_cap, hipStream_t s);
+                             const int2* f0, const int2* f1, int32_t* pi, int32_t n, Ctrl* ctrl,
+                             int block, int ept, int grid_cap, hipStream_t s);
 
 // Frontier compaction after the Compress of round `round`: keeps the entries
 // whose endpoints still have different roots, written as root pairs to
 // `dst` (capacity cap), size accumulated in ctrl->count[round & 1].
-hipError_t launch_compact(int round, const int32_t* u, const int32_t* v, int64_t m,
-                          const int2* src, int2* dst, int64_t cap, const int32_t* pi, int32_t n,
-                          Ctrl* ctrl, int block, int ept, int grid_cap, hipStream_t s);
+// tau: frontier rewrite threshold in thousandths (0xffffffff = every round).
+hipError_t launch_compact(int round, const int32_t* u, const int32_t* v, int64_t m, int2* f0,
+                          int2* f1, int64_t cap, const int32_t* pi, int32_t n, Ctrl* ctrl,
+                          uint32_t tau, int block, int ept, int grid_cap, hipStream_t s);
 
 // Fig. 1 as a host loop: a Hook pass over all m entries that sets
 // ctrl->hook_changed when an entry's parents differ, and one level of Jump

@@ -404,21 +404,47 @@ hipError_t launch_bitmap(const int32_t* pi, int32_t n, Ctrl* ctrl, uint32_t* bit
 }
 
 // ----------------------------------------------------------------------------- atomic-free Hook
+// Source of round `round` of the atomic-free Hook, from the record the
+// previous round's compaction left: the input lists in round 1; later, the
+// frontier buffer that round wrote (its survivors, count[] entries) or, when
+// it did not rewrite, the same buffer it read.  `total` is 0 once the
+// previous round found no active entry (converged).
+struct RoundSrc {
+    int32_t sel;      // 0 / 1 = frontier buffer, 2 = input lists
+    int64_t total;    // entries to read
+};
+__device__ __forceinline__ RoundSrc round_src(const Ctrl* ctrl, int round, int64_t m) {
+    RoundSrc r{2, m};
+    if (round == 1) return r;
+    const int p = (round - 1) & 1;
+    const int64_t active = ctrl->count[p];
+    if (ctrl->fwrote[p]) {
+        r.sel = ctrl->fsel[p] == 0 ? 1 : 0;
+        r.total = active;
+    } else {
+        r.sel = ctrl->fsel[p];
+        r.total = active ? (int64_t)ctrl->fsize[p] : 0;
+    }
+    r.total = min(r.total, m);
+    return r;
+}
+
 // Fig. 2 Hook: H = max(pi[u], pi[v]), L = min(...), plain store pi[H] = L.
 // Concurrent stores to one slot race and all but one are lost; the round
 // loop (Fig. 1) repeats until no entry is active, and every store writes a
 // smaller id than the slot's index, so no cycle forms.  Round 1 reads the
 // input lists (range-checked); later rounds read the frontier of root pairs
-// left by the previous compaction.  Block 0 also clears the count the
-// following compaction accumulates into, and records the round.
+// chosen by round_src (round 1 always writes one, so no later round reads
+// the input lists).  Block 0 also clears the count the following compaction
+// accumulates into, and records the round.
 template <int EPT, bool VEC, bool FIRST>
 __global__ __launch_bounds__(1024) void k_hook_plain(int round, const int32_t* __restrict__ eu,
                                                      const int32_t* __restrict__ ev, int64_t m,
-                                                     const int2* __restrict__ fr, int32_t* pi,
+                                                     const int2* f0, const int2* f1, int32_t* pi,
                                                      int32_t n, Ctrl* ctrl) {
-    // Later rounds: the frontier size, never more than the capacity `m`.
-    int64_t total = m;
-    if (!FIRST) total = min((int64_t)ctrl->count[(round - 1) & 1], m);
+    const RoundSrc rs = round_src(ctrl, round, m);
+    const int64_t total = rs.total;
+    const int2* fr = rs.sel == 0 ? f0 : f1;
     if (blockIdx.x == 0 && threadIdx.x == 0) {
         ctrl->count[round & 1] = 0;
         if (total > 0) ctrl->rounds = round;
@@ -472,24 +498,40 @@ __global__ __launch_bounds__(1024) void k_hook_plain(int round, const int32_t* _
 // ----------------------------------------------------------------------------- K-COMPACT
 // After the Compress of a round, an entry is still active iff its endpoints'
 // roots differ (pi is a forest of stars).  Trees only merge, so an inactive
-// entry never becomes active again and can be dropped for good.  Survivors are
-// written as root pairs.  Per wave, one 64-bit ballot per slot j gives each
-// lane its output position (mbcnt lane prefix plus the counts of earlier
-// slots); the wave totals are scanned in LDS, the workgroup reserves its
-// output range with one atomicAdd, and the survivors, staged in LDS in that
-// order, are written out as one contiguous run.
+// entry never becomes active again and can be dropped for good.  Every round
+// counts its active entries (count[r & 1], the convergence test); it writes
+// them, as root pairs, to the other frontier buffer only in round 1 and when
+// the previous round's surviving fraction (its active entries over its
+// source size) was below tau / 1000 -- otherwise the next round reads this
+// round's source again, dead entries included, and the rewrite is saved.
+// Per wave, one 64-bit ballot per slot j gives each lane its output position
+// (mbcnt lane prefix plus the counts of earlier slots); the wave totals are
+// scanned in LDS, the workgroup reserves its output range with one
+// atomicAdd, and the survivors, staged in LDS in that order, are written out
+// as one contiguous run.
 template <int EPT, bool VEC, bool FIRST>
 __global__ __launch_bounds__(256) void k_compact(int round, const int32_t* __restrict__ eu,
                                                  const int32_t* __restrict__ ev, int64_t m,
-                                                 const int2* __restrict__ src, int2* __restrict__ dst,
-                                                 int64_t cap, const int32_t* pi, int32_t n,
-                                                 Ctrl* ctrl) {
+                                                 int2* f0, int2* f1, int64_t cap, const int32_t* pi,
+                                                 int32_t n, Ctrl* ctrl, uint32_t tau) {
     __shared__ int2 stage[256 * EPT];
     __shared__ uint32_t wave_tot[4];
     __shared__ uint32_t wave_off[4];
     __shared__ uint32_t base_sh;
-    int64_t total = m;
-    if (!FIRST) total = min((int64_t)ctrl->count[(round - 1) & 1], m);
+    const RoundSrc rs = round_src(ctrl, round, m);
+    const int64_t total = rs.total;
+    const int2* src = rs.sel == 0 ? f0 : f1;
+    int2* dst = rs.sel == 0 ? f1 : f0;
+    bool write = true;
+    if (!FIRST) {
+        const int p = (round - 1) & 1;
+        write = (uint64_t)ctrl->count[p] * 1000u < (uint64_t)tau * ctrl->fsize[p];
+    }
+    if (blockIdx.x == 0 && threadIdx.x == 0) {
+        ctrl->fsel[round & 1] = rs.sel;
+        ctrl->fsize[round & 1] = (uint32_t)total;
+        ctrl->fwrote[round & 1] = write ? 1 : 0;
+    }
     if (total == 0) return;
     const int lane = threadIdx.x & 63;
     const int wave = threadIdx.x >> 6;
@@ -537,6 +579,10 @@ __global__ __launch_bounds__(256) void k_compact(int round, const int32_t* __res
             wave_tot[0] = acc;  // block total (read after the barrier)
         }
         __syncthreads();
+        if (!write) {
+            __syncthreads();  // wave_tot / wave_off are rewritten by the next tile
+            continue;
+        }
         const uint32_t woff = wave_off[wave];
 #pragma unroll
         for (int j = 0; j < EPT; ++j)
@@ -554,8 +600,8 @@ __global__ __launch_bounds__(256) void k_compact(int round, const int32_t* __res
 }
 
 hipError_t launch_hook_plain(int round, const int32_t* u, const int32_t* v, int64_t m,
-                             const int2* frontier, int32_t* pi, int32_t n, Ctrl* ctrl, int block,
-                             int ept, int grid_cap, hipStream_t s) {
+                             const int2* f0, const int2* f1, int32_t* pi, int32_t n, Ctrl* ctrl,
+                             int block, int ept, int grid_cap, hipStream_t s) {
     const int64_t tile = (int64_t)block * ept;
     int64_t grid64 = (m + tile - 1) / tile;
     if (grid64 < 1) grid64 = 1;
@@ -566,11 +612,11 @@ hipError_t launch_hook_plain(int round, const int32_t* u, const int32_t* v, int6
     do {                                                                                         \
         if (round == 1) {                                                                        \
             if (vec)                                                                             \
-                k_hook_plain<EPT, true, true><<<grid, block, 0, s>>>(round, u, v, m, frontier, pi, n, ctrl); \
+                k_hook_plain<EPT, true, true><<<grid, block, 0, s>>>(round, u, v, m, f0, f1, pi, n, ctrl); \
             else                                                                                 \
-                k_hook_plain<EPT, false, true><<<grid, block, 0, s>>>(round, u, v, m, frontier, pi, n, ctrl); \
+                k_hook_plain<EPT, false, true><<<grid, block, 0, s>>>(round, u, v, m, f0, f1, pi, n, ctrl); \
         } else {                                                                                 \
-            k_hook_plain<EPT, true, false><<<grid, block, 0, s>>>(round, u, v, m, frontier, pi, n, ctrl); \
+            k_hook_plain<EPT, true, false><<<grid, block, 0, s>>>(round, u, v, m, f0, f1, pi, n, ctrl); \
         }                                                                                        \
     } while (0)
     switch (ept) {
@@ -583,9 +629,9 @@ hipError_t launch_hook_plain(int round, const int32_t* u, const int32_t* v, int6
     return hipGetLastError();
 }
 
-hipError_t launch_compact(int round, const int32_t* u, const int32_t* v, int64_t m,
-                          const int2* src, int2* dst, int64_t cap, const int32_t* pi, int32_t n,
-                          Ctrl* ctrl, int block, int ept, int grid_cap, hipStream_t s) {
+hipError_t launch_compact(int round, const int32_t* u, const int32_t* v, int64_t m, int2* f0,
+                          int2* f1, int64_t cap, const int32_t* pi, int32_t n, Ctrl* ctrl,
+                          uint32_t tau, int block, int ept, int grid_cap, hipStream_t s) {
     (void)block;  // the compaction tile is fixed at 256 threads (LDS staging size)
     const int64_t tile = 256 * (int64_t)ept;
     int64_t grid64 = (m + tile - 1) / tile;
@@ -597,11 +643,11 @@ hipError_t launch_compact(int round, const int32_t* u, const int32_t* v, int64_t
     do {                                                                                         \
         if (round == 1) {                                                                        \
             if (vec)                                                                             \
-                k_compact<EPT, true, true><<<grid, 256, 0, s>>>(round, u, v, m, src, dst, cap, pi, n, ctrl); \
+                k_compact<EPT, true, true><<<grid, 256, 0, s>>>(round, u, v, m, f0, f1, cap, pi, n, ctrl, tau); \
             else                                                                                 \
-                k_compact<EPT, false, true><<<grid, 256, 0, s>>>(round, u, v, m, src, dst, cap, pi, n, ctrl); \
+                k_compact<EPT, false, true><<<grid, 256, 0, s>>>(round, u, v, m, f0, f1, cap, pi, n, ctrl, tau); \
         } else {                                                                                 \
-            k_compact<EPT, true, false><<<grid, 256, 0, s>>>(round, u, v, m, src, dst, cap, pi, n, ctrl); \
+            k_compact<EPT, true, false><<<grid, 256, 0, s>>>(round, u, v, m, f0, f1, cap, pi, n, ctrl, tau); \
         }                                                                                        \
     } while (0)
     switch (ept) {

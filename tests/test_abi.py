@@ -103,6 +103,11 @@ def test_host_side_argument_errors(lib):
         setattr(bad, field, value)
         assert lib.cc_labels_ex(4, dummy, dummy, 1, dummy, ctypes.byref(bad), None, 0, None,
                                 None) == cc.CC_ERR_ARG, field
+    for tau in (-1, 1001):
+        bad = cc._COptions()
+        bad.compact_threshold = tau
+        assert lib.cc_labels_ex(4, dummy, dummy, 1, dummy, ctypes.byref(bad), None, 0, None,
+                                None) == cc.CC_ERR_ARG, tau
     bad = cc._COptions()
     bad.no_sync = 2
     assert lib.cc_labels_ex(4, dummy, dummy, 1, dummy, ctypes.byref(bad), None, 0, None,

@@ -1,0 +1,60 @@
+"""Plan autotuner: the cache and shape keys on the host; on the GPU, a tuned
+plan (single graphs and batches) still gives the oracle's labels, and the
+search covers the knobs it claims to (segments, filter, tile, block, and the
+frontier compaction threshold when the atomic-free Hook wins)."""
+import numpy as np
+import pytest
+
+import graphgen
+import oracle
+import paper_1612_01178_amd as cc
+from paper_1612_01178_amd import autotune
+
+
+def test_shape_key_buckets():
+    assert autotune.shape_key(1 << 16, 1 << 19) == "gfx950:n2^16:d2^3"
+    # same bucket for nearby shapes, different for another degree
+    assert autotune.shape_key(70000, 560000) == autotune.shape_key(1 << 16, 1 << 19)
+    assert autotune.shape_key(1 << 16, 1 << 16) != autotune.shape_key(1 << 16, 1 << 19)
+    assert autotune.shape_key(1 << 10, 100) == "gfx950:n2^10:d2^-3"
+
+
+def test_cache_round_trip(tmp_path):
+    path = str(tmp_path / "tune.json")
+    assert autotune.options_for(1 << 16, 1 << 19, path=path) == cc.Options()
+    opt = cc.Options(hook="plain", edges_per_thread=16, compact_threshold=250)
+    autotune._store(path, autotune.shape_key(1 << 16, 1 << 19),
+                    {"options": opt.__dict__, "ms": 0.1, "n": 1 << 16, "m": 1 << 19})
+    assert autotune.options_for(1 << 16, 1 << 19, path=path) == opt
+    assert autotune.options_for(1 << 20, 1 << 19, path=path) == cc.Options()
+
+
+@pytest.mark.gpu
+def test_tuned_plans_are_exact(tmp_path):
+    torch = pytest.importorskip("torch")
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    dev = torch.device("cuda:0")
+    u, v, n, _ = graphgen.er_planted(1 << 14, 1 << 17, 16, seed=61)
+    want = oracle.labels(u, v, n)
+    du, dv = torch.from_numpy(u).to(dev), torch.from_numpy(v).to(dev)
+    path = str(tmp_path / "tune.json")
+    print("tune er 2^14", flush=True)
+    best, table = autotune.tune(du, dv, n, reps=1, path=path)
+    fields = {k for _, o in table for k, val in o.items() if val != getattr(cc.Options(), k)}
+    assert {"hook", "segments", "filter", "edges_per_thread", "block"} <= fields
+    if best.hook in ("plain", "auto"):
+        assert "compact_threshold" in fields
+    assert autotune.options_for(n, len(u), path=path) == best
+    for _, o in table:
+        got = cc.labels(du, dv, n, options=cc.Options(**o)).cpu().numpy()
+        assert np.array_equal(got, want), o
+    # batches: the segment cap
+    bu, bv, vo, eo = graphgen.batch_er(60, seed=62, lo_exp=6.0, hi_exp=12.0)
+    bwant = oracle.labels_batch(bu, bv, vo, eo)
+    dbu, dbv = torch.from_numpy(bu).to(dev), torch.from_numpy(bv).to(dev)
+    print("tune batch of 60", flush=True)
+    bopt, btable = autotune.tune_batch(dbu, dbv, vo, eo, reps=1)
+    assert sorted(seg for _, seg in btable) == [0, 1, 2, 4, 8]
+    got = cc.labels_batch(dbu, dbv, vo, eo, options=bopt).cpu().numpy()
+    assert np.array_equal(got, bwant)

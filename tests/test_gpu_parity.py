@@ -48,6 +48,9 @@ VARIANTS = {
     "plain_b128_e16_k1": cc.Options(hook="plain", edges_per_thread=16, block=128,
                                     rounds_per_check=1),
     "plain_e4_k7": cc.Options(hook="plain", edges_per_thread=4, rounds_per_check=7),
+    # frontier rewritten only below a surviving fraction of 0.1 % / 50 %
+    "plain_tau1_k1": cc.Options(hook="plain", compact_threshold=1, rounds_per_check=1),
+    "plain_tau500_e16": cc.Options(hook="plain", compact_threshold=500, edges_per_thread=16),
     "coherent_giant": cc.Options(hook="atomic", coherent_loads=True, segments=6, filter="giant"),
     "coherent_s3": cc.Options(hook="atomic", coherent_loads=True, segments=3, filter="off",
                               block=128),

@@ -487,7 +487,8 @@ def bench_batch(cc, torch, dev, num_graphs=10000, reps=5):
     u = torch.from_numpy(u_np).to(dev)
     v = torch.from_numpy(v_np).to(dev)
     out = torch.empty(int(vo[-1]), dtype=torch.int32, device=dev)
-    # the autotuner picks the per-graph segment cap (untimed, like warm-up)
+    # the autotuner picks the LDS climb's halving and the per-graph segment
+    # cap (untimed, like warm-up)
     bopt, btable = autotune.tune_batch(u, v, vo, eo, reps=2, log=log)
     for _ in range(2):
         cc.labels_batch(u, v, vo, eo, out=out, options=bopt)
@@ -517,8 +518,9 @@ def bench_batch(cc, torch, dev, num_graphs=10000, reps=5):
     m = int(eo[-1])
     log("batch: %.3f ms per batch call, loop %.1f ms" % (dt * 1e3, dt_loop * 1e3))
     return {"workload": "batch10k", "graphs": num_graphs, "n_total": int(vo[-1]), "m_total": m,
-            "segment_cap": bopt.segments,
-            "tuned_ms": {str(seg): round(t, 4) for t, seg in btable},
+            "segment_cap": bopt.segments, "path_halving": bopt.path_halving,
+            "tuned_ms": {"halving_%s_cap_%d" % (o["path_halving"], o["segments"]): round(t, 4)
+                         for t, o in btable},
             "graphs_per_s": num_graphs / dt, "edges_per_s": m / dt, "ms_per_batch": dt * 1e3,
             "loop_graphs_per_s": num_graphs / dt_loop, "speedup_vs_loop": dt_loop / dt,
             "parity_vs_oracle_digest": bool(parity and loop_parity),

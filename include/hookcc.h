@@ -242,11 +242,14 @@ int32_t cc_labels_batch(int32_t num_graphs, const int64_t* vtx_off, const int64_
                         const int32_t* edges_u, const int32_t* edges_v, int32_t* out_label);
 
 /* As cc_labels_batch on `stream` (hipStream_t, NULL = null stream), using the
- * library's workspace pool; `opts` and `stats` may be NULL.  Of `opts` only
- * `segments` is used: 0 gives every LDS-solved graph the paper's
- * round(m_g / n_g) segments, S > 0 caps that at S (in LDS a climb is cheap,
- * so fewer segments -- fewer workgroup barriers -- are often faster; the
- * autotuner picks it).  Larger graphs use the default device-memory plan. */
+ * library's workspace pool; `opts` and `stats` may be NULL.  For the
+ * LDS-solved graphs `opts` sets `path_halving` (CC_HALVE_AUTO / ON: the LDS
+ * climb re-points passed non-roots at their grandparents; OFF: Fig. 3
+ * exactly) and `segments`, a cap S on each graph's round(m_g / n_g) segments:
+ * 0 = default, 2 with halving and no cap without it (in LDS a climb is
+ * cheap, so fewer segments -- fewer Multi-Jump passes and barriers -- are
+ * faster; the autotuner picks S).  `graph` = 1 captures the launch sequence.
+ * Larger graphs use the default device-memory plan. */
 int32_t cc_labels_batch_ex(int32_t num_graphs, const int64_t* vtx_off, const int64_t* edge_off,
                            const int32_t* edges_u, const int32_t* edges_v, int32_t* out_label,
                            const cc_options* opts, void* stream, cc_stats* stats);

@@ -15,6 +15,9 @@ coordinate by coordinate from the library's default:
    (rewrite the frontier every round, or only below a surviving fraction of
    50 %, 25 %, 10 %).
 
+``tune_batch`` does the same for the batched LDS solver: path halving in
+the LDS climb and the per-graph segment cap.
+
 Results are cached in a JSON file keyed by device architecture and a shape
 bucket (log2 n, m/n rounded to a power of two), so graphs of a similar shape
 reuse a plan without re-timing.  ``options_for(n, m)`` returns the cached
@@ -130,13 +133,16 @@ def tune(u, v, n: int, *, reps: int = 3, cache: bool = True, path: str | None = 
 
 
 def tune_batch(u, v, vtx_off, edge_off, *, reps: int = 3, log=None):
-    """Per-graph segment cap of the batched LDS solver (0 = the paper's
-    round(m_g / n_g) per graph, else min(S, that)); returns (Options, table)."""
+    """Plan of the batched LDS solver: path halving in the LDS climb (on/off)
+    and the per-graph segment cap S (each graph gets min(S, round(m_g / n_g))
+    segments; 0 = the default, 2 with halving and the paper's round(m_g / n_g)
+    without).  Returns (best Options, table of (ms, options dict))."""
     import torch
     out = torch.empty(int(vtx_off[-1]), dtype=torch.int32, device=u.device)
+    cands = [Options(segments=s) for s in (1, 2, 4, 8)]
+    cands += [Options(segments=s, path_halving="off") for s in (0, 4, 8)]
     table = []
-    for seg in (0, 1, 2, 4, 8):
-        opt = Options(segments=seg)
+    for opt in cands:
         labels_batch(u, v, vtx_off, edge_off, out=out, options=opt)
         best = float("inf")
         for _ in range(reps):
@@ -144,8 +150,9 @@ def tune_batch(u, v, vtx_off, edge_off, *, reps: int = 3, log=None):
             t = time.perf_counter()
             labels_batch(u, v, vtx_off, edge_off, out=out, options=opt)
             best = min(best, time.perf_counter() - t)
-        table.append((best * 1e3, seg))
+        table.append((best * 1e3, opt))
         if log:
-            log("tune batch segments cap %d: %.3f ms" % (seg, best * 1e3))
-    table.sort()
-    return Options(segments=table[0][1]), table
+            log("tune batch halving %s, segment cap %d: %.3f ms"
+                % (opt.path_halving, opt.segments, best * 1e3))
+    table.sort(key=lambda x: x[0])
+    return table[0][1], [(t, o.__dict__) for t, o in table]

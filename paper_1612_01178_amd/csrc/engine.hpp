@@ -21,8 +21,8 @@ int32_t labels_impl(int32_t n, const int32_t* u, const int32_t* v, int64_t m, in
 size_t workspace_bytes_impl(int32_t n, int64_t m, const cc_options* opts);
 
 // Independent graphs given by descriptors (device arrays); synchronous on s.
-// opts (nullable): only `segments` is used (per-graph segment cap of the LDS
-// solver).
+// opts (nullable): `segments` (per-graph segment cap of the LDS solver),
+// `path_halving` (in the LDS climb) and `graph` are used.
 int32_t list_impl(int32_t count, const cc_graph* graphs, const cc_options* opts, hipStream_t s,
                   cc_stats* st);
 // Graphs packed back to back with host offsets; synchronous on s.

@@ -96,8 +96,8 @@ hipError_t launch_probe_bitgather(const int32_t* u, const int32_t* v, int64_t m,
 // from a device work queue in the order of `order`.
 hipError_t prepare_batch_lds();  // once per process, before the first launch
 hipError_t launch_batch_lds(const GraphDesc* descs, const int32_t* order, int32_t count,
-                            int32_t max_n, int32_t* queue_head, int32_t* status, int grid,
-                            hipStream_t s);
+                            int32_t max_n, int32_t* queue_head, int32_t* status, bool halve,
+                            int grid, hipStream_t s);
 
 // Zeroes `words` 32-bit words with a kernel (graph-capture friendly).
 hipError_t launch_zero(void* p, int64_t words, hipStream_t s);

@@ -40,8 +40,16 @@ __device__ __forceinline__ void lds_st16(uint16_t* spi, uint32_t idx, uint32_t x
     *reinterpret_cast<volatile uint16_t*>(spi + idx) = (uint16_t)x;
 }
 
-// Atomic-Hook in LDS (Fig. 3, top), same steps as the device-memory kernel.
-__device__ __forceinline__ void lds_atomic_hook(uint16_t* spi, uint32_t pu, uint32_t pv) {
+// Atomic-Hook in LDS (Fig. 3, top), same steps as the device-memory kernel;
+// with `halve`, a passed non-root H whose grandparent differs from its
+// parent is re-pointed at the grandparent (path halving).  That 16-bit store
+// cannot be lost to, nor undo, a concurrent CAS on the other half of its
+// 32-bit word: the CAS compares the whole word, so it fails and retries if
+// the store landed between its read and its swap.  In LDS the store costs
+// one write, and the shallower trees let a graph run with fewer segments
+// (fewer Multi-Jump passes over its vertices).
+__device__ __forceinline__ void lds_atomic_hook(uint16_t* spi, uint32_t pu, uint32_t pv,
+                                                bool halve) {
     while (pu != pv) {
         const uint32_t H = pu > pv ? pu : pv;
         const uint32_t L = pu > pv ? pv : pu;
@@ -49,13 +57,14 @@ __device__ __forceinline__ void lds_atomic_hook(uint16_t* spi, uint32_t pu, uint
         if (found == H) return;
         pu = lds_ld16(spi, found);
         pv = lds_ld16(spi, L);
+        if (halve && pu != found) lds_st16(spi, H, pu);
     }
 }
 
 __global__ __launch_bounds__(1024) void k_batch_lds(const GraphDesc* __restrict__ descs,
                                                     const int32_t* __restrict__ order,
                                                     int32_t count, int32_t* queue_head,
-                                                    int32_t* status) {
+                                                    int32_t* status, bool halve) {
     extern __shared__ uint16_t spi[];
     __shared__ int32_t next;
     const uint32_t tid = threadIdx.x;
@@ -103,7 +112,7 @@ __global__ __launch_bounds__(1024) void k_batch_lds(const GraphDesc* __restrict_
                         continue;
                     }
                     if (a[j] == b[j]) continue;
-                    lds_atomic_hook(spi, lds_ld16(spi, a[j]), lds_ld16(spi, b[j]));
+                    lds_atomic_hook(spi, lds_ld16(spi, a[j]), lds_ld16(spi, b[j]), halve);
                 }
 #pragma unroll
                 for (int j = 0; j < kBatchEPT; ++j) {
@@ -140,12 +149,12 @@ hipError_t prepare_batch_lds() {
 }
 
 hipError_t launch_batch_lds(const GraphDesc* descs, const int32_t* order, int32_t count,
-                            int32_t max_n, int32_t* queue_head, int32_t* status, int grid,
-                            hipStream_t s) {
+                            int32_t max_n, int32_t* queue_head, int32_t* status, bool halve,
+                            int grid, hipStream_t s) {
     if (count <= 0) return hipSuccess;
     if (max_n < 1 || max_n > 65536) return hipErrorInvalidValue;
     const size_t lds = (((size_t)max_n + 1) / 2) * 4;  // whole 32-bit words
-    k_batch_lds<<<grid, 1024, lds, s>>>(descs, order, count, queue_head, status);
+    k_batch_lds<<<grid, 1024, lds, s>>>(descs, order, count, queue_head, status, halve);
     return hipGetLastError();
 }
 

@@ -49,12 +49,14 @@ def test_tuned_plans_are_exact(tmp_path):
     for _, o in table:
         got = cc.labels(du, dv, n, options=cc.Options(**o)).cpu().numpy()
         assert np.array_equal(got, want), o
-    # batches: the segment cap
+    # batches: halving in the LDS climb and the segment cap
     bu, bv, vo, eo = graphgen.batch_er(60, seed=62, lo_exp=6.0, hi_exp=12.0)
     bwant = oracle.labels_batch(bu, bv, vo, eo)
     dbu, dbv = torch.from_numpy(bu).to(dev), torch.from_numpy(bv).to(dev)
     print("tune batch of 60", flush=True)
     bopt, btable = autotune.tune_batch(dbu, dbv, vo, eo, reps=1)
-    assert sorted(seg for _, seg in btable) == [0, 1, 2, 4, 8]
-    got = cc.labels_batch(dbu, dbv, vo, eo, options=bopt).cpu().numpy()
-    assert np.array_equal(got, bwant)
+    assert sorted((o["path_halving"], o["segments"]) for _, o in btable) == \
+        [("auto", 1), ("auto", 2), ("auto", 4), ("auto", 8), ("off", 0), ("off", 4), ("off", 8)]
+    for _, o in btable:
+        got = cc.labels_batch(dbu, dbv, vo, eo, options=cc.Options(**o)).cpu().numpy()
+        assert np.array_equal(got, bwant), o

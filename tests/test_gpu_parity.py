@@ -303,10 +303,10 @@ def test_batch_mixed_sizes_against_oracle(dev):
     want = oracle.labels_batch(u, v, vo, eo)
     got, st = cc.labels_batch(to_dev(u, dev), to_dev(v, dev), vo, eo, return_stats=True)
     assert np.array_equal(got.cpu().numpy(), want)
-    for cap in (1, 2, 5):
+    for cap, halve in ((1, "auto"), (2, "on"), (5, "auto"), (0, "off"), (3, "off")):
         got = cc.labels_batch(to_dev(u, dev), to_dev(v, dev), vo, eo,
-                              options=cc.Options(segments=cap))
-        assert np.array_equal(got.cpu().numpy(), want), cap
+                              options=cc.Options(segments=cap, path_halving=halve))
+        assert np.array_equal(got.cpu().numpy(), want), (cap, halve)
 
 
 def test_batch_range_error(dev):
@@ -384,9 +384,10 @@ def test_full_size_batch_matches_oracle_digest(dev):
     assert (int(vo[-1]), len(u)) == (rec["n"], rec["m"])
     say("full size batch10k")
     du, dv = to_dev(u, dev), to_dev(v, dev)
-    for cap in (0, 1, 3):
-        lab = cc.labels_batch(du, dv, vo, eo, options=cc.Options(segments=cap)).cpu().numpy()
-        assert digest(lab) == rec["sha256"], cap
+    for cap, halve in ((0, "auto"), (1, "auto"), (3, "auto"), (0, "off"), (3, "off")):
+        lab = cc.labels_batch(du, dv, vo, eo,
+                              options=cc.Options(segments=cap, path_halving=halve)).cpu().numpy()
+        assert digest(lab) == rec["sha256"], (cap, halve)
 
 
 # ----------------------------------------------------------------------------- streamed (host edges)
@@ -515,6 +516,63 @@ def test_csr_full_size_rmat24(dev):
     for opt in (cc.Options(), cc.Options(symmetric=True)):
         lab = cc.labels_csr(rp, col, n, options=opt).cpu().numpy()
         assert digest(lab) == rec["sha256"]
+
+
+# ----------------------------------------------------------------------------- maximum sizes
+def test_max_vertex_count(dev):
+    """n = 2^31 - 1 (the largest int32 vertex count): edges between far-apart
+    ids; closed form: {0, n-1, n-2} -> 0, {5, n-3, 2^30} -> 5, the rest alone."""
+    n = (1 << 31) - 1
+    u = torch.tensor([0, n - 1, 5, 1 << 30], dtype=torch.int32, device=dev)
+    v = torch.tensor([n - 1, n - 2, n - 3, n - 3], dtype=torch.int32, device=dev)
+    want = torch.arange(n, dtype=torch.int32, device=dev)
+    want[n - 1] = 0
+    want[n - 2] = 0
+    want[n - 3] = 5
+    want[1 << 30] = 5
+    out = torch.empty(n, dtype=torch.int32, device=dev)
+    for name in ("default", "atomic", "plain"):
+        say("n = 2^31 - 1", name)
+        out.fill_(-1)
+        cc.labels(u, v, n, out=out, options=VARIANTS[name])
+        assert torch.equal(out, want), name
+    del out, want
+    torch.cuda.empty_cache()
+
+
+def test_more_than_2_31_entries(dev):
+    """m = 2^31 + 12 entries (64-bit entry indices): a cycle over P = 2^20 ids
+    repeated, then four distinctive pairs stored beyond entry 2^31;
+    closed form: [0, P) -> 0, {P+5, P+7, P+11} -> P+5, {P+8, P+9} -> P+8,
+    {P+20, P+21} -> P+20, the rest alone."""
+    P = 1 << 20
+    n = (1 << 21) + 64
+    m = (1 << 31) + 12
+    u = torch.empty(m, dtype=torch.int32, device=dev)
+    v = torch.empty(m, dtype=torch.int32, device=dev)
+    chunk = 1 << 28
+    for start in range(0, m - 4, chunk):
+        end = min(m - 4, start + chunk)
+        k = torch.arange(start, end, dtype=torch.int64, device=dev)
+        u[start:end] = (k % P).to(torch.int32)
+        v[start:end] = ((k + 1) % P).to(torch.int32)
+        del k
+    u[m - 4:] = torch.tensor([P + 5, P + 9, P + 7, P + 20], dtype=torch.int32, device=dev)
+    v[m - 4:] = torch.tensor([P + 7, P + 8, P + 11, P + 21], dtype=torch.int32, device=dev)
+    want = torch.arange(n, dtype=torch.int32, device=dev)
+    want[:P] = 0
+    want[P + 7] = P + 5
+    want[P + 11] = P + 5
+    want[P + 9] = P + 8
+    want[P + 21] = P + 20
+    out = torch.empty(n, dtype=torch.int32, device=dev)
+    for name in ("default", "s1", "s5_giant_b1024_e16", "s3_nohalve"):
+        say("m = 2^31 + 12", name)
+        out.fill_(-1)
+        cc.labels(u, v, n, out=out, options=VARIANTS[name])
+        assert torch.equal(out, want), name
+    del u, v, out, want
+    torch.cuda.empty_cache()
 
 
 # ----------------------------------------------------------------------------- no-sync calls

@@ -349,7 +349,7 @@ def streamed(cc, torch, u_np, v_np, n, out, workload, reps=3, chunk=1 << 24):
             "frac_of_copy_ceiling": round(dcopy / dt, 3), "parity_vs_oracle_digest": bool(ok)}
 
 
-def serving(cc, torch, dev, requests, loads=(0.5, 0.7, 0.9), host_mode=False, pool_size=32,
+def serving(cc, torch, dev, requests, loads=(0.5, 0.7, 0.9), host_mode=False, pool_size=32, workers=3,
             warm=20, seed=1005):
     """Continuous-batching server vs a FIFO one-request-at-a-time server on a
     Poisson stream of R-MAT requests (scale U{10..22}, edge factor U{8..32},
@@ -411,7 +411,7 @@ def serving(cc, torch, dev, requests, loads=(0.5, 0.7, 0.9), host_mode=False, po
 
     out = {"mode": "host (PCIe copies in latency)" if host_mode else "device-resident requests",
            "pool": pool_size, "requests": requests, "warmup": warm}
-    servers = {"batched": dict(workers=3, max_batch=256),
+    servers = {"batched": dict(workers=workers, max_batch=256),
                "fifo_single": dict(workers=1, max_batch=1)}
     sat = {}
     for name, cfg in servers.items():

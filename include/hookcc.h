@@ -320,9 +320,12 @@ int32_t cc_labels_list(int32_t count, const cc_graph* graphs, const cc_options* 
  * bytes of labels if CC_REQ_HOST_LABELS, 256-byte granules; requests whose
  * arrays are already on the device take no arena space).  Each of
  * cfg->workers host threads owns one HIP stream and, whenever it is free,
- * solves every admitted waiting request as one wave (the cc_labels_list
- * solvers), so requests that arrive while other waves run join the next
- * wave and waves overlap on the device.  Times are seconds on the clock of
+ * solves a wave taken from the head of the queue in arrival order (the
+ * cc_labels_list solvers): the longest run of admitted small requests (at
+ * most CC_BATCH_LDS_MAX_N vertices, one persistent LDS launch), or a single
+ * large request on its own, so small requests never wait for a large one in
+ * their wave.  Requests that arrive while other waves run join the next
+ * wave, and waves overlap on the device.  Times are seconds on the clock of
  * cc_server_clock(). */
 #define CC_REQ_HOST_EDGES 1  /* edges_u/edges_v are [host]: copied in at admission   */
 #define CC_REQ_HOST_LABELS 2 /* out_label is [host]: labels copied back when done     */

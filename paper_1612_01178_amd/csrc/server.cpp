@@ -4,14 +4,18 @@
 // arena sized by the caller (HBM-footprint admission: edges 8m bytes and
 // labels 4n bytes for requests whose arrays live in host memory).  Each of
 // `workers` host threads owns one HIP stream; whenever a worker is free it
-// takes every admitted-and-waiting request that fits (up to max_batch
-// requests / max_batch_edges entries), copies host inputs to the device,
-// solves the whole wave with one graph-list call (one persistent LDS launch
-// for the small graphs, device-memory Atomic-Hook solves for the large
-// ones), copies labels back, and releases the arena space.  Requests that
-// arrive while other waves are on the GPU join the next free worker's wave,
-// so waves overlap on the device.  Every request records submit, admit,
-// launch, device-done and host-done times on one steady clock.
+// forms a wave from the head of the queue, in arrival order: either the
+// longest run of small requests (at most CC_BATCH_LDS_MAX_N vertices) that
+// fits (up to max_batch requests / max_batch_edges entries), solved together
+// by one persistent LDS launch, or a single large request, solved in device
+// memory.  A large request never joins a wave of small ones, so small
+// requests do not wait for it, and large requests run concurrently on
+// different workers' streams.  The worker copies host inputs to the device,
+// solves the wave with one graph-list call, copies labels back, and releases
+// the arena space.  Requests that arrive while other waves are on the GPU
+// join the next free worker's wave, so waves overlap on the device.  Every
+// request records submit, admit, launch, device-done and host-done times on
+// one steady clock.
 #include <algorithm>
 #include <chrono>
 #include <condition_variable>
@@ -213,7 +217,8 @@ void worker_main(cc_server* S) {
                 int64_t edges = 0;
                 while (!S->pending.empty() && (int32_t)wave.size() < S->cfg.max_batch) {
                     Request* r = S->pending.front();
-                    if (!wave.empty() && edges + r->m > S->cfg.max_batch_edges) break;
+                    const bool large = r->n > CC_BATCH_LDS_MAX_N;
+                    if (!wave.empty() && (large || edges + r->m > S->cfg.max_batch_edges)) break;
                     const size_t need = r->bytes;
                     if (need > S->arena_size) {
                         r->info.status = CC_ERR_NOMEM;
@@ -230,6 +235,7 @@ void worker_main(cc_server* S) {
                     wave.push_back(r);
                     edges += r->m;
                     S->pending.pop_front();
+                    if (large) break;  // a large request is a wave of its own
                 }
                 if (!wave.empty()) break;
                 S->cv_work.wait(lk);

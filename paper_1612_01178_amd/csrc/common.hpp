@@ -48,17 +48,19 @@ static_assert(sizeof(GraphDesc) == 40, "descriptor layout");
 // Accesses of the tree array pi.
 //
 // The races on pi are part of the method (concurrent hooks and jumps,
-// Section 3): every value pi[x] ever holds is x itself or an ancestor of x,
-// and values only move up the tree, so a load that returns an out-of-date
-// value still returns a valid ancestor.  The climbing loops only need that
-// (each kernel states why it stays correct and finite), so loads and the
-// plain stores are relaxed atomics of WORKGROUP scope: ordinary cached
-// accesses on gfx950 that hit in L1 / the XCD's L2 and may not yet see a
-// value another XCD wrote during the same kernel.  Kernel boundaries make
-// every earlier write visible.  Only the compare-and-swap that takes a root
-// must be device-coherent, so it is an AGENT-scope atomic.  COH = true makes
-// the loads and stores agent scope as well (coherent across XCDs, served
-// beyond the per-XCD L2); it is kept for measurement.
+// Section 3): every value pi[x] ever holds is x itself or a vertex of x's
+// tree smaller than x (trees only merge), so a load that returns an
+// out-of-date value still returns a valid pointer.  The climbing loops only
+// need that (each kernel states why it stays correct and finite), so loads
+// are relaxed atomics of WORKGROUP scope: ordinary cached accesses on gfx950
+// that hit in L1 / the XCD's L2 and may not yet see a value another XCD wrote
+// during the same kernel.  Kernel boundaries make every earlier write
+// visible.  Stores are workgroup scope too in kernels where no thread takes
+// a root by CAS (Multi-Jump, the atomic-free Hook).  In a kernel that hooks
+// by CAS, every write is AGENT scope: the CAS itself and the path-halving
+// store (halve_to).  COH = true makes the loads and stores agent scope as
+// well (coherent across XCDs, served beyond the per-XCD L2); it is kept for
+// measurement.
 template <bool COH>
 __device__ __forceinline__ int32_t ld_tree(const int32_t* p) {
     if (COH) return __hip_atomic_load(p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);

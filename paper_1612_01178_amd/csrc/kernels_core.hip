@@ -12,7 +12,8 @@
 // bound by the coalesced int32 edge stream from HBM and by random 4-byte
 // gathers of the tree array pi (L2 / Infinity Cache).  Edge entries are read
 // with 16-byte non-temporal vector loads so the stream does not evict pi from
-// the caches; tree accesses are relaxed agent-scope atomics (see common.hpp).
+// the caches; tree loads are cached relaxed atomics, and the scope of tree
+// writes follows the rule stated in common.hpp.
 #include "kernels.hpp"
 
 namespace hookcc {

@@ -4,12 +4,15 @@
 // entry's first endpoint is found differs.
 //
 // Row ids are expanded on the fly.  Each workgroup takes a tile of
-// consecutive entries, finds the rows spanning it with one binary search
-// per tile end (row_ptr is int64 and non-decreasing), loads that window of
-// row_ptr into LDS, and every thread finds the row of its first entry by a
-// binary search in LDS, advancing linearly for its following entries.  A
-// tile whose window exceeds the LDS budget (many empty rows) searches
-// row_ptr in device memory instead.
+// consecutive entries and finds the rows spanning it (row_ptr is int64 and
+// non-decreasing) with a 32-ary search per tile end, both run at once by the
+// first wave (half a wave each): 5 dependent rounds of loads for 16M rows
+// instead of the 24 of a binary search, which at one tile per 2,048 entries
+// otherwise dominate the pass.  The tile then loads that window of row_ptr
+// into LDS, and every thread finds the row of its first entry by a binary
+// search in LDS, advancing linearly for its following entries.  A tile whose
+// window exceeds the LDS budget (many empty rows) searches row_ptr in device
+// memory instead.
 //
 // With the giant filter, the row's bit is tested once per group of four
 // consecutive entries (they nearly always share the row) instead of once
@@ -26,6 +29,35 @@
 namespace hookcc {
 
 constexpr int kCsrWindow = 4096;  // rows of row_ptr held in LDS per tile
+
+// Largest r in [0, n - 1] with rp[r] <= e, by lanes [half*32, half*32 + 32)
+// of the calling wave (every lane of the wave must call it; each half-wave
+// searches for its own e).  Each round, the half-wave's lanes probe 32
+// evenly spaced rows of the current interval, and the interval shrinks to
+// the gap after the last probe that is still <= e.
+__device__ __forceinline__ int64_t upper_row32(const int64_t* __restrict__ rp, int32_t n, int64_t e) {
+    const int lane = threadIdx.x & 63;
+    const int sub = lane & 31;
+    const int half = lane >> 5;
+    int64_t lo = 0, hi = (int64_t)n - 1;  // answer in [lo, hi]; rp[0] <= e assumed
+    while (true) {
+        const int64_t span = hi - lo + 1;
+        const bool last = span <= 32;
+        // probe k (1..32) of this half-wave
+        const int64_t probe = last ? lo + sub : lo + (span * (sub + 1)) / 33;
+        const bool ok = probe <= hi && rp[probe] <= e;
+        const uint64_t mk = __ballot(ok);
+        const uint32_t mine = (uint32_t)(mk >> (32 * half));
+        // rp is non-decreasing, so the probes that pass form a prefix
+        const int cnt = __popc(mine);
+        if (last) return lo + cnt - 1 < lo ? lo : lo + cnt - 1;
+        // probes p_1 < ... < p_32; the answer lies in [p_cnt, p_{cnt+1} - 1]
+        const int64_t nlo = cnt ? lo + (span * cnt) / 33 : lo;
+        const int64_t nhi = cnt < 32 ? lo + (span * (cnt + 1)) / 33 - 1 : hi;
+        lo = nlo;
+        hi = nhi < lo ? lo : nhi;
+    }
+}
 
 __device__ __forceinline__ int64_t upper_row(const int64_t* __restrict__ rp, int64_t lo, int64_t hi,
                                              int64_t e) {
@@ -49,12 +81,15 @@ __global__ __launch_bounds__(256) void k_ahook_csr(const int64_t* __restrict__ r
     const int64_t tile = (int64_t)blockDim.x * EPT;
     const int64_t t0 = begin + (int64_t)blockIdx.x * tile;
     const int64_t t1 = min(end, t0 + tile);  // exclusive
-    if (threadIdx.x == 0) {
-        r_lo_sh = upper_row(row_ptr, 0, n - 1, t0);
-        r_hi_sh = upper_row(row_ptr, r_lo_sh, n - 1, t1 - 1);
+    if (threadIdx.x < 64) {
+        // half-wave 0 finds the row of t0, half-wave 1 the row of t1 - 1
+        const int64_t r = upper_row32(row_ptr, n, threadIdx.x < 32 ? t0 : t1 - 1);
+        if (threadIdx.x == 0) r_lo_sh = r;
+        if (threadIdx.x == 32) r_hi_sh = r;
     }
     __syncthreads();
-    const int64_t r_lo = r_lo_sh, r_hi = r_hi_sh;
+    const int64_t r_lo = r_lo_sh;
+    const int64_t r_hi = r_hi_sh < r_lo ? r_lo : r_hi_sh;  // only a malformed row_ptr inverts them
     const bool in_lds = r_hi - r_lo + 1 <= kCsrWindow;
     if (in_lds)
         for (int64_t r = r_lo + threadIdx.x; r <= r_hi + 1; r += blockDim.x) win[r - r_lo] = row_ptr[r];

@@ -71,7 +71,7 @@ __device__ __forceinline__ int64_t upper_row(const int64_t* __restrict__ rp, int
 }
 
 template <int EPT>
-__global__ __launch_bounds__(256) void k_ahook_csr(const int64_t* __restrict__ row_ptr,
+__global__ __launch_bounds__(512) void k_ahook_csr(const int64_t* __restrict__ row_ptr,
                                                    const int32_t* __restrict__ col, int32_t n,
                                                    int64_t begin, int64_t end, int32_t* pi,
                                                    Ctrl* ctrl, const uint32_t* __restrict__ bits,
@@ -211,11 +211,14 @@ hipError_t launch_ahook_csr(const int64_t* row_ptr, const int32_t* col, int32_t 
                             int64_t end, int32_t* pi, Ctrl* ctrl, const uint32_t* bits, bool sym,
                             bool halve, hipStream_t s) {
     if (end <= begin || n <= 0) return hipSuccess;
+    // 512 threads x 8 entries per tile: measured on R-MAT 24 (2^29 entries)
+    // 4.97 ms against 5.86 (256 x 8), 5.49 (256 x 16), 5.13 (1024 x 8)
     constexpr int EPT = 8;
-    const int64_t tile = 256 * EPT;
+    constexpr int kBlock = 512;
+    const int64_t tile = kBlock * EPT;
     const int64_t grid64 = (end - begin + tile - 1) / tile;
     if (grid64 > 0x7fffffff) return hipErrorInvalidValue;
-    k_ahook_csr<EPT><<<(int)grid64, 256, 0, s>>>(row_ptr, col, n, begin, end, pi, ctrl, bits,
+    k_ahook_csr<EPT><<<(int)grid64, kBlock, 0, s>>>(row_ptr, col, n, begin, end, pi, ctrl, bits,
                                                  bits != nullptr, sym, halve);
     return hipGetLastError();
 }

@@ -501,6 +501,21 @@ def bench_batch(cc, torch, dev, num_graphs=10000, reps=5):
     lab = out.cpu().numpy()
     golden = json.load(open(os.path.join(ROOT, "tests", "golden", "oracle_digests.json")))
     parity = digest(lab) == golden["batch10k"]["sha256"]
+    # the same call with its launch sequence captured once in a hipGraph and
+    # replayed (cc_options.graph; needs a stream other than the null stream)
+    gopt = cc.Options(**{**bopt.__dict__, "graph": True})
+    side = torch.cuda.Stream()
+    out.fill_(-1)
+    torch.cuda.synchronize()
+    for _ in range(2):
+        cc.labels_batch(u, v, vo, eo, out=out, options=gopt, stream=side)
+    side.synchronize()
+    t = time.perf_counter()
+    for _ in range(reps):
+        cc.labels_batch(u, v, vo, eo, out=out, options=gopt, stream=side)
+    side.synchronize()
+    dt_graph = (time.perf_counter() - t) / reps
+    parity = parity and digest(out.cpu().numpy()) == golden["batch10k"]["sha256"]
     # baseline: one synchronous cc_labels call per graph on the same resident data
     lib = cc.load()
     base_u, base_v, base_o = u.data_ptr(), v.data_ptr(), out.data_ptr()
@@ -516,12 +531,14 @@ def bench_batch(cc, torch, dev, num_graphs=10000, reps=5):
     dt_loop = time.perf_counter() - t
     loop_parity = digest(out.cpu().numpy()) == golden["batch10k"]["sha256"]
     m = int(eo[-1])
-    log("batch: %.3f ms per batch call, loop %.1f ms" % (dt * 1e3, dt_loop * 1e3))
+    log("batch: %.3f ms per batch call (%.3f ms replayed from a hipGraph), loop %.1f ms"
+        % (dt * 1e3, dt_graph * 1e3, dt_loop * 1e3))
     return {"workload": "batch10k", "graphs": num_graphs, "n_total": int(vo[-1]), "m_total": m,
             "segment_cap": bopt.segments, "path_halving": bopt.path_halving,
             "tuned_ms": {"halving_%s_cap_%d" % (o["path_halving"], o["segments"]): round(t, 4)
                          for t, o in btable},
             "graphs_per_s": num_graphs / dt, "edges_per_s": m / dt, "ms_per_batch": dt * 1e3,
+            "ms_per_batch_graph_replay": dt_graph * 1e3,
             "loop_graphs_per_s": num_graphs / dt_loop, "speedup_vs_loop": dt_loop / dt,
             "parity_vs_oracle_digest": bool(parity and loop_parity),
             "hbm_frac": round((8.0 * m + 4.0 * int(vo[-1])) / dt / 1e9 / HBM_PEAK_GBS, 4)}

@@ -268,11 +268,6 @@ struct KeyHash {
         for (size_t i = 0; i < sizeof(T); ++i) h = (h ^ p[i]) * 1099511628211ULL;
         return *this;
     }
-    KeyHash& bytes(const void* b, size_t n) {
-        const unsigned char* p = static_cast<const unsigned char*>(b);
-        for (size_t i = 0; i < n; ++i) h = (h ^ p[i]) * 1099511628211ULL;
-        return *this;
-    }
 };
 
 std::mutex g_pool_mu;
@@ -1070,8 +1065,12 @@ int32_t list_impl(int32_t count, const cc_graph* graphs, const cc_options* opts,
     const bool use_graph = opts && opts->graph == 1 && s != nullptr;
     if (use_graph) {
         KeyHash k;
-        k.add(count).add(ws).add(s).add(seg_cap).add(lds_halve).add(maxn_small).add(ns).add(nl);
-        if (ns > 0) k.bytes(pe->host_stage, (size_t)ns * sizeof(GraphDesc));
+        // The LDS graphs' descriptors are not part of the key: the captured
+        // copy node re-reads the pinned staging buffer, rewritten above, at
+        // every replay.  Only what the capture bakes in is: sizes, pointers,
+        // the LDS launch shape, and each large graph's arrays and plan.
+        k.add(count).add(ws).add(s).add(pe->host_stage).add(seg_cap).add(lds_halve)
+            .add(maxn_small).add(ns).add(nl);
         for (int32_t i = 0; i < nl; ++i) {
             const cc_graph& G = graphs[large[i]];
             k.add(G.edges_u).add(G.edges_v).add(G.out_label).add(G.m).add(G.n);

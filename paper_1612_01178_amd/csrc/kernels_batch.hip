@@ -33,12 +33,23 @@ __device__ __forceinline__ uint32_t lds_cas16(uint16_t* spi, uint32_t idx, uint3
     }
 }
 
-__device__ __forceinline__ uint32_t lds_ld16(const uint16_t* spi, uint32_t idx) {
-    return *reinterpret_cast<const volatile uint16_t*>(spi + idx);
+// Relaxed workgroup-scope atomics, not volatile accesses: the compiler keeps
+// every access (other threads change pi concurrently) and still sees that
+// the pointer is in LDS, so these are ds_read_u16 / ds_write_b16 -- a volatile
+// access through the pointer became a flat access, which also waits on the
+// outstanding global loads of the software pipeline.
+__device__ __forceinline__ uint32_t lds_ld16(uint16_t* spi, uint32_t idx) {
+    return __hip_atomic_load(spi + idx, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
 }
 __device__ __forceinline__ void lds_st16(uint16_t* spi, uint32_t idx, uint32_t x) {
-    *reinterpret_cast<volatile uint16_t*>(spi + idx) = (uint16_t)x;
+    __hip_atomic_store(spi + idx, (uint16_t)x, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
 }
+
+// The graph's arrays come from a descriptor in memory, so the compiler cannot
+// tell their address space; they are global memory, and saying so gives
+// global (not flat) loads and stores.
+typedef __attribute__((address_space(1))) const int32_t g_cint;
+typedef __attribute__((address_space(1))) int32_t g_int;
 
 // Atomic-Hook in LDS (Fig. 3, top), same steps as the device-memory kernel;
 // with `halve`, a passed non-root H whose grandparent differs from its
@@ -77,6 +88,9 @@ __global__ __launch_bounds__(1024) void k_batch_lds(const GraphDesc* __restrict_
         if (idx >= count) break;
         const GraphDesc d = descs[order[idx]];
         const uint32_t n = (uint32_t)d.n;
+        g_cint* du = (g_cint*)d.u;
+        g_cint* dv = (g_cint*)d.v;
+        g_int* dout = (g_int*)d.out;
         for (uint32_t x = tid; x < n; x += nthr) lds_st16(spi, x, x);
         __syncthreads();
         bool bad = false;
@@ -93,16 +107,16 @@ __global__ __launch_bounds__(1024) void k_batch_lds(const GraphDesc* __restrict_
 #pragma unroll
             for (int j = 0; j < kBatchEPT; ++j) {
                 const int64_t e = e0 + (int64_t)j * nthr;
-                a[j] = e < b1 ? __builtin_nontemporal_load(d.u + e) : 0;
-                b[j] = e < b1 ? __builtin_nontemporal_load(d.v + e) : 0;
+                a[j] = e < b1 ? __builtin_nontemporal_load(du + e) : 0;
+                b[j] = e < b1 ? __builtin_nontemporal_load(dv + e) : 0;
             }
             for (; e0 < b1; e0 += step) {
                 const int64_t e1 = e0 + step;
 #pragma unroll
                 for (int j = 0; j < kBatchEPT; ++j) {
                     const int64_t e = e1 + (int64_t)j * nthr;
-                    na[j] = e < b1 ? __builtin_nontemporal_load(d.u + e) : 0;
-                    nb[j] = e < b1 ? __builtin_nontemporal_load(d.v + e) : 0;
+                    na[j] = e < b1 ? __builtin_nontemporal_load(du + e) : 0;
+                    nb[j] = e < b1 ? __builtin_nontemporal_load(dv + e) : 0;
                 }
 #pragma unroll
                 for (int j = 0; j < kBatchEPT; ++j) {
@@ -135,7 +149,7 @@ __global__ __launch_bounds__(1024) void k_batch_lds(const GraphDesc* __restrict_
             __syncthreads();
         }
         if (bad) atomicOr(status, kStatusRange);
-        for (uint32_t x = tid; x < n; x += nthr) d.out[x] = (int32_t)lds_ld16(spi, x);
+        for (uint32_t x = tid; x < n; x += nthr) dout[x] = (int32_t)lds_ld16(spi, x);
         __syncthreads();
     }
 }

@@ -123,11 +123,15 @@ __global__ __launch_bounds__(512) void k_ahook_csr(const int64_t* __restrict__ r
                 a[j] = b[j] = 0;
                 continue;
             }
-            // advance to the row that owns e (rows may be empty)
-            // (stays inside the window even if row_ptr is malformed)
-            while (r < (in_lds ? r_hi : (int64_t)n - 1) &&
-                   (in_lds ? win[r + 1 - r_lo] : row_ptr[r + 1]) <= e)
-                ++r;
+            // advance to the row that owns e (rows may be empty); stays
+            // inside the window even if row_ptr is malformed.  Two loops,
+            // not one with a select between the LDS and the global row_ptr,
+            // which would become flat loads.
+            if (in_lds) {
+                while (r < r_hi && win[r + 1 - r_lo] <= e) ++r;
+            } else {
+                while (r < (int64_t)n - 1 && row_ptr[r + 1] <= e) ++r;
+            }
             a[j] = (int32_t)r;
             b[j] = __builtin_nontemporal_load(col + e);
             const bool in = (uint32_t)b[j] < (uint32_t)n;

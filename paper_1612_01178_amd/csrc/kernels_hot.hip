@@ -157,9 +157,17 @@ __global__ __launch_bounds__(1024) void k_ahook_hot(const int32_t* __restrict__ 
                 const uint32_t wa = (uint32_t)a[j] >> 5, wb = (uint32_t)b[j] >> 5;
                 const uint32_t sa = wa & (SLOTS - 1), sb = wb & (SLOTS - 1);
                 const uint32_t ka = wa / SLOTS, kb = wb / SLOTS;
-                // ka == kEmpty can never be cached (it is the empty marker)
-                const uint32_t worda = (ka < kEmpty && ltag[sa] == ka) ? lval[sa] : bits[wa];
-                const uint32_t wordb = (kb < kEmpty && ltag[sb] == kb) ? lval[sb] : bits[wb];
+                // ka == kEmpty can never be cached (it is the empty marker).
+                // Two separate (relaxed atomic) loads, the LDS one
+                // unconditional: plain loads here are merged into one load
+                // from a selected address, which is a flat load that also
+                // waits on the LDS traffic.
+                const bool hita = ka < kEmpty && (uint32_t)ltag[sa] == ka;
+                const bool hitb = kb < kEmpty && (uint32_t)ltag[sb] == kb;
+                uint32_t worda = __hip_atomic_load(lval + sa, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
+                uint32_t wordb = __hip_atomic_load(lval + sb, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
+                if (!hita) worda = __hip_atomic_load(bits + wa, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
+                if (!hitb) wordb = __hip_atomic_load(bits + wb, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
                 ba = worda >> (a[j] & 31) & 1;
                 bb = wordb >> (b[j] & 31) & 1;
             }

@@ -123,8 +123,10 @@ typedef struct cc_options {
     int32_t graph;            /* 1 = capture the call's launch sequence in a hipGraph on the
                                  call's stream the first time and replay it on later
                                  calls with the same arrays, sizes and plan (Atomic-Hook
-                                 single solves, graph lists and batches; needs a stream
-                                 other than the null stream, else ignored)             */
+                                 single solves, graph lists and batches; for the
+                                 atomic-free Hook, each block of rounds_per_check rounds
+                                 between two host reads; needs a stream other than the
+                                 null stream, else ignored; profile = 1 disables it)   */
     int32_t no_sync;          /* cc_labels_ex and cc_labels_csr only: 1 = enqueue the whole
                                  solve on the call's stream and return without waiting
                                  (Atomic-Hook only: CC_HOOK_AUTO then picks it, and

@@ -531,19 +531,23 @@ int32_t enqueue_atomic(int32_t n, const int32_t* u, const int32_t* v, int64_t m,
     return CC_OK;
 }
 
+// The atomic-free Hook in blocks of K = rounds_per_check rounds, the host
+// reading the control block after each block.  With `graph`, each block's
+// launches (block b: rounds bK+1 .. bK+K; block 0 also the init) are
+// captured once per (arrays, sizes, plan, b) and replayed.
 int32_t solve_plain(int32_t n, const int32_t* u, const int32_t* v, int64_t m, int32_t* pi,
-                    const Plan& p, char* ws, const Layout& L, hipStream_t s, Ctrl* hctrl,
-                    Timer& tm, cc_stats* st, int64_t* rounds_run) {
+                    const Plan& p, char* ws, const Layout& L, hipStream_t s, PoolEntry* pe,
+                    bool use_graph, Timer& tm, cc_stats* st, int64_t* rounds_run) {
     Ctrl* ctrl = reinterpret_cast<Ctrl*>(ws);
+    Ctrl* hctrl = pe->host_ctrl;
     int2* F0 = reinterpret_cast<int2*>(ws + L.f0);
     int2* F1 = reinterpret_cast<int2*>(ws + L.f1);
     const int grid_cap = device_cu_count() * 8;
-    TIMED(kPhaseOther, launch_init(pi, n, ctrl, s));
-    int64_t r = 0;
-    int hooks = 0, jumps = 0;
-    while (true) {
-        for (int k = 0; k < p.rounds_per_check; ++k) {
-            ++r;
+    const int K = p.rounds_per_check;
+    auto enqueue_block = [&](int64_t b) -> int32_t {
+        if (b == 0) TIMED(kPhaseOther, launch_init(pi, n, ctrl, s));
+        for (int k = 0; k < K; ++k) {
+            const int64_t r = b * K + k + 1;
             // sources and sizes are chosen on the device (round_src); the
             // grid covers the capacity and loops over what is there
             const int64_t work = (r == 1) ? m : L.cap;
@@ -553,10 +557,26 @@ int32_t solve_plain(int32_t n, const int32_t* u, const int32_t* v, int64_t m, in
                   launch_mj(pi, n, r == 1 ? nullptr : &ctrl->count[(r - 1) & 1], false, s));
             TIMED(kPhaseHook, launch_compact((int)r, u, v, work, F0, F1, L.cap, pi, n, ctrl,
                                              p.tau, p.block, p.ept, grid_cap, s));
-            hooks += 2;
-            ++jumps;
         }
-        int32_t rc = finish(s, ctrl, hctrl, st);
+        return CC_OK;
+    };
+    int64_t r = 0;
+    int hooks = 0, jumps = 0;
+    for (int64_t b = 0;; ++b) {
+        int32_t rc;
+        if (use_graph) {
+            KeyHash k;
+            k.add(n).add(m).add(u).add(v).add(pi).add(ws).add(s).add(p.block).add(p.ept)
+                .add(p.tau).add(K).add(b);
+            rc = run_graph(pe, k.h, s, [&]() { return enqueue_block(b); });
+        } else {
+            rc = enqueue_block(b);
+        }
+        if (rc != CC_OK) return rc;
+        r += K;
+        hooks += 2 * K;
+        jumps += K;
+        rc = finish(s, ctrl, hctrl, st);
         if (rc != CC_OK) return rc;
         if (hctrl->status) break;  // reported by the caller
         if (hctrl->count[r & 1] == 0) break;
@@ -701,7 +721,8 @@ int32_t labels_impl(int32_t n, const int32_t* u, const int32_t* v, int64_t m, in
     } else if (p.host_loop != CC_HOST_LOOP_OFF) {
         rc = solve_host_loop(n, u, v, m, out, p, ws, s, pe->host_ctrl, tm, st);
     } else {
-        rc = solve_plain(n, u, v, m, out, p, ws, L, s, pe->host_ctrl, tm, st, &rounds);
+        const bool use_graph = p.graph && s != nullptr && !p.profile;
+        rc = solve_plain(n, u, v, m, out, p, ws, L, s, pe, use_graph, tm, st, &rounds);
     }
     if (rc != CC_OK && rc != CC_ERR_NOCONVERGE) return rc;
     const Ctrl& c = *pe->host_ctrl;

@@ -640,7 +640,9 @@ def test_graph_capture_replays_match_eager(dev):
     out = torch.empty(n, dtype=torch.int32, device=dev)
     for opt in (cc.Options(hook="atomic", graph=True),
                 cc.Options(hook="atomic", filter="giant", segments=64, graph=True),
-                cc.Options(hook="atomic", filter="off", segments=3, graph=True)):
+                cc.Options(hook="atomic", filter="off", segments=3, graph=True),
+                cc.Options(hook="plain", graph=True),
+                cc.Options(hook="plain", graph=True, rounds_per_check=1, compact_threshold=500)):
         for rep in range(4):
             with torch.cuda.stream(s):
                 out.fill_(-1)

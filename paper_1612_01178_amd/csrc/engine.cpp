@@ -109,10 +109,10 @@ int32_t make_plan(int32_t n, int64_t m, const cc_options* o, Plan& p, bool allow
     const int64_t s_paper = n > 0 ? std::max<int64_t>(1, (m + n / 2) / n) : 1;
     // Automatic variant (measured on gfx950): on large lists Atomic-Hook with
     // path halving wins (one pass over the entries; R-MAT 24 4.6 ms vs 38 ms,
-    // percolated 4096^2 grid 0.99 vs 1.25 ms), and from average degree 8 the
+    // percolated 4096^2 grid 1.11 vs 1.21 ms), and from average degree 8 the
     // giant filter turns most entries into two bitmap tests.  On small lists
-    // (< 2^22 entries) launch count dominates and the atomic-free rounds, with
-    // fewer kernels, win (ER 2^16: 0.10 vs 0.13 ms).
+    // (< 2^22 entries) the per-kernel cost dominates and the atomic-free
+    // rounds, with fewer kernels, win (ER 2^16: 0.09 vs 0.27 ms).
     const bool large = m >= (int64_t(1) << 22);
     const bool dense_large = large && n > 0 && m >= 8 * (int64_t)n;
     bool auto_filtered = false;

@@ -401,7 +401,8 @@ int32_t cc_probe(int32_t mode, const int32_t* edges_u, const int32_t* edges_v, i
 const char* cc_last_error(void);
 
 /* Frees the library's cached device workspace (all streams).  Must not run
- * concurrently with another call. */
+ * concurrently with another call (the workers of a running cc_server make
+ * calls too). */
 void cc_release(void);
 
 /* Library version string. */

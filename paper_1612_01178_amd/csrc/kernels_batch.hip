@@ -3,8 +3,9 @@
 // One workgroup (1024 threads, 16 waves) per CU takes graphs from a device
 // work queue (an atomic counter over a host-sorted order, largest first) and
 // solves each one entirely in LDS: the graph's tree array pi lives in LDS as
-// 16-bit local ids (n <= 65536 -> at most 128 KiB of the 160 KiB LDS), the
-// edge entries are streamed once from HBM, and the labels are written once.
+// local ids, 32-bit for n <= 32768 and 16-bit up to 65536 (at most 128 KiB of
+// the 160 KiB LDS), the edge entries are streamed once from HBM, and the
+// labels are written once.
 // Per graph the schedule is the paper's adaptive one (Fig. 4): for each of
 // the graph's s edge segments, Atomic-Hook the segment, then Multi-Jump all
 // its vertices, with a workgroup barrier between phases.
@@ -33,43 +34,135 @@ __device__ __forceinline__ uint32_t lds_cas16(uint16_t* spi, uint32_t idx, uint3
     }
 }
 
-// Relaxed workgroup-scope atomics, not volatile accesses: the compiler keeps
-// every access (other threads change pi concurrently) and still sees that
-// the pointer is in LDS, so these are ds_read_u16 / ds_write_b16 -- a volatile
-// access through the pointer became a flat access, which also waits on the
-// outstanding global loads of the software pipeline.
-__device__ __forceinline__ uint32_t lds_ld16(uint16_t* spi, uint32_t idx) {
-    return __hip_atomic_load(spi + idx, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
-}
-__device__ __forceinline__ void lds_st16(uint16_t* spi, uint32_t idx, uint32_t x) {
-    __hip_atomic_store(spi + idx, (uint16_t)x, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
-}
-
 // The graph's arrays come from a descriptor in memory, so the compiler cannot
 // tell their address space; they are global memory, and saying so gives
 // global (not flat) loads and stores.
 typedef __attribute__((address_space(1))) const int32_t g_cint;
 typedef __attribute__((address_space(1))) int32_t g_int;
 
+// Slots of the tree array in LDS.  Graphs of at most kWideMaxN vertices keep
+// 32-bit slots (4n bytes <= 128 KiB) and hook with the native 32-bit LDS
+// compare-and-swap; larger ones keep 16-bit slots (2n bytes) and hook with
+// lds_cas16 on the containing word.
+constexpr uint32_t kWideMaxN = 32768;
+
+// Relaxed workgroup-scope atomics, not volatile accesses: the compiler keeps
+// every access (other threads change pi concurrently) and still sees that
+// the pointer is in LDS, so these are ds_read / ds_write -- a volatile access
+// through the pointer became a flat access, which also waits on the
+// outstanding global loads of the software pipeline.
+template <typename T>
+__device__ __forceinline__ uint32_t lds_ld(T* spi, uint32_t idx) {
+    return __hip_atomic_load(spi + idx, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
+}
+template <typename T>
+__device__ __forceinline__ void lds_st(T* spi, uint32_t idx, uint32_t x) {
+    __hip_atomic_store(spi + idx, (T)x, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
+}
+// Compare-and-swap of slot idx from `expected` to `desired`; returns the value
+// found (== expected on success).
+__device__ __forceinline__ uint32_t lds_cas(uint32_t* spi, uint32_t idx, uint32_t expected,
+                                            uint32_t desired) {
+    __hip_atomic_compare_exchange_strong(spi + idx, &expected, desired, __ATOMIC_RELAXED,
+                                         __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
+    return expected;
+}
+__device__ __forceinline__ uint32_t lds_cas(uint16_t* spi, uint32_t idx, uint32_t expected,
+                                            uint32_t desired) {
+    return lds_cas16(spi, idx, expected, desired);
+}
+
 // Atomic-Hook in LDS (Fig. 3, top), same steps as the device-memory kernel;
 // with `halve`, a passed non-root H whose grandparent differs from its
-// parent is re-pointed at the grandparent (path halving).  That 16-bit store
-// cannot be lost to, nor undo, a concurrent CAS on the other half of its
-// 32-bit word: the CAS compares the whole word, so it fails and retries if
-// the store landed between its read and its swap.  In LDS the store costs
-// one write, and the shallower trees let a graph run with fewer segments
-// (fewer Multi-Jump passes over its vertices).
-__device__ __forceinline__ void lds_atomic_hook(uint16_t* spi, uint32_t pu, uint32_t pv,
-                                                bool halve) {
+// parent is re-pointed at the grandparent (path halving).  The re-point of a
+// non-root never meets a successful CAS on its own slot (that needs a root),
+// and with 16-bit slots it cannot be lost to, nor undo, a concurrent CAS on
+// the other half of its 32-bit word: that CAS compares the whole word, so it
+// fails and retries if the store landed between its read and its swap.  In
+// LDS the store costs one write, and the shallower trees let a graph run
+// with fewer segments (fewer Multi-Jump passes over its vertices).
+template <typename T>
+__device__ __forceinline__ void lds_atomic_hook(T* spi, uint32_t pu, uint32_t pv, bool halve) {
     while (pu != pv) {
         const uint32_t H = pu > pv ? pu : pv;
         const uint32_t L = pu > pv ? pv : pu;
-        const uint32_t found = lds_cas16(spi, H, H, L);
+        const uint32_t found = lds_cas(spi, H, H, L);
         if (found == H) return;
-        pu = lds_ld16(spi, found);
-        pv = lds_ld16(spi, L);
-        if (halve && pu != found) lds_st16(spi, H, pu);
+        pu = lds_ld(spi, found);
+        pv = lds_ld(spi, L);
+        if (halve && pu != found) lds_st(spi, H, pu);
     }
+}
+
+// One graph by the whole workgroup (called by every thread): init, then per
+// segment Atomic-Hook of its entries and Multi-Jump of its vertices, then the
+// labels.  Sets `bad` on an endpoint outside [0, n).
+template <typename T>
+__device__ __forceinline__ void solve_graph(T* spi, const GraphDesc& d, bool halve, bool& bad) {
+    const uint32_t tid = threadIdx.x;
+    const uint32_t nthr = blockDim.x;
+    const uint32_t n = (uint32_t)d.n;
+    g_cint* du = (g_cint*)d.u;
+    g_cint* dv = (g_cint*)d.v;
+    g_int* dout = (g_int*)d.out;
+    for (uint32_t x = tid; x < n; x += nthr) lds_st(spi, x, x);
+    __syncthreads();
+    const int32_t s = d.segments > 0 ? d.segments : 1;
+    for (int32_t seg = 0; seg < s; ++seg) {
+        const int64_t b0 = d.m * seg / s, b1 = d.m * (seg + 1) / s;
+        // kBatchEPT entries per thread per step, all loads issued before
+        // any hook, and the next step's loads issued before this step's
+        // hooks (software pipelining), so the edge stream's latency
+        // overlaps the LDS work.
+        const int64_t step = (int64_t)nthr * kBatchEPT;
+        int32_t a[kBatchEPT], b[kBatchEPT], na[kBatchEPT], nb[kBatchEPT];
+        int64_t e0 = b0 + tid;
+#pragma unroll
+        for (int j = 0; j < kBatchEPT; ++j) {
+            const int64_t e = e0 + (int64_t)j * nthr;
+            a[j] = e < b1 ? __builtin_nontemporal_load(du + e) : 0;
+            b[j] = e < b1 ? __builtin_nontemporal_load(dv + e) : 0;
+        }
+        for (; e0 < b1; e0 += step) {
+            const int64_t e1 = e0 + step;
+#pragma unroll
+            for (int j = 0; j < kBatchEPT; ++j) {
+                const int64_t e = e1 + (int64_t)j * nthr;
+                na[j] = e < b1 ? __builtin_nontemporal_load(du + e) : 0;
+                nb[j] = e < b1 ? __builtin_nontemporal_load(dv + e) : 0;
+            }
+#pragma unroll
+            for (int j = 0; j < kBatchEPT; ++j) {
+                if (e0 + (int64_t)j * nthr >= b1) continue;
+                if ((uint32_t)a[j] >= n || (uint32_t)b[j] >= n) {
+                    bad = true;
+                    continue;
+                }
+                if (a[j] == b[j]) continue;
+                lds_atomic_hook(spi, lds_ld(spi, (uint32_t)a[j]), lds_ld(spi, (uint32_t)b[j]), halve);
+            }
+#pragma unroll
+            for (int j = 0; j < kBatchEPT; ++j) {
+                a[j] = na[j];
+                b[j] = nb[j];
+            }
+        }
+        __syncthreads();
+        // Multi-Jump (Fig. 3, bottom) over the graph's vertices, low ids first.
+        for (uint32_t x = tid; x < n; x += nthr) {
+            uint32_t p = lds_ld(spi, x);
+            if (p == x) continue;
+            uint32_t g = lds_ld(spi, p);
+            while (g != p) {
+                lds_st(spi, x, g);
+                p = g;
+                g = lds_ld(spi, p);
+            }
+        }
+        __syncthreads();
+    }
+    for (uint32_t x = tid; x < n; x += nthr) dout[x] = (int32_t)lds_ld(spi, x);
+    __syncthreads();
 }
 
 __global__ __launch_bounds__(1024) void k_batch_lds(const GraphDesc* __restrict__ descs,
@@ -78,80 +171,20 @@ __global__ __launch_bounds__(1024) void k_batch_lds(const GraphDesc* __restrict_
                                                     int32_t* status, bool halve) {
     extern __shared__ uint16_t spi[];
     __shared__ int32_t next;
-    const uint32_t tid = threadIdx.x;
-    const uint32_t nthr = blockDim.x;
+    bool bad = false;
     while (true) {
-        if (tid == 0) next = atomicAdd(queue_head, 1);
+        if (threadIdx.x == 0) next = atomicAdd(queue_head, 1);
         __syncthreads();
         const int32_t idx = next;
         __syncthreads();  // everyone has read `next` before thread 0 may overwrite it
         if (idx >= count) break;
         const GraphDesc d = descs[order[idx]];
-        const uint32_t n = (uint32_t)d.n;
-        g_cint* du = (g_cint*)d.u;
-        g_cint* dv = (g_cint*)d.v;
-        g_int* dout = (g_int*)d.out;
-        for (uint32_t x = tid; x < n; x += nthr) lds_st16(spi, x, x);
-        __syncthreads();
-        bool bad = false;
-        const int32_t s = d.segments > 0 ? d.segments : 1;
-        for (int32_t seg = 0; seg < s; ++seg) {
-            const int64_t b0 = d.m * seg / s, b1 = d.m * (seg + 1) / s;
-            // kBatchEPT entries per thread per step, all loads issued before
-            // any hook, and the next step's loads issued before this step's
-            // hooks (software pipelining), so the edge stream's latency
-            // overlaps the LDS work.
-            const int64_t step = (int64_t)nthr * kBatchEPT;
-            int32_t a[kBatchEPT], b[kBatchEPT], na[kBatchEPT], nb[kBatchEPT];
-            int64_t e0 = b0 + tid;
-#pragma unroll
-            for (int j = 0; j < kBatchEPT; ++j) {
-                const int64_t e = e0 + (int64_t)j * nthr;
-                a[j] = e < b1 ? __builtin_nontemporal_load(du + e) : 0;
-                b[j] = e < b1 ? __builtin_nontemporal_load(dv + e) : 0;
-            }
-            for (; e0 < b1; e0 += step) {
-                const int64_t e1 = e0 + step;
-#pragma unroll
-                for (int j = 0; j < kBatchEPT; ++j) {
-                    const int64_t e = e1 + (int64_t)j * nthr;
-                    na[j] = e < b1 ? __builtin_nontemporal_load(du + e) : 0;
-                    nb[j] = e < b1 ? __builtin_nontemporal_load(dv + e) : 0;
-                }
-#pragma unroll
-                for (int j = 0; j < kBatchEPT; ++j) {
-                    if (e0 + (int64_t)j * nthr >= b1) continue;
-                    if ((uint32_t)a[j] >= n || (uint32_t)b[j] >= n) {
-                        bad = true;
-                        continue;
-                    }
-                    if (a[j] == b[j]) continue;
-                    lds_atomic_hook(spi, lds_ld16(spi, a[j]), lds_ld16(spi, b[j]), halve);
-                }
-#pragma unroll
-                for (int j = 0; j < kBatchEPT; ++j) {
-                    a[j] = na[j];
-                    b[j] = nb[j];
-                }
-            }
-            __syncthreads();
-            // Multi-Jump (Fig. 3, bottom) over the graph's vertices, low ids first.
-            for (uint32_t x = tid; x < n; x += nthr) {
-                uint32_t p = lds_ld16(spi, x);
-                if (p == x) continue;
-                uint32_t g = lds_ld16(spi, p);
-                while (g != p) {
-                    lds_st16(spi, x, g);
-                    p = g;
-                    g = lds_ld16(spi, p);
-                }
-            }
-            __syncthreads();
-        }
-        if (bad) atomicOr(status, kStatusRange);
-        for (uint32_t x = tid; x < n; x += nthr) dout[x] = (int32_t)lds_ld16(spi, x);
-        __syncthreads();
+        if ((uint32_t)d.n <= kWideMaxN)
+            solve_graph(reinterpret_cast<uint32_t*>(spi), d, halve, bad);
+        else
+            solve_graph(spi, d, halve, bad);
     }
+    if (bad) atomicOr(status, kStatusRange);
 }
 
 hipError_t prepare_batch_lds() {
@@ -167,7 +200,8 @@ hipError_t launch_batch_lds(const GraphDesc* descs, const int32_t* order, int32_
                             int grid, hipStream_t s) {
     if (count <= 0) return hipSuccess;
     if (max_n < 1 || max_n > 65536) return hipErrorInvalidValue;
-    const size_t lds = (((size_t)max_n + 1) / 2) * 4;  // whole 32-bit words
+    // 32-bit slots for graphs of at most kWideMaxN vertices, 16-bit above
+    const size_t lds = (uint32_t)max_n <= kWideMaxN ? (size_t)max_n * 4 : (size_t)kWideMaxN * 4;
     k_batch_lds<<<grid, 1024, lds, s>>>(descs, order, count, queue_head, status, halve);
     return hipGetLastError();
 }

@@ -511,15 +511,16 @@ int32_t enqueue_atomic(int32_t n, const int32_t* u, const int32_t* v, int64_t m,
             else
                 TIMED(kPhaseHook, launch_ahook(u, v, bound(g), bound(h), pi, n, ctrl, bits,
                                                p.block, p.ept, p.coherent, p.halve, p.symmetric, s));
-            TIMED(kPhaseCompress, launch_mj(pi, n, nullptr, p.coherent, s));
+            if (h < S && !p.coherent) {
+                // Compress, bitmap refresh and hot-word refresh in one pass
+                TIMED(kPhaseCompress, launch_mj_bitmap(pi, n, ctrl, bits, hot ? fb.hot_tags : nullptr,
+                                                       fb.hot_vals, p.hot_slots, s));
+            } else {
+                TIMED(kPhaseCompress, launch_mj(pi, n, nullptr, p.coherent, s));
+                if (h < S) TIMED(kPhaseOther, launch_bitmap(pi, n, ctrl, bits, s));
+            }
             ++hooks;
             ++jumps;
-            if (h < S) {
-                TIMED(kPhaseOther, launch_bitmap(pi, n, ctrl, bits, s));
-                if (hot)
-                    TIMED(kPhaseOther, launch_hot_values(bits, fb.hot_tags, fb.hot_vals, ctrl,
-                                                         p.hot_slots, s));
-            }
             g = h;
             step *= kSuperGrowth;
         }

@@ -30,6 +30,10 @@ hipError_t launch_sample_giant(const int32_t* u, int64_t m, const int32_t* pi, i
 // bits[v] = (pi[v] == pi[ctrl->giant]) for v < n (stars required); no-op
 // unless ctrl->filter_on.
 hipError_t launch_bitmap(const int32_t* pi, int32_t n, Ctrl* ctrl, uint32_t* bits, hipStream_t s);
+// Multi-Jump, then (when ctrl->filter_on) the giant bitmap and, when hot_tags
+// is non-null, the cached words of the hot-word table, in one pass.
+hipError_t launch_mj_bitmap(int32_t* pi, int32_t n, Ctrl* ctrl, uint32_t* bits,
+                            const uint32_t* hot_tags, uint32_t* hot_vals, int slots, hipStream_t s);
 
 // Atomic-free Hook (Fig. 2) of round `round` (1-based).  Round 1 reads the
 // input entries [0, m) and checks ranges; later rounds read the frontier of

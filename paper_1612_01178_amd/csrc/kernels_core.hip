@@ -404,6 +404,93 @@ hipError_t launch_bitmap(const int32_t* pi, int32_t n, Ctrl* ctrl, uint32_t* bit
     return hipGetLastError();
 }
 
+// ----------------------------------------------------------------------------- MJ + bitmap
+// Bits 0..7 of x moved to bits 0, 4, 8, ..., 28.
+__device__ __forceinline__ uint32_t spread4(uint32_t x) {
+    x = (x | (x << 12)) & 0x000F000Fu;
+    x = (x | (x << 6)) & 0x03030303u;
+    x = (x | (x << 3)) & 0x11111111u;
+    return x;
+}
+
+// Multi-Jump (as k_mj) and, when the filter is on, the giant bitmap rebuilt
+// in the same pass (as k_bitmap) and the cached words of the hot-word table
+// refreshed (as k_hot_values), instead of three passes over pi.  Each thread
+// jumps its 4 vertices to their roots; the giant's current root is found by
+// climbing from the last giant label (other threads' jumps only move values
+// up, and no hook runs, so the climb ends at the root); a vertex's bit is
+// (its root == that root).  A wave covers 256 consecutive vertices: one
+// ballot per slot j (bit l = vertex 4l + j), and lane w < 8 assembles word w
+// (vertices 32w .. 32w + 31) from byte w of the four ballots.
+template <bool VEC>
+__global__ __launch_bounds__(256) void k_mj_bitmap(int32_t* pi, int32_t n, Ctrl* ctrl,
+                                                   uint32_t* __restrict__ bits,
+                                                   const uint32_t* __restrict__ hot_tags,
+                                                   uint32_t* __restrict__ hot_vals, int slots) {
+    const int64_t base = ((int64_t)blockIdx.x * blockDim.x + threadIdx.x) * 4;
+    int32_t p[4];
+    if (VEC && base + 3 < n) {
+        v4i q = *reinterpret_cast<const v4i*>(pi + base);
+        p[0] = q.x;
+        p[1] = q.y;
+        p[2] = q.z;
+        p[3] = q.w;
+    } else {
+#pragma unroll
+        for (int j = 0; j < 4; ++j)
+            p[j] = (base + j < n) ? ld_tree<false>(pi + base + j) : (int32_t)(base + j);
+    }
+    int32_t gp[4];
+#pragma unroll
+    for (int j = 0; j < 4; ++j) gp[j] = (p[j] != base + j) ? ld_tree<false>(pi + p[j]) : p[j];
+#pragma unroll
+    for (int j = 0; j < 4; ++j) {
+        int32_t q = p[j], g = gp[j];
+        while (g != q) {
+            st_tree<false>(pi + base + j, g);
+            q = g;
+            g = ld_tree<false>(pi + q);
+        }
+        p[j] = q;  // the root
+    }
+    if (!ctrl->filter_on) return;
+    int32_t groot = ctrl->giant;
+    for (int32_t up = ld_tree<false>(pi + groot); up != groot; up = ld_tree<false>(pi + groot))
+        groot = up;
+    const int lane = threadIdx.x & 63;
+    uint64_t m4[4];
+#pragma unroll
+    for (int j = 0; j < 4; ++j) m4[j] = __ballot(base + j < n && p[j] == groot);
+    if (lane < 8) {
+        const int64_t wave_base = base - 4 * lane;  // vertex of lane 0
+        const int64_t w = wave_base / 32 + lane;
+        if (w * 32 < n) {
+            uint32_t word = 0;
+#pragma unroll
+            for (int j = 0; j < 4; ++j) word |= spread4((uint32_t)(m4[j] >> (8 * lane)) & 0xffu) << j;
+            bits[w] = word;
+            if (hot_tags) {
+                const uint32_t slot = (uint32_t)w & (uint32_t)(slots - 1);
+                if (hot_tags[slot] == (uint32_t)(w / slots)) hot_vals[slot] = word;
+            }
+        }
+    }
+    if (blockIdx.x == 0 && threadIdx.x == 0) ctrl->giant = groot;
+}
+
+hipError_t launch_mj_bitmap(int32_t* pi, int32_t n, Ctrl* ctrl, uint32_t* bits,
+                            const uint32_t* hot_tags, uint32_t* hot_vals, int slots, hipStream_t s) {
+    if (n <= 0) return hipSuccess;
+    if (hot_tags && slots != 16384 && slots != 32768) return hipErrorInvalidValue;
+    const int64_t groups = ((int64_t)n + 3) / 4;
+    const int grid = (int)((groups + 255) / 256);
+    if (((uintptr_t)pi & 15) == 0)
+        k_mj_bitmap<true><<<grid, 256, 0, s>>>(pi, n, ctrl, bits, hot_tags, hot_vals, slots);
+    else
+        k_mj_bitmap<false><<<grid, 256, 0, s>>>(pi, n, ctrl, bits, hot_tags, hot_vals, slots);
+    return hipGetLastError();
+}
+
 // ----------------------------------------------------------------------------- atomic-free Hook
 // Source of round `round` of the atomic-free Hook, from the record the
 // previous round's compaction left: the input lists in round 1; later, the

@@ -239,6 +239,7 @@ ABLATION = [
     ("plain_device_convergence", dict(hook="plain")),
     ("plain_tau500", dict(hook="plain", compact_threshold=500)),
     ("plain_tau100", dict(hook="plain", compact_threshold=100)),
+    ("hybrid_round_then_atomic", dict(hook="hybrid")),
     ("library_auto", dict()),
 ]
 SEGMENT_SWEEP = [1, 2, 4, 8, 16, 32, 64, 128]

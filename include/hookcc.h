@@ -58,12 +58,18 @@ extern "C" {
 #define CC_ERR_NOCONVERGE (-5) /* the atomic-free Hook hit opts->max_rounds       */
 
 /* ---------------------------------------------------------------- options */
-#define CC_HOOK_AUTO 0   /* library choice (the default): Atomic-Hook for lists of
-                            m >= 2^22 entries (with the giant filter when m / n >= 8),
-                            the atomic-free Hook for smaller lists                     */
+#define CC_HOOK_AUTO 0   /* library choice (the default): for lists of m >= 2^22
+                            entries the Atomic-Hook with the giant filter when
+                            m / n >= 8 and the hybrid plan below otherwise; the
+                            atomic-free Hook for smaller lists (the hybrid plan for a
+                            no-sync call); the Atomic-Hook with the symmetric flag    */
 #define CC_HOOK_ATOMIC 1 /* Atomic-Hook (Fig. 3, CAS on roots) + segmentation (Fig. 4) */
 #define CC_HOOK_PLAIN 2  /* atomic-free Hook (Fig. 2) rounds until no change (Fig. 1),
                             convergence test and active-edge frontier on the device   */
+#define CC_HOOK_HYBRID 3 /* one atomic-free Hook round (Fig. 2) over all entries with its
+                            Multi-Jump and frontier compaction, then Atomic-Hook (Fig. 3,
+                            path halving) over the still-active root pairs and a final
+                            Multi-Jump: a fixed launch sequence, no host read        */
 
 #define CC_FILTER_OFF 0  /* Atomic-Hook only: hook every edge entry                   */
 #define CC_FILTER_GIANT 1 /* Atomic-Hook only: after the first segment(s), sample the
@@ -74,7 +80,8 @@ extern "C" {
 #define CC_FILTER_AUTO 2 /* library chooses (the default)                             */
 
 typedef struct cc_options {
-    int32_t hook;             /* CC_HOOK_AUTO (default), CC_HOOK_ATOMIC or CC_HOOK_PLAIN  */
+    int32_t hook;             /* CC_HOOK_AUTO (default), CC_HOOK_ATOMIC, CC_HOOK_PLAIN or
+                                 CC_HOOK_HYBRID                                          */
     int32_t segments;         /* Atomic-Hook: number of edge segments s; 0 = default
                                  max(1, round(m / n)) (8x that when CC_HOOK_AUTO picks the
                                  filtered Atomic-Hook, so the first segment is ~n/8

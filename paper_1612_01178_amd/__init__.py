@@ -30,7 +30,7 @@ CC_ERR_HIP = -4
 CC_ERR_NOCONVERGE = -5
 CC_BATCH_LDS_MAX_N = 65536
 
-_HOOKS = {"auto": 0, "atomic": 1, "plain": 2}
+_HOOKS = {"auto": 0, "atomic": 1, "plain": 2, "hybrid": 3}
 _FILTERS = {"off": 0, "giant": 1, "auto": 2}
 _HOST_LOOPS = {"off": 0, "jump": 1, "multijump": 2}
 

@@ -8,7 +8,7 @@ coordinate by coordinate from the library's default:
 
 1. hook variant and Hook-to-Compress switch: the paper's segment count
    s = round(m / n) (Section 3.B) and multiples of it, with and without the
-   giant-component filter, plus the atomic-free Hook;
+   giant-component filter, plus the atomic-free Hook and the hybrid plan;
 2. edge entries per thread (4, 8, 16);
 3. threads per workgroup (256, 512, 1024);
 4. when the atomic-free Hook wins, the frontier compaction threshold tau
@@ -104,7 +104,7 @@ def tune(u, v, n: int, *, reps: int = 3, cache: bool = True, path: str | None = 
     base = Options()
     best_t, best = run(base), base
     # 1. hook variant, segment count, filter
-    cands = [Options(hook="plain")]
+    cands = [Options(hook="plain"), Options(hook="hybrid")]
     for mult in (0.25, 0.5, 1, 2, 4, 8, 16):
         s = max(1, int(round(s0 * mult)))
         cands.append(Options(hook="atomic", segments=s, filter="off"))

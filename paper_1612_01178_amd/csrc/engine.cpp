@@ -55,7 +55,7 @@ int size_class(uint64_t w) {
 
 // ---------------------------------------------------------------------- plans
 struct Plan {
-    int hook = CC_HOOK_ATOMIC;  // resolved variant: CC_HOOK_ATOMIC or CC_HOOK_PLAIN
+    int hook = CC_HOOK_ATOMIC;  // resolved variant: CC_HOOK_ATOMIC, CC_HOOK_PLAIN or CC_HOOK_HYBRID
     int segments = 1;
     int filter = CC_FILTER_OFF;
     int filter_after = 1;
@@ -101,32 +101,39 @@ int32_t make_plan(int32_t n, int64_t m, const cc_options* o, Plan& p, bool allow
     if (op.coherent_loads != 0 && op.coherent_loads != 1)
         return fail(CC_ERR_ARG, "cc_options.coherent_loads must be 0 or 1");
     p.coherent = op.coherent_loads == 1;
-    if (op.hook != CC_HOOK_AUTO && op.hook != CC_HOOK_ATOMIC && op.hook != CC_HOOK_PLAIN)
+    if (op.hook != CC_HOOK_AUTO && op.hook != CC_HOOK_ATOMIC && op.hook != CC_HOOK_PLAIN &&
+        op.hook != CC_HOOK_HYBRID)
         return fail(CC_ERR_ARG, "unknown cc_options.hook");
     if (op.segments < 0) return fail(CC_ERR_ARG, "cc_options.segments < 0");
     // Average-degree heuristic (Section 3.B, Fig. 4): s = 2|E|/|V| with |E|
     // counted once per undirected edge, i.e. s = (entries passed) / n.
     const int64_t s_paper = n > 0 ? std::max<int64_t>(1, (m + n / 2) / n) : 1;
-    // Automatic variant (measured on gfx950): on large lists Atomic-Hook with
-    // path halving wins (one pass over the entries; R-MAT 24 4.6 ms vs 38 ms,
-    // percolated 4096^2 grid 1.11 vs 1.21 ms), and from average degree 8 the
-    // giant filter turns most entries into two bitmap tests.  On small lists
-    // (< 2^22 entries) the per-kernel cost dominates and the atomic-free
-    // rounds, with fewer kernels, win (ER 2^16: 0.09 vs 0.27 ms).
+    // Automatic variant (measured on gfx950): on large dense lists (average
+    // degree >= 8) the filtered Atomic-Hook wins (one pass over the entries,
+    // most of them reduced to two bitmap tests; R-MAT 24 4.6 ms against 38 ms
+    // for the atomic-free rounds); on large sparse lists the hybrid plan (one
+    // atomic-free round, then Atomic-Hook over the surviving root pairs;
+    // percolated 4096^2 grid 0.85 ms against 1.08 Atomic-Hook and 1.23
+    // atomic-free rounds).  On small lists (< 2^22 entries) the per-kernel
+    // cost dominates and the atomic-free rounds win (ER 2^16: 0.09 ms against
+    // 0.17 hybrid and 0.27 Atomic-Hook); a no-sync call needs a fixed launch
+    // sequence and takes the hybrid plan there.
     const bool large = m >= (int64_t(1) << 22);
     const bool dense_large = large && n > 0 && m >= 8 * (int64_t)n;
     bool auto_filtered = false;
     if (op.hook == CC_HOOK_AUTO) {
-        if (large || !allow_plain || op.symmetric == 1 || op.no_sync == 1) {
+        if (!allow_plain || op.symmetric == 1 || dense_large) {
             p.hook = CC_HOOK_ATOMIC;
             auto_filtered = dense_large && op.filter != CC_FILTER_OFF;
+        } else if (large || op.no_sync == 1) {
+            p.hook = CC_HOOK_HYBRID;
         } else {
             p.hook = CC_HOOK_PLAIN;
         }
     } else {
         p.hook = op.hook;
     }
-    if (!allow_plain && p.hook == CC_HOOK_PLAIN)
+    if (!allow_plain && (p.hook == CC_HOOK_PLAIN || p.hook == CC_HOOK_HYBRID))
         return fail(CC_ERR_ARG, "the atomic-free Hook is not available here");
     int64_t s = op.segments;
     if (s == 0) s = auto_filtered ? 8 * s_paper : s_paper;
@@ -177,9 +184,9 @@ int32_t make_plan(int32_t n, int64_t m, const cc_options* o, Plan& p, bool allow
     p.host_loop = op.host_loop;
     if (p.symmetric && p.hook != CC_HOOK_ATOMIC)
         return fail(CC_ERR_ARG, "cc_options.symmetric needs the Atomic-Hook");
-    if (p.hook == CC_HOOK_PLAIN && m >= (int64_t(1) << 32))
+    if ((p.hook == CC_HOOK_PLAIN || p.hook == CC_HOOK_HYBRID) && m >= (int64_t(1) << 32))
         return fail(CC_ERR_ARG, "atomic-free Hook supports m < 2^32 entries");
-    if (p.no_sync && (p.hook != CC_HOOK_ATOMIC || p.profile))
+    if (p.no_sync && ((p.hook != CC_HOOK_ATOMIC && p.hook != CC_HOOK_HYBRID) || p.profile))
         return fail(CC_ERR_ARG,
                     "cc_options.no_sync needs the Atomic-Hook (the atomic-free Hook reads the "
                     "device convergence word from the host) and profile = 0");
@@ -213,6 +220,11 @@ Layout layout(int32_t n, int64_t m, const Plan& p) {
         L.f0 = off;
         off += align256((size_t)m * 8);
         L.f1 = off;
+        off += align256((size_t)m * 8);
+    }
+    if (p.hook == CC_HOOK_HYBRID) {  // one frontier: round 1 writes it, nothing rewrites it
+        L.cap = m;
+        L.f0 = L.f1 = off;
         off += align256((size_t)m * 8);
     }
     L.total = off;
@@ -536,6 +548,34 @@ int32_t enqueue_atomic(int32_t n, const int32_t* u, const int32_t* v, int64_t m,
 // reading the control block after each block.  With `graph`, each block's
 // launches (block b: rounds bK+1 .. bK+K; block 0 also the init) are
 // captured once per (arrays, sizes, plan, b) and replayed.
+// Hybrid plan: one atomic-free Hook round (Fig. 2) over all entries, its
+// Multi-Jump, and the compaction of the still-active entries into root
+// pairs; then one Atomic-Hook pass with path halving (Fig. 3) over those
+// pairs and a final Multi-Jump (skipped on the device when no pair was
+// active).  Trees only merge, so an entry dropped by the compaction stays
+// satisfied; the pairs were roots when compacted, valid starting parents
+// for the climb.  A fixed launch sequence: no host read until the end.
+int32_t enqueue_hybrid(int32_t n, const int32_t* u, const int32_t* v, int64_t m, int32_t* pi,
+                       const Plan& p, char* ws, const Layout& L, hipStream_t s, Timer& tm,
+                       cc_stats* st) {
+    Ctrl* ctrl = reinterpret_cast<Ctrl*>(ws);
+    int2* F = reinterpret_cast<int2*>(ws + L.f0);
+    const int grid_cap = device_cu_count() * 8;
+    TIMED(kPhaseOther, launch_init(pi, n, ctrl, s));
+    TIMED(kPhaseHook, launch_hook_plain(1, u, v, m, F, F, pi, n, ctrl, p.block, p.ept, grid_cap, s));
+    TIMED(kPhaseCompress, launch_mj(pi, n, nullptr, false, s));
+    // round 1 reads the input lists and writes its survivors to F, count[1]
+    TIMED(kPhaseHook, launch_compact(1, u, v, m, F, F, L.cap, pi, n, ctrl, 0xffffffffu, p.block,
+                                     p.ept, grid_cap, s));
+    TIMED(kPhaseHook, launch_ahook_pairs(F, &ctrl->count[1], L.cap, pi, p.halve, grid_cap, s));
+    TIMED(kPhaseCompress, launch_mj(pi, n, &ctrl->count[1], false, s));
+    if (st) {
+        st->hook_launches += 3;
+        st->compress_launches += 2;
+    }
+    return CC_OK;
+}
+
 int32_t solve_plain(int32_t n, const int32_t* u, const int32_t* v, int64_t m, int32_t* pi,
                     const Plan& p, char* ws, const Layout& L, hipStream_t s, PoolEntry* pe,
                     bool use_graph, Timer& tm, cc_stats* st, int64_t* rounds_run) {
@@ -698,20 +738,22 @@ int32_t labels_impl(int32_t n, const int32_t* u, const int32_t* v, int64_t m, in
     tm.on = p.profile;
     tm.s = s;
     int64_t rounds = 0;
-    if (p.hook == CC_HOOK_ATOMIC) {
+    if (p.hook == CC_HOOK_ATOMIC || p.hook == CC_HOOK_HYBRID) {
+        // fixed launch sequences: no host read until the end
+        auto enqueue = [&](cc_stats* sx) {
+            if (p.hook == CC_HOOK_HYBRID)
+                return enqueue_hybrid(n, u, v, m, out, p, ws, L, s, tm, sx);
+            return enqueue_atomic(n, u, v, m, out, p, reinterpret_cast<Ctrl*>(ws),
+                                  filter_bufs(ws, L), s, tm, sx);
+        };
         if (p.graph && s != nullptr && !p.profile) {
             KeyHash k;
-            k.add(n).add(m).add(u).add(v).add(out).add(ws).add(s).add(p.segments).add(p.filter)
-                .add(p.filter_after).add(p.block).add(p.ept).add(p.coherent).add(p.hot)
-                .add(p.hot_slots).add(p.halve).add(p.symmetric);
-            cc_stats* st_capture = st;
-            rc = run_graph(pe, k.h, s, [&]() {
-                return enqueue_atomic(n, u, v, m, out, p, reinterpret_cast<Ctrl*>(ws),
-                                      filter_bufs(ws, L), s, tm, st_capture);
-            });
+            k.add(n).add(m).add(u).add(v).add(out).add(ws).add(s).add(p.hook).add(p.segments)
+                .add(p.filter).add(p.filter_after).add(p.block).add(p.ept).add(p.coherent)
+                .add(p.hot).add(p.hot_slots).add(p.halve).add(p.symmetric);
+            rc = run_graph(pe, k.h, s, [&]() { return enqueue(st); });
         } else {
-            rc = enqueue_atomic(n, u, v, m, out, p, reinterpret_cast<Ctrl*>(ws), filter_bufs(ws, L),
-                                s, tm, st);
+            rc = enqueue(st);
         }
         if (rc == CC_OK && p.no_sync) {
             rc = post_async(pe, s, reinterpret_cast<const Ctrl*>(ws));

@@ -45,6 +45,10 @@ hipError_t launch_hook_plain(int round, const int32_t* u, const int32_t* v, int6
 // Frontier compaction after the Compress of round `round`: keeps the entries
 // whose endpoints still have different roots, written as root pairs to
 // `dst` (capacity cap), size accumulated in ctrl->count[round & 1].
+// Atomic-Hook with path halving of the *count root pairs of a frontier.
+hipError_t launch_ahook_pairs(const int2* fr, const uint32_t* count, int64_t cap, int32_t* pi,
+                              bool halve, int grid_cap, hipStream_t s);
+
 // tau: frontier rewrite threshold in thousandths (0xffffffff = every round).
 hipError_t launch_compact(int round, const int32_t* u, const int32_t* v, int64_t m, int2* f0,
                           int2* f1, int64_t cap, const int32_t* pi, int32_t n, Ctrl* ctrl,

@@ -748,6 +748,44 @@ hipError_t launch_compact(int round, const int32_t* u, const int32_t* v, int64_t
     return hipGetLastError();
 }
 
+// ----------------------------------------------------------------------------- frontier Atomic-Hook
+// Atomic-Hook (Fig. 3, with path halving) of a frontier of root pairs left
+// by a compaction: *count pairs (at most cap), each a pair of roots at the
+// time of the compaction, so the climb starts from the pair itself (values
+// only ever name vertices of the same tree, smaller than the slot) without
+// gathering pi first.  Persistent grid over the pairs, consecutive lanes on
+// consecutive pairs.
+template <int EPT, bool HALVE>
+__global__ __launch_bounds__(256) void k_ahook_pairs(const int2* __restrict__ fr,
+                                                     const uint32_t* count, int64_t cap,
+                                                     int32_t* pi) {
+    const int64_t total = min((int64_t)*count, cap);
+    const int64_t tile = (int64_t)blockDim.x * EPT;
+    for (int64_t t0 = (int64_t)blockIdx.x * tile; t0 < total; t0 += (int64_t)gridDim.x * tile) {
+        int2 q[EPT];
+#pragma unroll
+        for (int j = 0; j < EPT; ++j) {
+            const int64_t e = t0 + (int64_t)j * blockDim.x + threadIdx.x;
+            q[j] = e < total ? fr[e] : int2{0, 0};
+        }
+#pragma unroll
+        for (int j = 0; j < EPT; ++j)
+            if (q[j].x != q[j].y) atomic_hook<false, HALVE>(pi, q[j].x, q[j].y);
+    }
+}
+
+hipError_t launch_ahook_pairs(const int2* fr, const uint32_t* count, int64_t cap, int32_t* pi,
+                              bool halve, int grid_cap, hipStream_t s) {
+    constexpr int EPT = 8;
+    const int64_t tile = 256 * EPT;
+    int64_t grid64 = (cap + tile - 1) / tile;
+    if (grid64 < 1) grid64 = 1;
+    if (grid64 > grid_cap) grid64 = grid_cap;
+    if (halve) k_ahook_pairs<EPT, true><<<(int)grid64, 256, 0, s>>>(fr, count, cap, pi);
+    else k_ahook_pairs<EPT, false><<<(int)grid64, 256, 0, s>>>(fr, count, cap, pi);
+    return hipGetLastError();
+}
+
 // ----------------------------------------------------------------------------- Fig. 1 host loop
 // Hook (Fig. 2) over every entry, raising ctrl->hook_changed (one store per
 // wave that saw an active entry) -- the flag the host reads after the launch.

@@ -109,6 +109,11 @@ def test_host_side_argument_errors(lib):
         assert lib.cc_labels_ex(4, dummy, dummy, 1, dummy, ctypes.byref(bad), None, 0, None,
                                 None) == cc.CC_ERR_ARG, tau
     bad = cc._COptions()
+    bad.hook = 3  # the hybrid plan starts with the atomic-free Hook: no symmetric flag
+    bad.symmetric = 1
+    assert lib.cc_labels_ex(4, dummy, dummy, 1, dummy, ctypes.byref(bad), None, 0, None,
+                            None) == cc.CC_ERR_ARG
+    bad = cc._COptions()
     bad.no_sync = 2
     assert lib.cc_labels_ex(4, dummy, dummy, 1, dummy, ctypes.byref(bad), None, 0, None,
                             None) == cc.CC_ERR_ARG
@@ -143,6 +148,8 @@ def test_workspace_sizes(lib):
     assert hot == 256 + 2 * (n // 32) * 4 + 2 * 32768 * 4
     plain = cc.workspace_bytes(n, m, cc.Options(hook="plain"))
     assert plain == 256 + 2 * m * 8
+    hybrid = cc.workspace_bytes(n, m, cc.Options(hook="hybrid"))
+    assert hybrid == 256 + m * 8
     assert cc.workspace_bytes(-1, 5) == 0
 
 

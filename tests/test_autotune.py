@@ -43,6 +43,7 @@ def test_tuned_plans_are_exact(tmp_path):
     best, table = autotune.tune(du, dv, n, reps=1, path=path)
     fields = {k for _, o in table for k, val in o.items() if val != getattr(cc.Options(), k)}
     assert {"hook", "segments", "filter", "edges_per_thread", "block"} <= fields
+    assert {o["hook"] for _, o in table} >= {"auto", "plain", "hybrid", "atomic"}
     if best.hook in ("plain", "auto"):
         assert "compact_threshold" in fields
     assert autotune.options_for(n, len(u), path=path) == best

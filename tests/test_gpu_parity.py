@@ -54,6 +54,8 @@ VARIANTS = {
     "coherent_giant": cc.Options(hook="atomic", coherent_loads=True, segments=6, filter="giant"),
     "coherent_s3": cc.Options(hook="atomic", coherent_loads=True, segments=3, filter="off",
                               block=128),
+    "hybrid": cc.Options(hook="hybrid"),
+    "hybrid_nohalve_e4": cc.Options(hook="hybrid", path_halving="off", edges_per_thread=4),
     "hostloop_jump": cc.Options(hook="plain", host_loop="jump"),
     "hostloop_multijump": cc.Options(hook="plain", host_loop="multijump", edges_per_thread=16),
 }
@@ -334,7 +336,7 @@ def test_full_size_workloads_match_oracle_digest(dev, name):
     du, dv = to_dev(u, dev), to_dev(v, dev)
     del u, v
     for opt in ("default", "plain", "atomic", "s1", "coherent_giant", "s6_giant_nohot_e4",
-                "s12_giant_hotlarge_e16", "s8_giant_nohalve"):
+                "s12_giant_hotlarge_e16", "s8_giant_nohalve", "hybrid"):
         if name == "rmat24" and opt == "s1":
             opt = "s9_giant_after3"
         say("full size", name, opt)
@@ -358,7 +360,8 @@ def test_repeated_solves_on_deep_trees_stay_exact(dev):
     del u, v, want_np
     out = torch.empty(n, dtype=torch.int32, device=dev)
     reps = 12
-    for opt in ("default", "s1", "s12_giant_hotlarge_e16", "s5_giant_b1024_e16", "coherent_s3"):
+    for opt in ("default", "s1", "s12_giant_hotlarge_e16", "s5_giant_b1024_e16", "coherent_s3",
+                "hybrid"):
         say("repeated solves grid4k", opt, reps)
         bad = 0
         for _ in range(reps):

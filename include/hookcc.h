@@ -69,7 +69,9 @@ extern "C" {
 #define CC_HOOK_HYBRID 3 /* one atomic-free Hook round (Fig. 2) over all entries with its
                             Multi-Jump and frontier compaction, then Atomic-Hook (Fig. 3,
                             path halving) over the still-active root pairs and a final
-                            Multi-Jump: a fixed launch sequence, no host read        */
+                            Multi-Jump: a fixed launch sequence, no host read.  For CSR
+                            input: an atomic-free pass and an Atomic-Hook pass over all
+                            entries, each followed by a Multi-Jump                  */
 
 #define CC_FILTER_OFF 0  /* Atomic-Hook only: hook every edge entry                   */
 #define CC_FILTER_GIANT 1 /* Atomic-Hook only: after the first segment(s), sample the
@@ -291,7 +293,9 @@ int32_t cc_labels_host(int32_t n, const int32_t* host_u, const int32_t* host_v, 
  *   row_ptr    [device] int64[n+1]: row_ptr[0] == 0, non-decreasing, row_ptr[n] == m
  *   col        [device] int32[m], ids in [0, n)
  *   out_label  [device] int32[n]
- *   opts       as cc_labels_ex (hook must be CC_HOOK_AUTO or CC_HOOK_ATOMIC);
+ *   opts       as cc_labels_ex; hook CC_HOOK_AUTO, CC_HOOK_ATOMIC or CC_HOOK_HYBRID
+ *              (AUTO: the hybrid plan for m >= 2^22 entries with m / n < 8, else
+ *              the Atomic-Hook, filtered when m >= 2^22 and m / n >= 8);
  *              opts->symmetric = 1 promises a symmetric adjacency (every pair in
  *              both rows) and hooks only the entries with col > row
  * Synchronous on `stream` (NULL = null stream) unless opts->no_sync = 1 (as

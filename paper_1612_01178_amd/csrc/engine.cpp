@@ -75,7 +75,15 @@ struct Plan {
     uint32_t tau = 0xffffffffu;  // atomic-free Hook: frontier rewrite threshold (1/1000)
 };
 
-int32_t make_plan(int32_t n, int64_t m, const cc_options* o, Plan& p, bool allow_plain = true) {
+// Hook variants an input form supports: pair lists all of them; CSR input the
+// Atomic-Hook and the hybrid plan (its atomic-free pass needs no frontier);
+// the graph-list path the Atomic-Hook only.
+enum PlanInput { kInputPairs, kInputCsr, kInputAtomicOnly };
+
+int32_t make_plan(int32_t n, int64_t m, const cc_options* o, Plan& p,
+                  PlanInput input = kInputPairs) {
+    const bool allow_plain = input == kInputPairs;
+    const bool allow_hybrid = input != kInputAtomicOnly;
     cc_options d;
     std::memset(&d, 0, sizeof d);
     d.filter = CC_FILTER_AUTO;
@@ -117,14 +125,18 @@ int32_t make_plan(int32_t n, int64_t m, const cc_options* o, Plan& p, bool allow
     // atomic-free rounds).  On small lists (< 2^22 entries) the per-kernel
     // cost dominates and the atomic-free rounds win (ER 2^16: 0.09 ms against
     // 0.17 hybrid and 0.27 Atomic-Hook); a no-sync call needs a fixed launch
-    // sequence and takes the hybrid plan there.
+    // sequence and takes the hybrid plan there.  CSR input has no atomic-free
+    // rounds: its large sparse inputs take the hybrid plan (grid as CSR 0.93
+    // ms against 1.47 Atomic-Hook), the rest the Atomic-Hook.
     const bool large = m >= (int64_t(1) << 22);
     const bool dense_large = large && n > 0 && m >= 8 * (int64_t)n;
     bool auto_filtered = false;
     if (op.hook == CC_HOOK_AUTO) {
-        if (!allow_plain || op.symmetric == 1 || dense_large) {
+        if (!allow_hybrid || (allow_plain && op.symmetric == 1) || dense_large) {
             p.hook = CC_HOOK_ATOMIC;
             auto_filtered = dense_large && op.filter != CC_FILTER_OFF;
+        } else if (!allow_plain) {
+            p.hook = large ? CC_HOOK_HYBRID : CC_HOOK_ATOMIC;
         } else if (large || op.no_sync == 1) {
             p.hook = CC_HOOK_HYBRID;
         } else {
@@ -133,7 +145,7 @@ int32_t make_plan(int32_t n, int64_t m, const cc_options* o, Plan& p, bool allow
     } else {
         p.hook = op.hook;
     }
-    if (!allow_plain && (p.hook == CC_HOOK_PLAIN || p.hook == CC_HOOK_HYBRID))
+    if ((!allow_plain && p.hook == CC_HOOK_PLAIN) || (!allow_hybrid && p.hook == CC_HOOK_HYBRID))
         return fail(CC_ERR_ARG, "the atomic-free Hook is not available here");
     int64_t s = op.segments;
     if (s == 0) s = auto_filtered ? 8 * s_paper : s_paper;
@@ -189,7 +201,7 @@ int32_t make_plan(int32_t n, int64_t m, const cc_options* o, Plan& p, bool allow
     if (op.host_loop != CC_HOST_LOOP_OFF && op.hook != CC_HOOK_PLAIN)
         return fail(CC_ERR_ARG, "cc_options.host_loop needs hook = CC_HOOK_PLAIN");
     p.host_loop = op.host_loop;
-    if (p.symmetric && p.hook != CC_HOOK_ATOMIC)
+    if (p.symmetric && p.hook != CC_HOOK_ATOMIC && !(input == kInputCsr && p.hook == CC_HOOK_HYBRID))
         return fail(CC_ERR_ARG, "cc_options.symmetric needs the Atomic-Hook");
     if ((p.hook == CC_HOOK_PLAIN || p.hook == CC_HOOK_HYBRID) && m >= (int64_t(1) << 32))
         return fail(CC_ERR_ARG, "atomic-free Hook supports m < 2^32 entries");
@@ -813,7 +825,7 @@ int32_t stream_impl(int32_t n, const int32_t* hu, const int32_t* hv, int64_t m, 
     if (opts && opts->no_sync)
         return fail(CC_ERR_ARG, "cc_options.no_sync is for cc_labels_ex and cc_labels_csr only");
     Plan p;
-    rc = make_plan(n, m, opts, p, /*allow_plain=*/false);
+    rc = make_plan(n, m, opts, p, kInputAtomicOnly);
     if (rc != CC_OK) return rc;
     // Giant filter: as asked, or (auto) for dense lists that span several chunks.
     const int32_t fopt = opts ? opts->filter : CC_FILTER_AUTO;
@@ -893,7 +905,12 @@ int32_t stream_impl(int32_t n, const int32_t* hu, const int32_t* hv, int64_t m, 
 // ---------------------------------------------------------------------- CSR input
 // Same plan as a pair list of m entries (segments of the col[] array, each
 // followed by a Multi-Jump; with the giant filter the growing super-segments
-// of enqueue_atomic); the first endpoint of an entry is its row.
+// of enqueue_atomic); the first endpoint of an entry is its row.  The hybrid
+// plan is one atomic-free Hook pass over all entries, a Multi-Jump, then one
+// Atomic-Hook pass (with path halving) over all entries and a Multi-Jump: the
+// first pass joins nearly everything with plain stores, and the second, in
+// which almost every entry finds its endpoints already in one tree, restores
+// the links the first pass overwrote.  CSR needs no frontier for it.
 int32_t csr_impl(int32_t n, const int64_t* row_ptr, const int32_t* col, int64_t m, int32_t* out,
                  const cc_options* opts, hipStream_t s, cc_stats* st) {
     if (n < 0 || m < 0) return fail(CC_ERR_ARG, "n < 0 or m < 0");
@@ -901,14 +918,14 @@ int32_t csr_impl(int32_t n, const int64_t* row_ptr, const int32_t* col, int64_t 
     if (m > 0 && !col) return fail(CC_ERR_ARG, "null col with m > 0");
     if (n > 0 && !out) return fail(CC_ERR_ARG, "null out_label with n > 0");
     if (opts && opts->hook == CC_HOOK_PLAIN)
-        return fail(CC_ERR_ARG, "CSR input uses the Atomic-Hook");
+        return fail(CC_ERR_ARG, "CSR input uses the Atomic-Hook or the hybrid plan");
     Plan p;
-    int32_t rc = make_plan(n, m, opts, p, /*allow_plain=*/false);
+    int32_t rc = make_plan(n, m, opts, p, kInputCsr);
     if (rc != CC_OK) return rc;
     if (st) {
         std::memset(st, 0, sizeof *st);
-        st->hook = CC_HOOK_ATOMIC;
-        st->segments = p.segments;
+        st->hook = p.hook;
+        st->segments = p.hook == CC_HOOK_ATOMIC ? p.segments : 0;
         st->giant_label = -1;
     }
     if (n == 0) {
@@ -934,10 +951,18 @@ int32_t csr_impl(int32_t n, const int64_t* row_ptr, const int32_t* col, int64_t 
     int hooks = 0, jumps = 0;
     TIMED(kPhaseOther, launch_init(out, n, ctrl, s));
     TIMED(kPhaseOther, launch_csr_check(row_ptr, n, m, ctrl, s));
-    if (!filter) {
+    if (p.hook == CC_HOOK_HYBRID) {
+        TIMED(kPhaseHook, launch_ahook_csr(row_ptr, col, n, 0, m, out, ctrl, nullptr, p.symmetric,
+                                           false, /*plain=*/true, s));
+        TIMED(kPhaseCompress, launch_mj(out, n, nullptr, false, s));
+        TIMED(kPhaseHook, launch_ahook_csr(row_ptr, col, n, 0, m, out, ctrl, nullptr, p.symmetric,
+                                           p.halve, false, s));
+        TIMED(kPhaseCompress, launch_mj(out, n, nullptr, false, s));
+        hooks = jumps = 2;
+    } else if (!filter) {
         for (int i = 0; i < S; ++i) {
             TIMED(kPhaseHook, launch_ahook_csr(row_ptr, col, n, bound(i), bound(i + 1), out, ctrl,
-                                               nullptr, p.symmetric, p.halve, s));
+                                               nullptr, p.symmetric, p.halve, false, s));
             TIMED(kPhaseCompress, launch_mj(out, n, nullptr, false, s));
             ++hooks;
             ++jumps;
@@ -946,7 +971,7 @@ int32_t csr_impl(int32_t n, const int64_t* row_ptr, const int32_t* col, int64_t 
         const int fa = p.filter_after;
         for (int i = 0; i < fa; ++i) {
             TIMED(kPhaseHook, launch_ahook_csr(row_ptr, col, n, bound(i), bound(i + 1), out, ctrl,
-                                               nullptr, p.symmetric, p.halve, s));
+                                               nullptr, p.symmetric, p.halve, false, s));
             TIMED(kPhaseCompress, launch_mj(out, n, nullptr, false, s));
             ++hooks;
             ++jumps;
@@ -958,7 +983,7 @@ int32_t csr_impl(int32_t n, const int64_t* row_ptr, const int32_t* col, int64_t 
         while (g < S) {
             const int64_t h = std::min<int64_t>(S, g + step);
             TIMED(kPhaseHook, launch_ahook_csr(row_ptr, col, n, bound(g), bound(h), out, ctrl, bits,
-                                               p.symmetric, p.halve, s));
+                                               p.symmetric, p.halve, false, s));
             TIMED(kPhaseCompress, launch_mj(out, n, nullptr, false, s));
             ++hooks;
             ++jumps;
@@ -1074,7 +1099,7 @@ int32_t list_impl(int32_t count, const cc_graph* graphs, const cc_options* opts,
     off += order_bytes;
     for (int32_t i = 0; i < nl; ++i) {
         const cc_graph& G = graphs[large[i]];
-        int32_t rc = make_plan(G.n, G.m, nullptr, plans[i], /*allow_plain=*/false);
+        int32_t rc = make_plan(G.n, G.m, nullptr, plans[i], kInputAtomicOnly);
         if (rc != CC_OK) return rc;
         layouts[i] = layout(G.n, G.m, plans[i]);  // its control block is ctrls[1 + i] instead
         region_off[i] = off;

@@ -82,10 +82,11 @@ hipError_t launch_ahook_hot(const int32_t* u, const int32_t* v, int64_t begin, i
 
 // CSR adjacency (kernels_csr.hip): Atomic-Hook of entries [begin, end) of
 // col[], the first endpoint of entry i being its row; `bits` non-null applies
-// the giant filter; `sym` hooks only col < row.
+// the giant filter; `sym` hooks only col > row; `plain` runs the atomic-free
+// Hook (Fig. 2) instead (no filter, no halving).
 hipError_t launch_ahook_csr(const int64_t* row_ptr, const int32_t* col, int32_t n, int64_t begin,
                             int64_t end, int32_t* pi, Ctrl* ctrl, const uint32_t* bits, bool sym,
-                            bool halve, hipStream_t s);
+                            bool halve, bool plain, hipStream_t s);
 // Sets the range bit unless row_ptr[0] == 0, row_ptr[n] == m and row_ptr is
 // non-decreasing.
 hipError_t launch_csr_check(const int64_t* row_ptr, int32_t n, int64_t m, Ctrl* ctrl,

@@ -24,6 +24,13 @@
 // forms before the filter samples for it.  Keeping col < row instead hooks
 // only pairs inside the row prefix seen so far, and the filter finds no
 // giant until late.
+//
+// PLAIN: the atomic-free Hook (Fig. 2) instead of the CAS climb: where an
+// entry's two parents differ, the larger is pointed at the smaller with a
+// plain store.  Stores may overwrite each other, so this pass alone does not
+// finish the solve: it is the first pass of the hybrid plan, whose closing
+// Atomic-Hook pass over all entries restores every link lost here.  The
+// kernel then has no CAS, so its stores may use workgroup scope.
 #include "kernels.hpp"
 
 namespace hookcc {
@@ -70,7 +77,7 @@ __device__ __forceinline__ int64_t upper_row(const int64_t* __restrict__ rp, int
     return lo;
 }
 
-template <int EPT>
+template <int EPT, bool PLAIN>
 __global__ __launch_bounds__(512) void k_ahook_csr(const int64_t* __restrict__ row_ptr,
                                                    const int32_t* __restrict__ col, int32_t n,
                                                    int64_t begin, int64_t end, int32_t* pi,
@@ -94,7 +101,7 @@ __global__ __launch_bounds__(512) void k_ahook_csr(const int64_t* __restrict__ r
     if (in_lds)
         for (int64_t r = r_lo + threadIdx.x; r <= r_hi + 1; r += blockDim.x) win[r - r_lo] = row_ptr[r];
     __syncthreads();
-    const bool use_filter = filter && ctrl->filter_on;
+    const bool use_filter = !PLAIN && filter && ctrl->filter_on;
     const int32_t g = use_filter ? ctrl->giant : 0;
     bool bad = false;
 #pragma unroll
@@ -166,6 +173,14 @@ __global__ __launch_bounds__(512) void k_ahook_csr(const int64_t* __restrict__ r
             pa[j] = na ? xa : g;
             pb[j] = nb ? xb : g;
         }
+        if (PLAIN) {
+#pragma unroll
+            for (int j = 0; j < 4; ++j) {
+                if ((act >> j & 1) && pa[j] != pb[j])
+                    st_rlx(pi + (pa[j] > pb[j] ? pa[j] : pb[j]), pa[j] > pb[j] ? pb[j] : pa[j]);
+            }
+            continue;
+        }
 #pragma unroll
         for (int j = 0; j < 4; ++j) {
             if (!(act >> j & 1)) continue;
@@ -213,7 +228,7 @@ hipError_t launch_csr_check(const int64_t* row_ptr, int32_t n, int64_t m, Ctrl* 
 
 hipError_t launch_ahook_csr(const int64_t* row_ptr, const int32_t* col, int32_t n, int64_t begin,
                             int64_t end, int32_t* pi, Ctrl* ctrl, const uint32_t* bits, bool sym,
-                            bool halve, hipStream_t s) {
+                            bool halve, bool plain, hipStream_t s) {
     if (end <= begin || n <= 0) return hipSuccess;
     // 512 threads x 8 entries per tile: measured on R-MAT 24 (2^29 entries)
     // 4.97 ms against 5.86 (256 x 8), 5.49 (256 x 16), 5.13 (1024 x 8)
@@ -222,8 +237,12 @@ hipError_t launch_ahook_csr(const int64_t* row_ptr, const int32_t* col, int32_t 
     const int64_t tile = kBlock * EPT;
     const int64_t grid64 = (end - begin + tile - 1) / tile;
     if (grid64 > 0x7fffffff) return hipErrorInvalidValue;
-    k_ahook_csr<EPT><<<(int)grid64, kBlock, 0, s>>>(row_ptr, col, n, begin, end, pi, ctrl, bits,
-                                                 bits != nullptr, sym, halve);
+    if (plain)
+        k_ahook_csr<EPT, true><<<(int)grid64, kBlock, 0, s>>>(row_ptr, col, n, begin, end, pi, ctrl,
+                                                           nullptr, false, sym, false);
+    else
+        k_ahook_csr<EPT, false><<<(int)grid64, kBlock, 0, s>>>(row_ptr, col, n, begin, end, pi, ctrl,
+                                                            bits, bits != nullptr, sym, halve);
     return hipGetLastError();
 }
 

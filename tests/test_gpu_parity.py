@@ -374,11 +374,12 @@ def test_repeated_solves_on_deep_trees_stay_exact(dev):
     rp = torch.zeros(n + 1, dtype=torch.int64, device=dev)
     rp[1:] = torch.cumsum(torch.bincount(du, minlength=n), 0)
     del order
-    bad = 0
-    for _ in range(reps):
-        cc.labels_csr(rp, col, n, out=out)
-        bad += not torch.equal(out, want)
-    assert bad == 0, ("csr", bad, reps)
+    for opt in ("auto", "atomic", "hybrid"):
+        bad = 0
+        for _ in range(reps):
+            cc.labels_csr(rp, col, n, out=out, options=cc.Options(hook=opt))
+            bad += not torch.equal(out, want)
+        assert bad == 0, ("csr", opt, bad, reps)
 
 
 def test_full_size_batch_matches_oracle_digest(dev):
@@ -474,22 +475,25 @@ def test_csr_input_matches_oracle(dev):
         drp = torch.from_numpy(rp).to(dev)
         dcol = to_dev(col, dev)
         for opt in (cc.Options(), cc.Options(filter="giant", segments=8),
-                    cc.Options(filter="off", segments=3, path_halving="off")):
-            say("csr", name, opt.filter, opt.segments)
+                    cc.Options(filter="off", segments=3, path_halving="off"),
+                    cc.Options(hook="hybrid"), cc.Options(hook="hybrid", path_halving="off")):
+            say("csr", name, opt.hook, opt.filter, opt.segments)
             got = cc.labels_csr(drp, dcol, n, options=opt).cpu().numpy()
             assert np.array_equal(got, want), (name, opt)
         if name == "rmat_sym":
             for opt in (cc.Options(symmetric=True),
-                        cc.Options(symmetric=True, filter="giant", segments=8)):
+                        cc.Options(symmetric=True, filter="giant", segments=8),
+                        cc.Options(symmetric=True, hook="hybrid")):
                 got = cc.labels_csr(drp, dcol, n, options=opt).cpu().numpy()
                 assert np.array_equal(got, want)
             # the flag hooks exactly the entries with col > row: an adjacency
             # holding only those gives the same labels
             keep = v > u
             rp2, col2 = _to_csr(u[keep], v[keep], n)
-            got = cc.labels_csr(torch.from_numpy(rp2).to(dev), to_dev(col2, dev), n,
-                                options=cc.Options(symmetric=True)).cpu().numpy()
-            assert np.array_equal(got, want)
+            for opt in (cc.Options(symmetric=True), cc.Options(symmetric=True, hook="hybrid")):
+                got = cc.labels_csr(torch.from_numpy(rp2).to(dev), to_dev(col2, dev), n,
+                                    options=opt).cpu().numpy()
+                assert np.array_equal(got, want)
 
 
 def test_csr_rejects_malformed_input(dev):
@@ -516,7 +520,7 @@ def test_csr_full_size_rmat24(dev):
     rp = torch.zeros(n + 1, dtype=torch.int64, device=dev)
     rp[1:] = torch.cumsum(counts, 0)
     del du, dv, order
-    for opt in (cc.Options(), cc.Options(symmetric=True)):
+    for opt in (cc.Options(), cc.Options(symmetric=True), cc.Options(hook="hybrid")):
         lab = cc.labels_csr(rp, col, n, options=opt).cpu().numpy()
         assert digest(lab) == rec["sha256"]
 

@@ -54,7 +54,7 @@ def main():
     ap.add_argument("--block", type=int, default=0)
     ap.add_argument("--profile-steps", type=int, default=3)
     ap.add_argument("--coherent", action="store_true", help="agent-scope tree loads (A/B only)")
-    ap.add_argument("--hot", default="auto", choices=["auto", "on", "off", "large"])
+    ap.add_argument("--hot", default="auto", choices=["auto", "on", "off", "large", "vertex"])
     ap.add_argument("--symmetric", action="store_true",
                     help="flagged option: hook only u <= v of a symmetrised list (not the headline)")
     ap.add_argument("--skip-cpu", action="store_true")
@@ -149,7 +149,7 @@ def main():
     traffic = None
     if st.get("hook") == 1:
         alg_bytes = 8.0 * m  # each int32 (u, v) entry read once across the Atomic-Hook launches
-        kernel = "k_ahook + k_ahook_hot (all Atomic-Hook launches of one solve)"
+        kernel = "k_ahook + k_ahook_hotv (all Atomic-Hook launches of one solve)"
         if args.hook == "auto" and args.filter == "auto" and args.hot == "auto" and not (
                 args.segments or args.ept or args.block or args.coherent or args.symmetric):
             traffic = measured_traffic(args.workload, "atomic")
@@ -235,7 +235,8 @@ ABLATION = [
     ("atomic_s1_halving", dict(hook="atomic", segments=1, filter="off")),
     ("adaptive_giant_filter", dict(hook="atomic", filter="giant", path_halving="off",
                                    hot_cache="off")),
-    ("giant_filter_hot_halving", dict(hook="atomic", filter="giant")),
+    ("giant_filter_hotword_halving", dict(hook="atomic", filter="giant", hot_cache="large")),
+    ("giant_filter_hotvertex_halving", dict(hook="atomic", filter="giant")),
     ("plain_device_convergence", dict(hook="plain")),
     ("plain_tau500", dict(hook="plain", compact_threshold=500)),
     ("plain_tau100", dict(hook="plain", compact_threshold=100)),

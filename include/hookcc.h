@@ -113,11 +113,14 @@ typedef struct cc_options {
                                  L2); 0 (default) = cached loads, which may return an
                                  older ancestor -- always a valid one (kept for
                                  measurement; results are identical)                   */
-    int32_t hot_cache;        /* giant filter only: CC_HOT_AUTO (default, = CC_HOT_LARGE),
-                                 CC_HOT_ON (16,384 LDS slots), CC_HOT_LARGE (32,768 slots,
-                                 all 160 KiB of LDS) or CC_HOT_OFF -- keep the bitmap words
-                                 that sampled endpoints hit most often in LDS and answer
-                                 those bit tests there                                   */
+    int32_t hot_cache;        /* giant filter only: answer the bit tests of the endpoints
+                                 that a sample of the entries hits most often from a table
+                                 in LDS.  CC_HOT_VERTEX: 131,072 one-byte vertex slots
+                                 (128 KiB; slot t holds the most sampled vertex
+                                 k * 131072 + t, k < 127, with its bit); CC_HOT_LARGE:
+                                 32,768 bitmap-word slots (160 KiB); CC_HOT_ON: 16,384
+                                 word slots; CC_HOT_OFF: none.  CC_HOT_AUTO (default):
+                                 CC_HOT_VERTEX for n <= 2^24, else CC_HOT_LARGE         */
     int32_t path_halving;     /* Atomic-Hook climb: CC_HALVE_AUTO (default, on), CC_HALVE_ON
                                  or CC_HALVE_OFF (Fig. 3 exactly) -- re-point a non-root
                                  passed on the way up at its grandparent, on every 4th
@@ -159,6 +162,7 @@ typedef struct cc_options {
 #define CC_HOT_ON 1
 #define CC_HOT_OFF 2
 #define CC_HOT_LARGE 3
+#define CC_HOT_VERTEX 4
 
 #define CC_HALVE_AUTO 0
 #define CC_HALVE_ON 1

@@ -125,7 +125,7 @@ class Options:
         o.profile = 1 if self.profile else 0
         o.host_loop = _HOST_LOOPS[self.host_loop]
         o.coherent_loads = 1 if self.coherent_loads else 0
-        o.hot_cache = {"auto": 0, "on": 1, "off": 2, "large": 3}[self.hot_cache]
+        o.hot_cache = {"auto": 0, "on": 1, "off": 2, "large": 3, "vertex": 4}[self.hot_cache]
         o.path_halving = {"auto": 0, "on": 1, "off": 2}[self.path_halving]
         o.symmetric = 1 if self.symmetric else 0
         o.graph = 1 if self.graph else 0

@@ -31,9 +31,11 @@ hipError_t launch_sample_giant(const int32_t* u, int64_t m, const int32_t* pi, i
 // unless ctrl->filter_on.
 hipError_t launch_bitmap(const int32_t* pi, int32_t n, Ctrl* ctrl, uint32_t* bits, hipStream_t s);
 // Multi-Jump, then (when ctrl->filter_on) the giant bitmap and, when hot_tags
-// is non-null, the cached words of the hot-word table, in one pass.
+// is non-null, the cached words of the hot-word table, or when vtab is
+// non-null, the bits of the vertex table, in one pass.
 hipError_t launch_mj_bitmap(int32_t* pi, int32_t n, Ctrl* ctrl, uint32_t* bits,
-                            const uint32_t* hot_tags, uint32_t* hot_vals, int slots, hipStream_t s);
+                            const uint32_t* hot_tags, uint32_t* hot_vals, int slots, uint8_t* vtab,
+                            hipStream_t s);
 
 // Atomic-free Hook (Fig. 2) of round `round` (1-based).  Round 1 reads the
 // input entries [0, m) and checks ranges; later rounds read the frontier of
@@ -66,6 +68,30 @@ hipError_t launch_jump(int32_t* pi, int32_t n, Ctrl* ctrl, hipStream_t s);
 // direct-mapped slots (16384 or 32768); tags[t] = k means slot t caches bitmap
 // word k * slots + t.  Global tag/value arrays hold kHotSlotsMax words.
 constexpr int kHotSlotsMax = 32768;
+// Vertex table: kVertSlots one-byte slots; slot t holds (k << 1) | bit of the
+// vertex k * kVertSlots + t, k < kVertTagNone (k == kVertTagNone: empty).
+constexpr int kVertSlots = 1 << 17;
+constexpr uint32_t kVertTagNone = 127;
+// Selection sample: up to kVertRuns runs of 64 entries, kVRunsPerPart runs per
+// workgroup part; slots grouped in kVBuckets buckets of kVBucketSlots.
+constexpr int64_t kVertRuns = int64_t(1) << 15;
+constexpr int kVRunsPerPart = 128;
+constexpr int kVPartsMax = (int)(kVertRuns / kVRunsPerPart);
+constexpr int kVPartCap = kVRunsPerPart * 64 * 2;  // endpoints of one part
+constexpr int kVBucketSlots = 256;
+constexpr int kVBuckets = kVertSlots / kVBucketSlots;
+// Scratch words used by launch_hot_vprepare.
+constexpr int64_t kVertScratchWords = (int64_t)kVPartsMax * kVPartCap + 2LL * kVPartsMax * kVBuckets;
+// For every slot, the most sampled vertex (scratch: kVertScratchWords words);
+// bits are filled by launch_hot_vvalues.
+hipError_t launch_hot_vprepare(const int32_t* u, const int32_t* v, int64_t m, int32_t n,
+                               uint32_t* scratch, uint8_t* table, hipStream_t s);
+// Every slot's bit from the bitmap; no-op unless ctrl->filter_on.
+hipError_t launch_hot_vvalues(const uint32_t* bits, uint8_t* table, const Ctrl* ctrl, hipStream_t s);
+// Filtered Atomic-Hook of entries [begin, end) with the vertex table in LDS.
+hipError_t launch_ahook_hotv(const int32_t* u, const int32_t* v, int64_t begin, int64_t end,
+                             int32_t* pi, int32_t n, Ctrl* ctrl, const uint32_t* bits,
+                             const uint8_t* table, bool halve, bool sym, hipStream_t s);
 // Counts sampled endpoints per bitmap word (counts: ceil(n/32) words of
 // scratch) and picks the hottest word for every slot.
 hipError_t launch_hot_prepare(const int32_t* u, const int32_t* v, int64_t m, int32_t n,

@@ -426,7 +426,8 @@ template <bool VEC>
 __global__ __launch_bounds__(256) void k_mj_bitmap(int32_t* pi, int32_t n, Ctrl* ctrl,
                                                    uint32_t* __restrict__ bits,
                                                    const uint32_t* __restrict__ hot_tags,
-                                                   uint32_t* __restrict__ hot_vals, int slots) {
+                                                   uint32_t* __restrict__ hot_vals, int slots,
+                                                   uint8_t* vtab) {
     const int64_t base = ((int64_t)blockIdx.x * blockDim.x + threadIdx.x) * 4;
     int32_t p[4];
     if (VEC && base + 3 < n) {
@@ -461,6 +462,17 @@ __global__ __launch_bounds__(256) void k_mj_bitmap(int32_t* pi, int32_t n, Ctrl*
     uint64_t m4[4];
 #pragma unroll
     for (int j = 0; j < 4; ++j) m4[j] = __ballot(base + j < n && p[j] == groot);
+    if (vtab && base < n && base / kVertSlots < kVertTagNone) {
+        // the four slots of base .. base + 3 (same tag: kVertSlots is a
+        // multiple of 4); a slot is rewritten only by the vertex it holds
+        const uint32_t k = (uint32_t)(base / kVertSlots);
+        const uint32_t t0 = (uint32_t)(base & (kVertSlots - 1));
+        const uint32_t w = *reinterpret_cast<const uint32_t*>(vtab + t0);
+#pragma unroll
+        for (int j = 0; j < 4; ++j)
+            if (base + j < n && (w >> (8 * j + 1) & 0x7fu) == k)
+                vtab[t0 + j] = (uint8_t)((k << 1) | (p[j] == groot ? 1u : 0u));
+    }
     if (lane < 8) {
         const int64_t wave_base = base - 4 * lane;  // vertex of lane 0
         const int64_t w = wave_base / 32 + lane;
@@ -479,15 +491,16 @@ __global__ __launch_bounds__(256) void k_mj_bitmap(int32_t* pi, int32_t n, Ctrl*
 }
 
 hipError_t launch_mj_bitmap(int32_t* pi, int32_t n, Ctrl* ctrl, uint32_t* bits,
-                            const uint32_t* hot_tags, uint32_t* hot_vals, int slots, hipStream_t s) {
+                            const uint32_t* hot_tags, uint32_t* hot_vals, int slots, uint8_t* vtab,
+                            hipStream_t s) {
     if (n <= 0) return hipSuccess;
     if (hot_tags && slots != 16384 && slots != 32768) return hipErrorInvalidValue;
     const int64_t groups = ((int64_t)n + 3) / 4;
     const int grid = (int)((groups + 255) / 256);
     if (((uintptr_t)pi & 15) == 0)
-        k_mj_bitmap<true><<<grid, 256, 0, s>>>(pi, n, ctrl, bits, hot_tags, hot_vals, slots);
+        k_mj_bitmap<true><<<grid, 256, 0, s>>>(pi, n, ctrl, bits, hot_tags, hot_vals, slots, vtab);
     else
-        k_mj_bitmap<false><<<grid, 256, 0, s>>>(pi, n, ctrl, bits, hot_tags, hot_vals, slots);
+        k_mj_bitmap<false><<<grid, 256, 0, s>>>(pi, n, ctrl, bits, hot_tags, hot_vals, slots, vtab);
     return hipGetLastError();
 }
 

@@ -144,8 +144,16 @@ def test_workspace_sizes(lib):
     assert base == 256
     giant = cc.workspace_bytes(n, m, cc.Options(filter="giant", hot_cache="off"))
     assert giant == 256 + (n // 32) * 4
-    hot = cc.workspace_bytes(n, m, cc.Options(filter="giant"))
+    hot = cc.workspace_bytes(n, m, cc.Options(filter="giant", hot_cache="large"))
     assert hot == 256 + 2 * (n // 32) * 4 + 2 * 32768 * 4
+    # vertex table: 256 parts x 16,384 sampled endpoints, two 256 x 512
+    # count/offset tables, 131,072 one-byte slots
+    vert = cc.workspace_bytes(n, m, cc.Options(filter="giant"))
+    assert vert == 256 + (n // 32) * 4 + (256 * 16384 + 2 * 256 * 512) * 4 + 131072
+    assert cc.workspace_bytes(n, m, cc.Options(filter="giant", hot_cache="vertex")) == vert
+    big = 1 << 25  # above 2^24 vertices the automatic choice is the word table
+    assert cc.workspace_bytes(big, m, cc.Options(filter="giant")) == \
+        cc.workspace_bytes(big, m, cc.Options(filter="giant", hot_cache="large"))
     plain = cc.workspace_bytes(n, m, cc.Options(hook="plain"))
     assert plain == 256 + 2 * m * 8
     hybrid = cc.workspace_bytes(n, m, cc.Options(hook="hybrid"))

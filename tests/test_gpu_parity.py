@@ -45,6 +45,11 @@ VARIANTS = {
                                     edges_per_thread=4),
     "s12_giant_hotlarge_e16": cc.Options(hook="atomic", segments=12, filter="giant",
                                          hot_cache="large", edges_per_thread=16),
+    "s10_giant_hotvertex": cc.Options(hook="atomic", segments=10, filter="giant",
+                                      hot_cache="vertex"),
+    "s6_giant_hotvertex_nohalve_after2": cc.Options(hook="atomic", segments=6, filter="giant",
+                                                    filter_after=2, hot_cache="vertex",
+                                                    path_halving="off"),
     "plain_b128_e16_k1": cc.Options(hook="plain", edges_per_thread=16, block=128,
                                     rounds_per_check=1),
     "plain_e4_k7": cc.Options(hook="plain", edges_per_thread=4, rounds_per_check=7),
@@ -336,7 +341,7 @@ def test_full_size_workloads_match_oracle_digest(dev, name):
     du, dv = to_dev(u, dev), to_dev(v, dev)
     del u, v
     for opt in ("default", "plain", "atomic", "s1", "coherent_giant", "s6_giant_nohot_e4",
-                "s12_giant_hotlarge_e16", "s8_giant_nohalve", "hybrid"):
+                "s12_giant_hotlarge_e16", "s10_giant_hotvertex", "s8_giant_nohalve", "hybrid"):
         if name == "rmat24" and opt == "s1":
             opt = "s9_giant_after3"
         say("full size", name, opt)
@@ -360,7 +365,8 @@ def test_repeated_solves_on_deep_trees_stay_exact(dev):
     del u, v, want_np
     out = torch.empty(n, dtype=torch.int32, device=dev)
     reps = 12
-    for opt in ("default", "s1", "s12_giant_hotlarge_e16", "s5_giant_b1024_e16", "coherent_s3",
+    for opt in ("default", "s1", "s12_giant_hotlarge_e16", "s10_giant_hotvertex",
+                "s5_giant_b1024_e16", "coherent_s3",
                 "hybrid"):
         say("repeated solves grid4k", opt, reps)
         bad = 0

@@ -102,11 +102,11 @@ int32_t make_plan(int32_t n, int64_t m, const cc_options* o, Plan& p,
     p.symmetric = op.symmetric == 1;
     if (op.hot_cache < CC_HOT_AUTO || op.hot_cache > CC_HOT_VERTEX)
         return fail(CC_ERR_ARG, "unknown cc_options.hot_cache");
-    // Hot cache: the vertex table where it can hold every id below 127 * 2^17
-    // but the last 1/128 of them (n <= 2^24; R-MAT 24: 3.96 ms against 4.52
-    // with 32,768 word slots), else the word table.
+    // Hot cache: the vertex table where every id fits its tags (n <= 127 *
+    // 163,840; R-MAT 24: 3.96 ms against 4.52 with 32,768 word slots), else
+    // the word table.
     const bool vert = op.hot_cache == CC_HOT_VERTEX ||
-                      (op.hot_cache == CC_HOT_AUTO && n <= (int64_t(1) << 24));
+                      (op.hot_cache == CC_HOT_AUTO && n <= (int64_t)kVertTagNone * kVertSlots);
     p.hot_slots = op.hot_cache == CC_HOT_ON ? 16384 : vert ? kVertSlots : 32768;
     if (op.path_halving < CC_HALVE_AUTO || op.path_halving > CC_HALVE_OFF)
         return fail(CC_ERR_ARG, "unknown cc_options.path_halving");

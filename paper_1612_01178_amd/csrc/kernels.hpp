@@ -70,7 +70,7 @@ hipError_t launch_jump(int32_t* pi, int32_t n, Ctrl* ctrl, hipStream_t s);
 constexpr int kHotSlotsMax = 32768;
 // Vertex table: kVertSlots one-byte slots; slot t holds (k << 1) | bit of the
 // vertex k * kVertSlots + t, k < kVertTagNone (k == kVertTagNone: empty).
-constexpr int kVertSlots = 1 << 17;
+constexpr int kVertSlots = 5 << 15;  // 163,840 slots = all 160 KiB of LDS
 constexpr uint32_t kVertTagNone = 127;
 // Selection sample: up to kVertRuns runs of 64 entries, kVRunsPerPart runs per
 // workgroup part; slots grouped in kVBuckets buckets of kVBucketSlots.

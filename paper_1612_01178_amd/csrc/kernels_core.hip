@@ -465,8 +465,8 @@ __global__ __launch_bounds__(256) void k_mj_bitmap(int32_t* pi, int32_t n, Ctrl*
     if (vtab && base < n && base / kVertSlots < kVertTagNone) {
         // the four slots of base .. base + 3 (same tag: kVertSlots is a
         // multiple of 4); a slot is rewritten only by the vertex it holds
-        const uint32_t k = (uint32_t)(base / kVertSlots);
-        const uint32_t t0 = (uint32_t)(base & (kVertSlots - 1));
+        const uint32_t k = (uint32_t)base / kVertSlots;
+        const uint32_t t0 = (uint32_t)base % kVertSlots;
         const uint32_t w = *reinterpret_cast<const uint32_t*>(vtab + t0);
 #pragma unroll
         for (int j = 0; j < 4; ++j)

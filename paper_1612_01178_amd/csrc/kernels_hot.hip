@@ -18,12 +18,12 @@
 // so a cached answer is exactly the bitmap's answer; the filter's exactness
 // argument is unchanged.
 //
-// Vertex table (kVertSlots one-byte slots, 128 KiB of LDS): a hot vertex
+// Vertex table (kVertSlots one-byte slots, all 160 KiB of LDS): a hot vertex
 // shares its bitmap word with 31 mostly cold ones, so word slots spend most
 // of their bits on vertices that are rarely tested.  Slot t caches one vertex
-// v = k * kVertSlots + t as the byte (k << 1) | bit(v): four times the hot
-// vertices in less LDS (R-MAT 24: about 48 % of the bit tests answered in LDS
-// against 35 % for 32,768 word slots).  Chosen from sampled endpoints
+// v = k * kVertSlots + t as the byte (k << 1) | bit(v): five times the hot
+// vertices of the word table in the same LDS (R-MAT 24: about half of the
+// bit tests answered in LDS, against 35 % for 32,768 word slots).  Chosen from sampled endpoints
 // (k_vsample, k_vselect); the fused Multi-Jump/bitmap pass refreshes the
 // bits with byte stores, each slot written only by its own vertex.
 #include "kernels.hpp"
@@ -103,12 +103,12 @@ __device__ __forceinline__ bool vcandidate(uint32_t x, int32_t n) {
 }
 
 __device__ __forceinline__ uint32_t vbucket(uint32_t x) {
-    return (x & (kVertSlots - 1)) / kVBucketSlots;
+    return (x % kVertSlots) / kVBucketSlots;
 }
 
-// Exclusive scan of two values per thread over a 256-thread workgroup;
+// Exclusive scan of one value per thread over a 256-thread workgroup;
 // returns this thread's base (the sum of the values of lower threads).
-__device__ __forceinline__ uint32_t block_scan_pairs(uint32_t pair, uint32_t* wsum) {
+__device__ __forceinline__ uint32_t block_scan(uint32_t pair, uint32_t* wsum) {
     const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
     uint32_t incl = pair;
 #pragma unroll
@@ -131,14 +131,15 @@ __global__ __launch_bounds__(256) void k_vsample(const int32_t* __restrict__ eu,
                                                  uint32_t* __restrict__ region,
                                                  uint32_t* __restrict__ cnt,
                                                  uint32_t* __restrict__ off) {
-    __shared__ uint32_t hist[kVBuckets];
-    __shared__ uint32_t cur[kVBuckets];
+    constexpr int kPer = (kVBuckets + 255) / 256;  // buckets per thread in the scan
+    __shared__ uint32_t hist[256 * kPer];
+    __shared__ uint32_t cur[256 * kPer];
     __shared__ uint32_t wsum[4];
     __shared__ uint32_t stage[kVPartCap];  // the part, grouped by bucket
-    static_assert(kVBuckets == 2 * 256, "two buckets per thread");
     const int g = blockIdx.x;
     const int tid = threadIdx.x;
-    hist[2 * tid] = hist[2 * tid + 1] = 0;
+#pragma unroll
+    for (int q = 0; q < kPer; ++q) hist[kPer * tid + q] = 0;
     // this thread's samples, all loads issued before any is used
     const int64_t s0 = (int64_t)g * kVRunsPerPart * 64;
     const int64_t s1 = min(runs, (int64_t)(g + 1) * kVRunsPerPart) * 64;
@@ -157,14 +158,22 @@ __global__ __launch_bounds__(256) void k_vsample(const int32_t* __restrict__ eu,
         if (vcandidate(y[i], n)) atomicAdd(&hist[vbucket(y[i])], 1u);
     }
     __syncthreads();
-    const uint32_t a0 = hist[2 * tid], a1 = hist[2 * tid + 1];
-    const uint32_t ex = block_scan_pairs(a0 + a1, wsum);
-    cur[2 * tid] = ex;
-    cur[2 * tid + 1] = ex + a0;
-    cnt[(int64_t)g * kVBuckets + 2 * tid] = a0;
-    cnt[(int64_t)g * kVBuckets + 2 * tid + 1] = a1;
-    off[(int64_t)g * kVBuckets + 2 * tid] = ex;
-    off[(int64_t)g * kVBuckets + 2 * tid + 1] = ex + a0;
+    // exclusive scan: thread tid owns buckets kPer * tid .. kPer * tid + kPer - 1
+    uint32_t own = 0;
+#pragma unroll
+    for (int q = 0; q < kPer; ++q) own += hist[kPer * tid + q];
+    uint32_t at = block_scan(own, wsum);
+#pragma unroll
+    for (int q = 0; q < kPer; ++q) {
+        const int bk = kPer * tid + q;
+        const uint32_t h = hist[bk];
+        cur[bk] = at;
+        if (bk < kVBuckets) {
+            cnt[(int64_t)g * kVBuckets + bk] = h;
+            off[(int64_t)g * kVBuckets + bk] = at;
+        }
+        at += h;
+    }
     const uint32_t total = wsum[0] + wsum[1] + wsum[2] + wsum[3];
     __syncthreads();
 #pragma unroll
@@ -196,7 +205,7 @@ __global__ __launch_bounds__(256) void k_vselect(const uint32_t* __restrict__ re
     const uint32_t k = tid < parts ? cnt[(int64_t)tid * kVBuckets + b] : 0u;
     src0[tid] = tid < parts ? (uint32_t)(tid * kVPartCap) + off[(int64_t)tid * kVBuckets + b] : 0u;
     for (int i = tid; i < kVBucketSlots * kTags / 2; i += 256) c[i] = 0;
-    const uint32_t st = block_scan_pairs(k, wsum);  // one value per thread here
+    const uint32_t st = block_scan(k, wsum);  // one value per thread here
     start[tid] = st;
     if (tid == 255) start[256] = st + k;
     __syncthreads();
@@ -219,7 +228,7 @@ __global__ __launch_bounds__(256) void k_vselect(const uint32_t* __restrict__ re
 #pragma unroll
         for (int q = 0; q < kUnroll; ++q) {
             if (xs[q] == 0xffffffffu) continue;
-            const uint32_t i = (xs[q] % kVBucketSlots) * kTags + xs[q] / kVertSlots;
+            const uint32_t i = (xs[q] % kVertSlots % kVBucketSlots) * kTags + xs[q] / kVertSlots;
             atomicAdd(&c[i >> 1], 1u << (16 * (i & 1)));
         }
     }
@@ -427,8 +436,8 @@ __global__ __launch_bounds__(1024) void k_ahook_hotv(const int32_t* __restrict__
                 const uint32_t xa = (uint32_t)a[j], xb = (uint32_t)b[j];
                 // a tag of kVertTagNone or more never matches a stored byte's
                 // tag (stored tags are below it or mark an empty slot)
-                const uint32_t ca = lbyte[xa & (kVertSlots - 1)];
-                const uint32_t cb = lbyte[xb & (kVertSlots - 1)];
+                const uint32_t ca = lbyte[xa % kVertSlots];
+                const uint32_t cb = lbyte[xb % kVertSlots];
                 const bool hita = (ca >> 1) == xa / kVertSlots && xa / kVertSlots < kVertTagNone;
                 const bool hitb = (cb >> 1) == xb / kVertSlots && xb / kVertSlots < kVertTagNone;
                 uint32_t worda = ca, wordb = cb;

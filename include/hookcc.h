@@ -115,12 +115,13 @@ typedef struct cc_options {
                                  measurement; results are identical)                   */
     int32_t hot_cache;        /* giant filter only: answer the bit tests of the endpoints
                                  that a sample of the entries hits most often from a table
-                                 in LDS.  CC_HOT_VERTEX: 163,840 one-byte vertex slots
-                                 (160 KiB; slot t holds the most sampled vertex
-                                 k * 163840 + t, k < 127, with its bit); CC_HOT_LARGE:
+                                 in LDS.  CC_HOT_VERTEX: 81,920 two-way sets of one-byte
+                                 vertex tags (160 KiB; set s holds the two most sampled
+                                 vertices k * 81920 + s, k < 255, and answers for them
+                                 while they are in the giant component); CC_HOT_LARGE:
                                  32,768 bitmap-word slots (160 KiB); CC_HOT_ON: 16,384
                                  word slots; CC_HOT_OFF: none.  CC_HOT_AUTO (default):
-                                 CC_HOT_VERTEX for n <= 127 * 163840, else CC_HOT_LARGE  */
+                                 CC_HOT_VERTEX for n <= 255 * 81920, else CC_HOT_LARGE  */
     int32_t path_halving;     /* Atomic-Hook climb: CC_HALVE_AUTO (default, on), CC_HALVE_ON
                                  or CC_HALVE_OFF (Fig. 3 exactly) -- re-point a non-root
                                  passed on the way up at its grandparent, on every 4th

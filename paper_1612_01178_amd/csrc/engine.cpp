@@ -102,11 +102,11 @@ int32_t make_plan(int32_t n, int64_t m, const cc_options* o, Plan& p,
     p.symmetric = op.symmetric == 1;
     if (op.hot_cache < CC_HOT_AUTO || op.hot_cache > CC_HOT_VERTEX)
         return fail(CC_ERR_ARG, "unknown cc_options.hot_cache");
-    // Hot cache: the vertex table where every id fits its tags (n <= 127 *
-    // 163,840; R-MAT 24: 3.96 ms against 4.52 with 32,768 word slots), else
-    // the word table.
+    // Hot cache: the vertex table where every id fits its tags (n <= 255 *
+    // 81,920; R-MAT 24: 3.9 ms against 4.52 with 32,768 word slots), else the
+    // word table.
     const bool vert = op.hot_cache == CC_HOT_VERTEX ||
-                      (op.hot_cache == CC_HOT_AUTO && n <= (int64_t)kVertTagNone * kVertSlots);
+                      (op.hot_cache == CC_HOT_AUTO && n <= (int64_t)kVertTagNone * kVertSets);
     p.hot_slots = op.hot_cache == CC_HOT_ON ? 16384 : vert ? kVertSlots : 32768;
     if (op.path_halving < CC_HALVE_AUTO || op.path_halving > CC_HALVE_OFF)
         return fail(CC_ERR_ARG, "unknown cc_options.path_halving");
@@ -233,8 +233,8 @@ Layout layout(int32_t n, int64_t m, const Plan& p) {
         if (p.hot && p.hot_slots == kVertSlots) {  // selection scratch, byte table
             L.hot_counts = off;
             off += align256((size_t)kVertScratchWords * 4);
-            L.hot_tags = L.hot_vals = off;
-            off += align256((size_t)kVertSlots);
+            L.hot_tags = L.hot_vals = off;  // tags, then member flags
+            off += align256((size_t)kVertSlots * 2);
         } else if (p.hot) {
             L.hot_counts = off;
             off += align256(((size_t)n + 31) / 32 * 4);

@@ -68,25 +68,29 @@ hipError_t launch_jump(int32_t* pi, int32_t n, Ctrl* ctrl, hipStream_t s);
 // direct-mapped slots (16384 or 32768); tags[t] = k means slot t caches bitmap
 // word k * slots + t.  Global tag/value arrays hold kHotSlotsMax words.
 constexpr int kHotSlotsMax = 32768;
-// Vertex table: kVertSlots one-byte slots; slot t holds (k << 1) | bit of the
-// vertex k * kVertSlots + t, k < kVertTagNone (k == kVertTagNone: empty).
-constexpr int kVertSlots = 5 << 15;  // 163,840 slots = all 160 KiB of LDS
-constexpr uint32_t kVertTagNone = 127;
+// Vertex table: kVertSets sets of kVertWays one-byte slots; slot 2s + w holds
+// the tag k of the vertex k * kVertSets + s (k < kVertTagNone; kVertTagNone
+// marks an empty slot).  In device memory: the tags (kVertSlots bytes), then
+// one member flag per slot (kVertSlots bytes; 1 = in the giant component).
+constexpr int kVertSets = 5 << 14;  // 81,920
+constexpr int kVertWays = 2;
+constexpr int kVertSlots = kVertSets * kVertWays;  // 163,840 bytes = all 160 KiB of LDS
+constexpr uint32_t kVertTagNone = 255;
 // Selection sample: up to kVertRuns runs of 64 entries, kVRunsPerPart runs per
-// workgroup part; slots grouped in kVBuckets buckets of kVBucketSlots.
+// workgroup part; sets grouped in kVBuckets buckets of kVBucketSets.
 constexpr int64_t kVertRuns = int64_t(1) << 15;
 constexpr int kVRunsPerPart = 128;
 constexpr int kVPartsMax = (int)(kVertRuns / kVRunsPerPart);
 constexpr int kVPartCap = kVRunsPerPart * 64 * 2;  // endpoints of one part
-constexpr int kVBucketSlots = 256;
-constexpr int kVBuckets = kVertSlots / kVBucketSlots;
+constexpr int kVBucketSets = 128;
+constexpr int kVBuckets = kVertSets / kVBucketSets;
 // Scratch words used by launch_hot_vprepare.
 constexpr int64_t kVertScratchWords = (int64_t)kVPartsMax * kVPartCap + 2LL * kVPartsMax * kVBuckets;
-// For every slot, the most sampled vertex (scratch: kVertScratchWords words);
-// bits are filled by launch_hot_vvalues.
+// For every set, the kVertWays most sampled vertices (scratch:
+// kVertScratchWords words); member flags are filled by launch_hot_vvalues.
 hipError_t launch_hot_vprepare(const int32_t* u, const int32_t* v, int64_t m, int32_t n,
                                uint32_t* scratch, uint8_t* table, hipStream_t s);
-// Every slot's bit from the bitmap; no-op unless ctrl->filter_on.
+// Every slot's member flag from the bitmap; no-op unless ctrl->filter_on.
 hipError_t launch_hot_vvalues(const uint32_t* bits, uint8_t* table, const Ctrl* ctrl, hipStream_t s);
 // Filtered Atomic-Hook of entries [begin, end) with the vertex table in LDS.
 hipError_t launch_ahook_hotv(const int32_t* u, const int32_t* v, int64_t begin, int64_t end,

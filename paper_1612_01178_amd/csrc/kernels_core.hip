@@ -462,16 +462,20 @@ __global__ __launch_bounds__(256) void k_mj_bitmap(int32_t* pi, int32_t n, Ctrl*
     uint64_t m4[4];
 #pragma unroll
     for (int j = 0; j < 4; ++j) m4[j] = __ballot(base + j < n && p[j] == groot);
-    if (vtab && base < n && base / kVertSlots < kVertTagNone) {
-        // the four slots of base .. base + 3 (same tag: kVertSlots is a
-        // multiple of 4); a slot is rewritten only by the vertex it holds
-        const uint32_t k = (uint32_t)base / kVertSlots;
-        const uint32_t t0 = (uint32_t)base % kVertSlots;
-        const uint32_t w = *reinterpret_cast<const uint32_t*>(vtab + t0);
+    if (vtab && base < n && (uint32_t)base / kVertSets < kVertTagNone) {
+        // the sets of base .. base + 3 (same tag: kVertSets is a multiple of
+        // 4) and their 8 tag bytes; a member flag is written only by the
+        // vertex its slot holds
+        const uint32_t k = (uint32_t)base / kVertSets;
+        const uint32_t s0 = (uint32_t)base % kVertSets;
+        const uint64_t tags = *reinterpret_cast<const uint64_t*>(vtab + 2 * s0);
+        uint8_t* mem = vtab + kVertSlots + 2 * s0;
 #pragma unroll
         for (int j = 0; j < 4; ++j)
-            if (base + j < n && (w >> (8 * j + 1) & 0x7fu) == k)
-                vtab[t0 + j] = (uint8_t)((k << 1) | (p[j] == groot ? 1u : 0u));
+#pragma unroll
+            for (int w = 0; w < kVertWays; ++w)
+                if (base + j < n && (uint32_t)(tags >> (8 * (2 * j + w)) & 0xffu) == k)
+                    mem[2 * j + w] = p[j] == groot ? 1 : 0;
     }
     if (lane < 8) {
         const int64_t wave_base = base - 4 * lane;  // vertex of lane 0

@@ -18,14 +18,19 @@
 // so a cached answer is exactly the bitmap's answer; the filter's exactness
 // argument is unchanged.
 //
-// Vertex table (kVertSlots one-byte slots, all 160 KiB of LDS): a hot vertex
-// shares its bitmap word with 31 mostly cold ones, so word slots spend most
-// of their bits on vertices that are rarely tested.  Slot t caches one vertex
-// v = k * kVertSlots + t as the byte (k << 1) | bit(v): five times the hot
-// vertices of the word table in the same LDS (R-MAT 24: about half of the
-// bit tests answered in LDS, against 35 % for 32,768 word slots).  Chosen from sampled endpoints
-// (k_vsample, k_vselect); the fused Multi-Jump/bitmap pass refreshes the
-// bits with byte stores, each slot written only by its own vertex.
+// Vertex table (kVertSets two-way sets of one-byte slots, all 160 KiB of
+// LDS): a hot vertex shares its bitmap word with 31 mostly cold ones, so word
+// slots spend most of their bits on vertices that are rarely tested.  Set s
+// caches up to two vertices v = k * kVertSets + s by their tags k; the LDS
+// copy keeps a tag only while its vertex is in the giant component (else the
+// slot reads as empty), so a tag match answers the test with 1 and anything
+// else goes to the bitmap.  Membership only grows (trees only merge), and the
+// hot vertices of a graph with a giant component are nearly all in it.
+// Five times the hot vertices of the word table in the same LDS (R-MAT 24:
+// 56 % of the bit tests answered in LDS, against 35 % for 32,768 word slots).
+// Chosen from sampled endpoints (k_vsample, k_vselect); the fused
+// Multi-Jump/bitmap pass refreshes the member flags in device memory with
+// byte stores, each flag written only by its own vertex.
 #include "kernels.hpp"
 
 namespace hookcc {
@@ -82,15 +87,15 @@ __global__ __launch_bounds__(256) void k_hot_values(const uint32_t* __restrict__
 // per-vertex count array run at about 2 x 10^10/s here, 0.2 ms for 2^22
 // endpoints).  Sampled entries: up to kVertRuns runs of 64 consecutive
 // entries spread evenly over the list.  Endpoints x < n with tag
-// x / kVertSlots < kVertTagNone are candidates; bucket(x) is the range of
-// kVBucketSlots slots that holds slot x mod kVertSlots.
+// x / kVertSets < kVertTagNone are candidates; bucket(x) is the range of
+// kVBucketSets sets that holds set x mod kVertSets.
 //   k_vsample  workgroup g takes kVRunsPerPart runs, histograms its
 //              candidates by bucket in LDS, scans, and writes them grouped by
 //              bucket into its own part of `region`, with the per-bucket
 //              counts and offsets (cnt, off: [part][bucket]).
 //   k_vselect  workgroup b gathers bucket b from every part, counts every
-//              (slot, tag) pair in LDS, and gives each slot the tag with the
-//              largest count (ties -> smallest tag).
+//              (set, tag) pair in LDS, and gives each set the kVertWays tags
+//              with the largest counts (ties -> smaller tag).
 // Entry of sample s: lane s % 64 of run s / 64, which starts at about
 // (s / 64) * (m - 64) / runs (step = (m - 64) / runs; m >= 64).
 __device__ __forceinline__ int64_t vsample_entry(int64_t s, int64_t m, double step) {
@@ -99,11 +104,11 @@ __device__ __forceinline__ int64_t vsample_entry(int64_t s, int64_t m, double st
 }
 
 __device__ __forceinline__ bool vcandidate(uint32_t x, int32_t n) {
-    return x < (uint32_t)n && x / kVertSlots < kVertTagNone;
+    return x < (uint32_t)n && x / kVertSets < kVertTagNone;
 }
 
 __device__ __forceinline__ uint32_t vbucket(uint32_t x) {
-    return (x % kVertSlots) / kVBucketSlots;
+    return (x % kVertSets) / kVBucketSets;
 }
 
 // Exclusive scan of one value per thread over a 256-thread workgroup;
@@ -189,23 +194,23 @@ __global__ __launch_bounds__(256) void k_vsample(const int32_t* __restrict__ eu,
 __global__ __launch_bounds__(256) void k_vselect(const uint32_t* __restrict__ region,
                                                  const uint32_t* __restrict__ cnt,
                                                  const uint32_t* __restrict__ off, int parts,
-                                                 int32_t n, uint8_t* __restrict__ table) {
+                                                 int32_t n, uint8_t* __restrict__ tags) {
     constexpr int kTags = (int)kVertTagNone;  // candidate tags 0 .. kTags - 1
     // 16-bit counters, two per word (counter i in half i & 1 of word i / 2);
     // at most 65,535 endpoints of a bucket are counted, so none overflows
-    __shared__ uint32_t c[kVBucketSlots * kTags / 2];
+    __shared__ uint32_t c[kVBucketSets * kTags / 2 + 1];
     __shared__ uint32_t start[kVPartsMax + 1];  // first flat index of each part's piece
     __shared__ uint32_t src0[kVPartsMax];       // its offset in region
     __shared__ uint32_t wsum[4];
-    static_assert(kVBucketSlots == 256 && kVPartsMax == 256, "one slot and one part per thread");
+    static_assert(kVPartsMax == 256 && kVBucketSets <= 256, "one part per thread");
     const int b = blockIdx.x;
     const int tid = threadIdx.x;
     // the bucket's piece of every part, flattened: piece of part g holds the
     // flat indices [start[g], start[g + 1])
     const uint32_t k = tid < parts ? cnt[(int64_t)tid * kVBuckets + b] : 0u;
     src0[tid] = tid < parts ? (uint32_t)(tid * kVPartCap) + off[(int64_t)tid * kVBuckets + b] : 0u;
-    for (int i = tid; i < kVBucketSlots * kTags / 2; i += 256) c[i] = 0;
-    const uint32_t st = block_scan(k, wsum);  // one value per thread here
+    for (int i = tid; i < kVBucketSets * kTags / 2 + 1; i += 256) c[i] = 0;
+    const uint32_t st = block_scan(k, wsum);
     start[tid] = st;
     if (tid == 255) start[256] = st + k;
     __syncthreads();
@@ -228,34 +233,70 @@ __global__ __launch_bounds__(256) void k_vselect(const uint32_t* __restrict__ re
 #pragma unroll
         for (int q = 0; q < kUnroll; ++q) {
             if (xs[q] == 0xffffffffu) continue;
-            const uint32_t i = (xs[q] % kVertSlots % kVBucketSlots) * kTags + xs[q] / kVertSlots;
+            const uint32_t i = (xs[q] % kVertSets % kVBucketSets) * kTags + xs[q] / kVertSets;
             atomicAdd(&c[i >> 1], 1u << (16 * (i & 1)));
         }
     }
     __syncthreads();
-    const int64_t t = (int64_t)b * kVBucketSlots + tid;
-    uint32_t best_k = kVertTagNone, best_c = 0;
-    for (int q = 0; q < kTags && t + (int64_t)q * kVertSlots < n; ++q) {
-        const uint32_t i = tid * kTags + q;
+    // the two largest counts of set s (ties -> smaller tag); tags of vertices
+    // past n are not candidates.  Threads 2i and 2i + 1 scan the lower and
+    // upper half of set i's tags, then merge.
+    static_assert(2 * kVBucketSets == 256 && kVertWays == 2, "two threads per set, two ways");
+    const int set = tid >> 1, half = tid & 1;
+    const int64_t s = (int64_t)b * kVBucketSets + set;
+    const int64_t tags_n = (int64_t)n > s ? ((int64_t)n - s + kVertSets - 1) / kVertSets : 0;
+    const int q0 = half * ((kTags + 1) / 2);
+    const int q1 = (int)min<int64_t>(tags_n, half ? kTags : (kTags + 1) / 2);
+    uint32_t k1 = kVertTagNone, c1 = 0, k2 = kVertTagNone, c2 = 0;
+#pragma unroll 8
+    for (int q = q0; q < q1; ++q) {
+        const uint32_t i = set * kTags + q;
         const uint32_t cc = c[i >> 1] >> (16 * (i & 1)) & 0xffffu;
-        if (best_k == kVertTagNone || cc > best_c) {
-            best_k = (uint32_t)q;
-            best_c = cc;
+        if (k1 == kVertTagNone || cc > c1) {
+            k2 = k1;
+            c2 = c1;
+            k1 = (uint32_t)q;
+            c1 = cc;
+        } else if (k2 == kVertTagNone || cc > c2) {
+            k2 = (uint32_t)q;
+            c2 = cc;
         }
     }
-    table[t] = (uint8_t)(best_k << 1);
+    // merge with the other half (all of its tags are larger for half 0):
+    // the order is count descending, then tag ascending
+    const uint32_t o1 = __shfl_xor(k1, 1, 64), p1 = __shfl_xor(c1, 1, 64);
+    const uint32_t o2 = __shfl_xor(k2, 1, 64), p2 = __shfl_xor(c2, 1, 64);
+    auto before = [](uint32_t ka, uint32_t ca, uint32_t kb, uint32_t cb) {
+        return ka != kVertTagNone && (kb == kVertTagNone || ca > cb || (ca == cb && ka < kb));
+    };
+    uint32_t r1, r2;
+    if (before(k1, c1, o1, p1)) {
+        r1 = k1;
+        r2 = before(k2, c2, o1, p1) ? k2 : o1;
+    } else {
+        r1 = o1;
+        r2 = before(k1, c1, o2, p2) ? k1 : o2;
+    }
+    if (half == 0) {
+        tags[2 * s] = (uint8_t)r1;
+        tags[2 * s + 1] = (uint8_t)r2;
+    }
 }
 
-// Fills the bit of every slot from the bitmap; no-op unless ctrl->filter_on.
+// Member flag of every slot from the bitmap (0 for an empty slot); no-op
+// unless ctrl->filter_on.
 __global__ __launch_bounds__(256) void k_hot_vvalues(const uint32_t* __restrict__ bits,
-                                                     uint8_t* __restrict__ table, const Ctrl* ctrl) {
+                                                     uint8_t* __restrict__ vtab, const Ctrl* ctrl) {
     if (!ctrl->filter_on) return;
     const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (t >= kVertSlots) return;
-    const uint32_t k = table[t] >> 1;
-    if (k >= kVertTagNone) return;
-    const int64_t v = (int64_t)k * kVertSlots + t;
-    table[t] = (uint8_t)((k << 1) | (bits[v >> 5] >> (v & 31) & 1u));
+    const uint32_t k = vtab[t];
+    uint8_t f = 0;
+    if (k < kVertTagNone) {
+        const int64_t v = (int64_t)k * kVertSets + t / kVertWays;
+        f = (uint8_t)(bits[v >> 5] >> (v & 31) & 1u);
+    }
+    vtab[kVertSlots + t] = f;
 }
 
 template <int EPT>
@@ -392,9 +433,10 @@ hipError_t launch_hot_values(const uint32_t* bits, const uint32_t* tags, uint32_
     return hipGetLastError();
 }
 
-// Filtered Atomic-Hook with the vertex table in LDS (one byte per slot,
-// loaded once per workgroup).  A test of vertex x is answered in LDS when
-// slot x mod kVertSlots holds x (tag x / kVertSlots), else from the bitmap.
+// Filtered Atomic-Hook with the vertex table in LDS (loaded once per
+// workgroup, a slot's tag kept only while its member flag is set).  A test of
+// vertex x is answered with 1 in LDS when set x mod kVertSets holds the tag
+// x / kVertSets, else from the bitmap.
 template <int EPT>
 __global__ __launch_bounds__(1024) void k_ahook_hotv(const int32_t* __restrict__ eu,
                                                      const int32_t* __restrict__ ev, int64_t begin,
@@ -406,12 +448,23 @@ __global__ __launch_bounds__(1024) void k_ahook_hotv(const int32_t* __restrict__
     const bool filter = ctrl->filter_on != 0;
     const int32_t g = ctrl->giant;
     if (filter) {
-        const v4i* src = reinterpret_cast<const v4i*>(gtab);
+        // tag | 0xff per byte whose member flag (0 or 1) is 0: bytes of
+        // (0x01010101 - flags) are 1 - flag, times 0xff without carries
+        const v4i* tg = reinterpret_cast<const v4i*>(gtab);
+        const v4i* fl = reinterpret_cast<const v4i*>(gtab + kVertSlots);
         v4i* dst = reinterpret_cast<v4i*>(ltab);
-        for (uint32_t i = threadIdx.x; i < (uint32_t)(kVertSlots / 16); i += blockDim.x) dst[i] = src[i];
+        for (uint32_t i = threadIdx.x; i < (uint32_t)(kVertSlots / 16); i += blockDim.x) {
+            const v4i t = tg[i], f = fl[i];
+            v4i o;
+            o.x = (int32_t)((uint32_t)t.x | (0x01010101u - (uint32_t)f.x) * 0xffu);
+            o.y = (int32_t)((uint32_t)t.y | (0x01010101u - (uint32_t)f.y) * 0xffu);
+            o.z = (int32_t)((uint32_t)t.z | (0x01010101u - (uint32_t)f.z) * 0xffu);
+            o.w = (int32_t)((uint32_t)t.w | (0x01010101u - (uint32_t)f.w) * 0xffu);
+            dst[i] = o;
+        }
         __syncthreads();
     }
-    const uint8_t* lbyte = reinterpret_cast<const uint8_t*>(ltab);
+    const uint16_t* lset = reinterpret_cast<const uint16_t*>(ltab);
     const int64_t stride = (int64_t)blockDim.x * 4;
     const int64_t tile = (int64_t)blockDim.x * EPT;
     bool bad = false;
@@ -436,11 +489,12 @@ __global__ __launch_bounds__(1024) void k_ahook_hotv(const int32_t* __restrict__
                 const uint32_t xa = (uint32_t)a[j], xb = (uint32_t)b[j];
                 // a tag of kVertTagNone or more never matches a stored byte's
                 // tag (stored tags are below it or mark an empty slot)
-                const uint32_t ca = lbyte[xa % kVertSlots];
-                const uint32_t cb = lbyte[xb % kVertSlots];
-                const bool hita = (ca >> 1) == xa / kVertSlots && xa / kVertSlots < kVertTagNone;
-                const bool hitb = (cb >> 1) == xb / kVertSlots && xb / kVertSlots < kVertTagNone;
-                uint32_t worda = ca, wordb = cb;
+                // a tag of kVertTagNone (the empty marker) or more never hits
+                const uint32_t sa = lset[xa % kVertSets], sb = lset[xb % kVertSets];
+                const uint32_t ka = xa / kVertSets, kb = xb / kVertSets;
+                const bool hita = ka < kVertTagNone && ((sa & 0xffu) == ka || (sa >> 8) == ka);
+                const bool hitb = kb < kVertTagNone && ((sb & 0xffu) == kb || (sb >> 8) == kb);
+                uint32_t worda = 1, wordb = 1;
                 if (!hita) worda = __hip_atomic_load(bits + (xa >> 5), __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP) >> (xa & 31);
                 if (!hitb) wordb = __hip_atomic_load(bits + (xb >> 5), __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP) >> (xb & 31);
                 ba = worda & 1;
@@ -469,7 +523,7 @@ hipError_t launch_hot_vprepare(const int32_t* u, const int32_t* v, int64_t m, in
     const int parts = (int)((runs + kVRunsPerPart - 1) / kVRunsPerPart);
     const double step = runs > 0 ? (double)(m - 64) / (double)runs : 0.0;
     if (parts > 0) k_vsample<<<parts, 256, 0, s>>>(u, v, m, n, runs, step, region, cnt, off);
-    k_vselect<<<kVBuckets, 256, 0, s>>>(region, cnt, off, parts, n, table);
+    k_vselect<<<kVBuckets, 256, 0, s>>>(region, cnt, off, parts, n, table);  // tags
     return hipGetLastError();
 }
 

@@ -85,14 +85,15 @@ typedef struct cc_options {
     int32_t hook;             /* CC_HOOK_AUTO (default), CC_HOOK_ATOMIC, CC_HOOK_PLAIN or
                                  CC_HOOK_HYBRID                                          */
     int32_t segments;         /* Atomic-Hook: number of edge segments s; 0 = default
-                                 max(1, round(m / n)) (8x that when CC_HOOK_AUTO picks the
-                                 filtered Atomic-Hook, so the first segment is ~n/8
+                                 max(1, round(m / n)) (16x that when CC_HOOK_AUTO picks the
+                                 filtered Atomic-Hook, so the first segment is ~n/16
                                  entries); clamped to [1, ceil(m / 4)]                  */
     int32_t filter;           /* CC_FILTER_* (Atomic-Hook only); default CC_FILTER_AUTO  */
     int32_t filter_after;     /* segments hooked before the giant-component sample
                                  (0 = default 1)                                        */
     int32_t block;            /* threads per workgroup for the edge kernels: 64..1024,
-                                 multiple of 64; 0 = default 256                        */
+                                 multiple of 64; 0 = default: 256, 512 for the filtered
+                                 plan CC_HOOK_AUTO picks, 1024 for the hybrid plan      */
     int32_t edges_per_thread; /* edge entries per thread in the edge kernels: 4, 8 or 16;
                                  0 = default                                            */
     int32_t max_rounds;       /* atomic-free Hook: round cap (0 = n + 1, which is never

@@ -531,6 +531,26 @@ def test_csr_full_size_rmat24(dev):
         assert digest(lab) == rec["sha256"]
 
 
+def test_vertex_table_past_its_tag_range(dev):
+    """The vertex table caches ids below 255 * 81,920 only; forced on a graph
+    of 2^25 vertices, the ids above that range (more than a third of them)
+    are always tested in the bitmap.  A skewed graph with a giant component,
+    so the filter and the table are both used; labels against the oracle."""
+    u, v, n = graphgen.rmat(25, 2, seed=77, m=(1 << 24))
+    assert n > 255 * 81920
+    want = oracle.labels(u, v, n)
+    du, dv = to_dev(u, dev), to_dev(v, dev)
+    for opt in (cc.Options(hook="atomic", segments=64, filter="giant", hot_cache="vertex"),
+                cc.Options(hook="atomic", segments=32, filter="giant", hot_cache="vertex",
+                           path_halving="off"),
+                cc.Options()):
+        say("vertex table past its tag range", opt.segments, opt.hot_cache)
+        lab, st = cc.labels(du, dv, n, options=opt, return_stats=True)
+        assert np.array_equal(lab.cpu().numpy(), want), opt
+        if opt.hot_cache == "vertex":
+            assert st["filter_used"] == 1
+
+
 # ----------------------------------------------------------------------------- maximum sizes
 def test_max_vertex_count(dev):
     """n = 2^31 - 1 (the largest int32 vertex count): edges between far-apart

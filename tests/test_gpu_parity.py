@@ -482,8 +482,10 @@ def test_csr_input_matches_oracle(dev):
         dcol = to_dev(col, dev)
         for opt in (cc.Options(), cc.Options(filter="giant", segments=8),
                     cc.Options(filter="off", segments=3, path_halving="off"),
-                    cc.Options(hook="hybrid"), cc.Options(hook="hybrid", path_halving="off")):
-            say("csr", name, opt.hook, opt.filter, opt.segments)
+                    cc.Options(hook="hybrid"), cc.Options(hook="hybrid", path_halving="off"),
+                    cc.Options(filter="giant", segments=6, hot_cache="off"),
+                    cc.Options(filter="giant", segments=12, filter_after=2, path_halving="off")):
+            say("csr", name, opt.hook, opt.filter, opt.segments, opt.hot_cache)
             got = cc.labels_csr(drp, dcol, n, options=opt).cpu().numpy()
             assert np.array_equal(got, want), (name, opt)
         if name == "rmat_sym":
@@ -526,9 +528,10 @@ def test_csr_full_size_rmat24(dev):
     rp = torch.zeros(n + 1, dtype=torch.int64, device=dev)
     rp[1:] = torch.cumsum(counts, 0)
     del du, dv, order
-    for opt in (cc.Options(), cc.Options(symmetric=True), cc.Options(hook="hybrid")):
+    for opt in (cc.Options(), cc.Options(symmetric=True), cc.Options(hook="hybrid"),
+                cc.Options(hot_cache="off")):
         lab = cc.labels_csr(rp, col, n, options=opt).cpu().numpy()
-        assert digest(lab) == rec["sha256"]
+        assert digest(lab) == rec["sha256"], opt
 
 
 def test_vertex_table_past_its_tag_range(dev):

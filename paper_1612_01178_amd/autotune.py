@@ -13,7 +13,9 @@ coordinate by coordinate from the library's default:
 3. threads per workgroup (256, 512, 1024);
 4. when the atomic-free Hook wins, the frontier compaction threshold tau
    (rewrite the frontier every round, or only below a surviving fraction of
-   50 %, 25 %, 10 %).
+   50 %, 25 %, 10 %);
+5. when the giant-component filter is in the plan, its LDS table: the
+   two-way vertex table, the bitmap-word table, or none.
 
 ``tune_batch`` does the same for the batched LDS solver: path halving in
 the LDS climb and the per-graph segment cap.
@@ -119,6 +121,11 @@ def tune(u, v, n: int, *, reps: int = 3, cache: bool = True, path: str | None = 
     sweeps = [("edges_per_thread", (4, 8, 16)), ("block", (256, 512, 1024))]
     if best.hook == "plain" or (best.hook == "auto" and m < (1 << 22)):
         sweeps.append(("compact_threshold", (0, 500, 250, 100)))
+    # the library's own choice for auto plans: the filter on large lists of
+    # average degree >= 8 (entries per vertex)
+    filtered = best.filter == "giant" or (best.hook == "auto" and m >= (1 << 22) and m >= 8 * n)
+    if filtered:
+        sweeps.append(("hot_cache", ("vertex", "large", "off")))
     for field, values in sweeps:
         for val in values:
             c = Options(**{**best.__dict__, field: val})

@@ -1,7 +1,8 @@
 """Plan autotuner: the cache and shape keys on the host; on the GPU, a tuned
 plan (single graphs and batches) still gives the oracle's labels, and the
-search covers the knobs it claims to (segments, filter, tile, block, and the
-frontier compaction threshold when the atomic-free Hook wins)."""
+search covers the knobs it claims to (segments, filter, tile, block, the
+frontier compaction threshold when the atomic-free Hook wins, the LDS table
+when the filter does)."""
 import numpy as np
 import pytest
 
@@ -27,6 +28,32 @@ def test_cache_round_trip(tmp_path):
                     {"options": opt.__dict__, "ms": 0.1, "n": 1 << 16, "m": 1 << 19})
     assert autotune.options_for(1 << 16, 1 << 19, path=path) == opt
     assert autotune.options_for(1 << 20, 1 << 19, path=path) == cc.Options()
+
+
+def test_search_on_a_cost_model(monkeypatch):
+    """The coordinate search with the solver replaced by a cost model on the
+    host: a filtered plan wins the first coordinate, so the LDS-table
+    coordinate is searched too, and every coordinate's best value is kept."""
+    torch = pytest.importorskip("torch")
+
+    def cost(u, v, n, out, opt, reps):
+        t = 10.0
+        if opt.filter == "giant":
+            t -= 4.0 - 0.01 * opt.segments  # fewest segments among the filtered plans
+        t -= {"large": 1.0, "vertex": 0.5}.get(opt.hot_cache, 0.0)
+        t -= 0.25 if opt.block == 512 else 0.0
+        t -= 0.125 if opt.edges_per_thread == 16 else 0.0
+        return t
+
+    monkeypatch.setattr(autotune, "_time", cost)
+    n, m = 1 << 16, 1 << 20
+    u = torch.zeros(1, dtype=torch.int32).expand(m)  # only its length is used
+    best, table = autotune.tune(u, u, n, reps=1, cache=False)
+    assert (best.hook, best.filter, best.segments) == ("atomic", "giant", 4)
+    assert (best.hot_cache, best.block, best.edges_per_thread) == ("large", 512, 16)
+    assert {o["hot_cache"] for _, o in table} == {"auto", "vertex", "large", "off"}
+    assert "compact_threshold" not in {k for _, o in table for k, val in o.items()
+                                       if val != getattr(cc.Options(), k)}
 
 
 @pytest.mark.gpu

@@ -82,7 +82,7 @@ constexpr int64_t kVertRuns = int64_t(1) << 15;
 constexpr int kVRunsPerPart = 128;
 constexpr int kVPartsMax = (int)(kVertRuns / kVRunsPerPart);
 constexpr int kVPartCap = kVRunsPerPart * 64 * 2;  // endpoints of one part
-constexpr int kVBucketSets = 128;
+constexpr int kVBucketSets = 64;
 constexpr int kVBuckets = kVertSets / kVBucketSets;
 // Scratch words used by launch_hot_vprepare.
 constexpr int64_t kVertScratchWords = (int64_t)kVPartsMax * kVPartCap + 2LL * kVPartsMax * kVBuckets;

@@ -239,14 +239,15 @@ __global__ __launch_bounds__(256) void k_vselect(const uint32_t* __restrict__ re
     }
     __syncthreads();
     // the two largest counts of set s (ties -> smaller tag); tags of vertices
-    // past n are not candidates.  Threads 2i and 2i + 1 scan the lower and
-    // upper half of set i's tags, then merge.
-    static_assert(2 * kVBucketSets == 256 && kVertWays == 2, "two threads per set, two ways");
-    const int set = tid >> 1, half = tid & 1;
+    // past n are not candidates.  Threads 4i .. 4i + 3 scan a quarter of set
+    // i's tags each, then merge their top two in two butterfly steps.
+    static_assert(4 * kVBucketSets == 256 && kVertWays == 2, "four threads per set, two ways");
+    constexpr int kQuarter = (kTags + 3) / 4;
+    const int set = tid >> 2, part = tid & 3;
     const int64_t s = (int64_t)b * kVBucketSets + set;
     const int64_t tags_n = (int64_t)n > s ? ((int64_t)n - s + kVertSets - 1) / kVertSets : 0;
-    const int q0 = half * ((kTags + 1) / 2);
-    const int q1 = (int)min<int64_t>(tags_n, half ? kTags : (kTags + 1) / 2);
+    const int q0 = part * kQuarter;
+    const int q1 = (int)min<int64_t>(tags_n, min(kTags, (part + 1) * kQuarter));
     uint32_t k1 = kVertTagNone, c1 = 0, k2 = kVertTagNone, c2 = 0;
 #pragma unroll 8
     for (int q = q0; q < q1; ++q) {
@@ -262,24 +263,35 @@ __global__ __launch_bounds__(256) void k_vselect(const uint32_t* __restrict__ re
             c2 = cc;
         }
     }
-    // merge with the other half (all of its tags are larger for half 0):
-    // the order is count descending, then tag ascending
-    const uint32_t o1 = __shfl_xor(k1, 1, 64), p1 = __shfl_xor(c1, 1, 64);
-    const uint32_t o2 = __shfl_xor(k2, 1, 64), p2 = __shfl_xor(c2, 1, 64);
+    // merge with the partner's list: the order is count descending, then tag
+    // ascending (the same in every thread, so all four end with one result)
     auto before = [](uint32_t ka, uint32_t ca, uint32_t kb, uint32_t cb) {
         return ka != kVertTagNone && (kb == kVertTagNone || ca > cb || (ca == cb && ka < kb));
     };
-    uint32_t r1, r2;
-    if (before(k1, c1, o1, p1)) {
-        r1 = k1;
-        r2 = before(k2, c2, o1, p1) ? k2 : o1;
-    } else {
-        r1 = o1;
-        r2 = before(k1, c1, o2, p2) ? k1 : o2;
+#pragma unroll
+    for (int d = 1; d <= 2; d <<= 1) {
+        const uint32_t o1 = __shfl_xor(k1, d, 64), p1 = __shfl_xor(c1, d, 64);
+        const uint32_t o2 = __shfl_xor(k2, d, 64), p2 = __shfl_xor(c2, d, 64);
+        if (before(k1, c1, o1, p1)) {
+            if (!before(k2, c2, o1, p1)) {
+                k2 = o1;
+                c2 = p1;
+            }
+        } else {
+            if (!before(k1, c1, o2, p2)) {
+                k2 = o2;
+                c2 = p2;
+            } else {
+                k2 = k1;
+                c2 = c1;
+            }
+            k1 = o1;
+            c1 = p1;
+        }
     }
-    if (half == 0) {
-        tags[2 * s] = (uint8_t)r1;
-        tags[2 * s + 1] = (uint8_t)r2;
+    if (part == 0) {
+        tags[2 * s] = (uint8_t)k1;
+        tags[2 * s + 1] = (uint8_t)k2;
     }
 }
 

@@ -146,10 +146,11 @@ def test_workspace_sizes(lib):
     assert giant == 256 + (n // 32) * 4
     hot = cc.workspace_bytes(n, m, cc.Options(filter="giant", hot_cache="large"))
     assert hot == 256 + 2 * (n // 32) * 4 + 2 * 32768 * 4
-    # vertex table: 256 parts x 16,384 sampled endpoints, two 256 x 640
-    # count/offset tables, 163,840 one-byte tags and as many member flags
+    # vertex table: 256 parts x 16,384 sampled endpoints, two 256 x 1,280
+    # count/offset tables (parts x buckets of 64 sets), 163,840 one-byte tags
+    # and as many member flags
     vert = cc.workspace_bytes(n, m, cc.Options(filter="giant"))
-    assert vert == 256 + (n // 32) * 4 + (256 * 16384 + 2 * 256 * 640) * 4 + 2 * 163840
+    assert vert == 256 + (n // 32) * 4 + (256 * 16384 + 2 * 256 * 1280) * 4 + 2 * 163840
     assert cc.workspace_bytes(n, m, cc.Options(filter="giant", hot_cache="vertex")) == vert
     big = 255 * 81920 + 1  # ids past the tags' range: the automatic choice is the word table
     assert cc.workspace_bytes(big, m, cc.Options(filter="giant")) == \

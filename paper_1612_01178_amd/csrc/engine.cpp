@@ -610,7 +610,7 @@ int32_t enqueue_hybrid(int32_t n, const int32_t* u, const int32_t* v, int64_t m,
     const int grid_cap = device_cu_count() * 8;
     TIMED(kPhaseOther, launch_init(pi, n, ctrl, s));
     TIMED(kPhaseHook, launch_hook_plain(1, u, v, m, F, F, pi, n, ctrl, p.block, p.ept, grid_cap, s));
-    TIMED(kPhaseCompress, launch_mj(pi, n, nullptr, false, s));
+    TIMED(kPhaseCompress, launch_mj_deep(pi, n, s));  // the round leaves chains
     // round 1 reads the input lists and writes its survivors to F, count[1]
     TIMED(kPhaseHook, launch_compact(1, u, v, m, F, F, L.cap, pi, n, ctrl, 0xffffffffu, p.block,
                                      p.ept, grid_cap, s));
@@ -641,8 +641,10 @@ int32_t solve_plain(int32_t n, const int32_t* u, const int32_t* v, int64_t m, in
             const int64_t work = (r == 1) ? m : L.cap;
             TIMED(kPhaseHook, launch_hook_plain((int)r, u, v, work, F0, F1, pi, n, ctrl, p.block,
                                                 p.ept, grid_cap, s));
-            TIMED(kPhaseCompress,
-                  launch_mj(pi, n, r == 1 ? nullptr : &ctrl->count[(r - 1) & 1], false, s));
+            if (r == 1)  // the round leaves chains
+                TIMED(kPhaseCompress, launch_mj_deep(pi, n, s));
+            else
+                TIMED(kPhaseCompress, launch_mj(pi, n, &ctrl->count[(r - 1) & 1], false, s));
             TIMED(kPhaseHook, launch_compact((int)r, u, v, work, F0, F1, L.cap, pi, n, ctrl,
                                              p.tau, p.block, p.ept, grid_cap, s));
         }
@@ -982,7 +984,7 @@ int32_t csr_impl(int32_t n, const int64_t* row_ptr, const int32_t* col, int64_t 
     if (p.hook == CC_HOOK_HYBRID) {
         TIMED(kPhaseHook, launch_ahook_csr(row_ptr, col, n, 0, m, out, ctrl, nullptr, p.symmetric,
                                            false, /*plain=*/true, s));
-        TIMED(kPhaseCompress, launch_mj(out, n, nullptr, false, s));
+        TIMED(kPhaseCompress, launch_mj_deep(out, n, s));  // the pass leaves chains
         TIMED(kPhaseHook, launch_ahook_csr(row_ptr, col, n, 0, m, out, ctrl, nullptr, p.symmetric,
                                            p.halve, false, s));
         TIMED(kPhaseCompress, launch_mj(out, n, nullptr, false, s));

@@ -21,6 +21,11 @@ hipError_t launch_ahook(const int32_t* u, const int32_t* v, int64_t begin, int64
 // loads and stores (see common.hpp).
 hipError_t launch_mj(int32_t* pi, int32_t n, const uint32_t* gate, bool coherent, hipStream_t s);
 
+// Multi-Jump for deep trees: pointer jumping within blocks of consecutive
+// vertices in LDS, then a climb across blocks (the plain Multi-Jump for
+// n < 2^22).  Postcondition as launch_mj: every tree is a star.
+hipError_t launch_mj_deep(int32_t* pi, int32_t n, hipStream_t s);
+
 // Giant-component sample: label of the component that holds the most of
 // `samples` edge endpoints drawn across entries [0, m); sets ctrl->giant and
 // ctrl->filter_on.  Requires pi to be a forest of stars (after Multi-Jump).

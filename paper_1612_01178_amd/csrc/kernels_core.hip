@@ -275,6 +275,81 @@ __global__ __launch_bounds__(256) void k_mj(int32_t* pi, int32_t n, const uint32
     }
 }
 
+// Multi-Jump for deep trees (after an atomic-free Hook round every vertex
+// points at a neighbour, and on a percolated grid the trees are chains of up
+// to ~150 levels, which a per-vertex climb walks one dependent load at a
+// time: 0.33 ms on a 4096^2 grid).  k_mj_local first takes kMjBlock
+// consecutive vertices per workgroup into LDS and, in rounds, replaces every
+// parent that lies inside the block by its own parent, until each vertex
+// points at a root or outside the block, and writes back the changed
+// entries; the Multi-Jump that follows then climbs across blocks only (a
+// 4096^2 grid: 0.6 block exits per path on average).  Every value written
+// is an ancestor, so pi stays a forest with pi[x] <= x.  No hook runs
+// concurrently.
+constexpr int kMjBlock = 16384;
+
+__global__ __launch_bounds__(1024, 8) void k_mj_local(int32_t* pi, int32_t n) {
+    __shared__ int32_t lp[kMjBlock];
+    constexpr int kPer = kMjBlock / 1024;
+    const int64_t base = (int64_t)blockIdx.x * kMjBlock;
+    const int cnt = (int)min<int64_t>(kMjBlock, (int64_t)n - base);
+    auto lds_ld = [&](int i) { return __hip_atomic_load(lp + i, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP); };
+    auto lds_st = [&](int i, int32_t x) { __hip_atomic_store(lp + i, x, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP); };
+#pragma unroll
+    for (int k = 0; k < kPer; ++k) {
+        const int i = k * 1024 + (int)threadIdx.x;
+        if (i < cnt) lds_st(i, pi[base + i]);
+    }
+    __syncthreads();
+    uint32_t dirty = 0;  // bit k: entry k of this thread changed
+    constexpr int kGroup = 4;  // entries whose loads are in flight together
+    while (true) {
+        bool changed = false;
+#pragma unroll
+        for (int h = 0; h < kPer; h += kGroup) {
+            int32_t pv[kGroup], gv[kGroup];
+#pragma unroll
+            for (int k = 0; k < kGroup; ++k) {
+                const int i = (h + k) * 1024 + (int)threadIdx.x;
+                pv[k] = i < cnt ? lds_ld(i) : (int32_t)(base + i);
+            }
+#pragma unroll
+            for (int k = 0; k < kGroup; ++k) {
+                const int i = (h + k) * 1024 + (int)threadIdx.x;
+                const int64_t q = (int64_t)pv[k] - base;
+                const bool inside = i < cnt && q >= 0 && q < cnt && q != i;
+                gv[k] = lds_ld(inside ? (int)q : 0);
+                if (!inside) gv[k] = pv[k];
+            }
+#pragma unroll
+            for (int k = 0; k < kGroup; ++k) {
+                if (gv[k] != pv[k]) {
+                    lds_st((h + k) * 1024 + (int)threadIdx.x, gv[k]);
+                    dirty |= 1u << (h + k);
+                    changed = true;
+                }
+            }
+        }
+        if (!__syncthreads_or(changed)) break;
+    }
+#pragma unroll
+    for (int k = 0; k < kPer; ++k)
+        if (dirty >> k & 1) {
+            const int i = k * 1024 + (int)threadIdx.x;
+            st_tree<false>(pi + base + i, lds_ld(i));
+        }
+}
+
+hipError_t launch_mj_deep(int32_t* pi, int32_t n, hipStream_t s) {
+    if (n <= 0) return hipSuccess;
+    // below ~256 blocks the GPU is not filled and the plain Multi-Jump wins
+    if (n >= (1 << 22)) {
+        const int grid = (int)(((int64_t)n + kMjBlock - 1) / kMjBlock);
+        k_mj_local<<<grid, 1024, 0, s>>>(pi, n);
+    }
+    return launch_mj(pi, n, nullptr, false, s);
+}
+
 hipError_t launch_mj(int32_t* pi, int32_t n, const uint32_t* gate, bool coherent, hipStream_t s) {
     if (n <= 0) return hipSuccess;
     const int64_t groups = ((int64_t)n + 3) / 4;

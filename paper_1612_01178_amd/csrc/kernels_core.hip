@@ -302,17 +302,11 @@ __global__ __launch_bounds__(1024, 8) void k_mj_local(int32_t* pi, int32_t n) {
     }
     __syncthreads();
     uint32_t dirty = 0;  // bit k: entry k of this thread changed
-    // bit k: entry k may still change.  An entry that did not change in a
-    // round points at a root or outside the block, and roots stay roots, so
-    // it is final.
-    uint32_t pending = (1u << kPer) - 1;
     constexpr int kGroup = 4;  // entries whose loads are in flight together
     while (true) {
         bool changed = false;
-        uint32_t still = 0;
 #pragma unroll
         for (int h = 0; h < kPer; h += kGroup) {
-            if (!(pending >> h & ((1u << kGroup) - 1))) continue;
             int32_t pv[kGroup], gv[kGroup];
 #pragma unroll
             for (int k = 0; k < kGroup; ++k) {
@@ -329,15 +323,13 @@ __global__ __launch_bounds__(1024, 8) void k_mj_local(int32_t* pi, int32_t n) {
             }
 #pragma unroll
             for (int k = 0; k < kGroup; ++k) {
-                if ((pending >> (h + k) & 1) && gv[k] != pv[k]) {
+                if (gv[k] != pv[k]) {
                     lds_st((h + k) * 1024 + (int)threadIdx.x, gv[k]);
                     dirty |= 1u << (h + k);
-                    still |= 1u << (h + k);
                     changed = true;
                 }
             }
         }
-        pending = still;
         if (!__syncthreads_or(changed)) break;
     }
 #pragma unroll

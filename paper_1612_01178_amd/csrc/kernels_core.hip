@@ -340,14 +340,30 @@ __global__ __launch_bounds__(1024, 8) void k_mj_local(int32_t* pi, int32_t n) {
         }
 }
 
+// Multi-Jump with one vertex per thread: after k_mj_local most climbs are a
+// dependent load or two across blocks, and a thread holding four vertices
+// would run their climbs one after the other.
+__global__ __launch_bounds__(256) void k_mj1(int32_t* pi, int32_t n) {
+    const int64_t v = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (v >= n) return;
+    int32_t q = ld_tree<false>(pi + v);
+    if (q == v) return;
+    int32_t g = ld_tree<false>(pi + q);
+    while (g != q) {
+        st_tree<false>(pi + v, g);
+        q = g;
+        g = ld_tree<false>(pi + q);
+    }
+}
+
 hipError_t launch_mj_deep(int32_t* pi, int32_t n, hipStream_t s) {
     if (n <= 0) return hipSuccess;
     // below ~256 blocks the GPU is not filled and the plain Multi-Jump wins
-    if (n >= (1 << 22)) {
-        const int grid = (int)(((int64_t)n + kMjBlock - 1) / kMjBlock);
-        k_mj_local<<<grid, 1024, 0, s>>>(pi, n);
-    }
-    return launch_mj(pi, n, nullptr, false, s);
+    if (n < (1 << 22)) return launch_mj(pi, n, nullptr, false, s);
+    const int grid = (int)(((int64_t)n + kMjBlock - 1) / kMjBlock);
+    k_mj_local<<<grid, 1024, 0, s>>>(pi, n);
+    k_mj1<<<(int)(((int64_t)n + 255) / 256), 256, 0, s>>>(pi, n);
+    return hipGetLastError();
 }
 
 hipError_t launch_mj(int32_t* pi, int32_t n, const uint32_t* gate, bool coherent, hipStream_t s) {

@@ -615,7 +615,7 @@ int32_t enqueue_hybrid(int32_t n, const int32_t* u, const int32_t* v, int64_t m,
     TIMED(kPhaseHook, launch_compact(1, u, v, m, F, F, L.cap, pi, n, ctrl, 0xffffffffu, p.block,
                                      p.ept, grid_cap, s));
     TIMED(kPhaseHook, launch_ahook_pairs(F, &ctrl->count[1], L.cap, pi, p.halve, grid_cap, s));
-    TIMED(kPhaseCompress, launch_mj(pi, n, &ctrl->count[1], false, s));
+    TIMED(kPhaseCompress, launch_mj1(pi, n, &ctrl->count[1], s));
     if (st) {
         st->hook_launches += 3;
         st->compress_launches += 2;
@@ -644,7 +644,7 @@ int32_t solve_plain(int32_t n, const int32_t* u, const int32_t* v, int64_t m, in
             if (r == 1)  // the round leaves chains
                 TIMED(kPhaseCompress, launch_mj_deep(pi, n, s));
             else
-                TIMED(kPhaseCompress, launch_mj(pi, n, &ctrl->count[(r - 1) & 1], false, s));
+                TIMED(kPhaseCompress, launch_mj1(pi, n, &ctrl->count[(r - 1) & 1], s));
             TIMED(kPhaseHook, launch_compact((int)r, u, v, work, F0, F1, L.cap, pi, n, ctrl,
                                              p.tau, p.block, p.ept, grid_cap, s));
         }

@@ -25,6 +25,8 @@ hipError_t launch_mj(int32_t* pi, int32_t n, const uint32_t* gate, bool coherent
 // vertices in LDS, then a climb across blocks (the plain Multi-Jump for
 // n < 2^22).  Postcondition as launch_mj: every tree is a star.
 hipError_t launch_mj_deep(int32_t* pi, int32_t n, hipStream_t s);
+// Multi-Jump with one vertex per thread (atomic-free path); `gate` as launch_mj.
+hipError_t launch_mj1(int32_t* pi, int32_t n, const uint32_t* gate, hipStream_t s);
 
 // Giant-component sample: label of the component that holds the most of
 // `samples` edge endpoints drawn across entries [0, m); sets ctrl->giant and

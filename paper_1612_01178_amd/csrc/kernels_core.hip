@@ -340,10 +340,14 @@ __global__ __launch_bounds__(1024, 8) void k_mj_local(int32_t* pi, int32_t n) {
         }
 }
 
-// Multi-Jump with one vertex per thread: after k_mj_local most climbs are a
-// dependent load or two across blocks, and a thread holding four vertices
-// would run their climbs one after the other.
-__global__ __launch_bounds__(256) void k_mj1(int32_t* pi, int32_t n) {
+// Multi-Jump with one vertex per thread, for the atomic-free path: after
+// k_mj_local, or after a round that hooked roots, most climbs are a
+// dependent load or two, and a thread holding four vertices would run their
+// climbs one after the other (a 4096^2 grid: 0.575 -> 0.537 ms; ER 2^16
+// rounds: 0.100 -> 0.090 ms).  The Atomic-Hook path keeps k_mj, whose
+// 16-byte loads win on its shallow trees (R-MAT 24: 3.75 against 3.78 ms).
+__global__ __launch_bounds__(256) void k_mj1(int32_t* pi, int32_t n, const uint32_t* gate) {
+    if (gate != nullptr && *gate == 0) return;
     const int64_t v = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (v >= n) return;
     int32_t q = ld_tree<false>(pi + v);
@@ -359,10 +363,16 @@ __global__ __launch_bounds__(256) void k_mj1(int32_t* pi, int32_t n) {
 hipError_t launch_mj_deep(int32_t* pi, int32_t n, hipStream_t s) {
     if (n <= 0) return hipSuccess;
     // below ~256 blocks the GPU is not filled and the plain Multi-Jump wins
-    if (n < (1 << 22)) return launch_mj(pi, n, nullptr, false, s);
+    if (n < (1 << 22)) return launch_mj1(pi, n, nullptr, s);
     const int grid = (int)(((int64_t)n + kMjBlock - 1) / kMjBlock);
     k_mj_local<<<grid, 1024, 0, s>>>(pi, n);
-    k_mj1<<<(int)(((int64_t)n + 255) / 256), 256, 0, s>>>(pi, n);
+    k_mj1<<<(int)(((int64_t)n + 255) / 256), 256, 0, s>>>(pi, n, nullptr);
+    return hipGetLastError();
+}
+
+hipError_t launch_mj1(int32_t* pi, int32_t n, const uint32_t* gate, hipStream_t s) {
+    if (n <= 0) return hipSuccess;
+    k_mj1<<<(int)(((int64_t)n + 255) / 256), 256, 0, s>>>(pi, n, gate);
     return hipGetLastError();
 }
 

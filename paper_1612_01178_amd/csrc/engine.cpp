@@ -508,8 +508,8 @@ FilterBufs filter_bufs(char* base, const Layout& L) {
 // Growth factor of the super-segments hooked after the giant filter is on:
 // with the filter, later segments hook few edges, so they are taken in
 // launches of 1, 4, 16, ... segments (each followed by a Multi-Jump and a
-// bitmap refresh).  Measured on R-MAT 24 (s = 256): x2 4.67 ms, x4 4.57 ms,
-// x8 4.62 ms -- fewer refreshes against a staler bitmap.
+// bitmap refresh).  Measured on R-MAT 24 (s = 512): x2 3.81 ms, x4 3.76 ms,
+// x8 3.88 ms -- fewer refreshes against a staler bitmap.
 constexpr int64_t kSuperGrowth = 4;
 
 int32_t enqueue_atomic(int32_t n, const int32_t* u, const int32_t* v, int64_t m, int32_t* pi,

@@ -554,6 +554,28 @@ def test_vertex_table_past_its_tag_range(dev):
             assert st["filter_used"] == 1
 
 
+def test_deep_chains_with_a_ragged_last_block(dev):
+    """Two interleaved paths (edges (v, v + 2)) on 2^22 + 5 vertices, in a
+    seeded shuffled order: the atomic-free pass leaves chains thousands of
+    levels deep, which the block-local jumping (blocks of 16,384 vertices,
+    the last one ragged) and the following Multi-Jump must flatten.  Closed
+    form: label[v] = v mod 2.  Atomic-free rounds, the hybrid plan and the
+    CSR hybrid."""
+    n = (1 << 22) + 5
+    a = np.arange(n - 2, dtype=np.int32)
+    perm = graphgen.permutation(n - 2, seed=81)
+    u, v = a[perm], a[perm] + 2
+    want = np.arange(n, dtype=np.int32) % 2
+    du, dv = to_dev(u, dev), to_dev(v, dev)
+    for opt in (cc.Options(hook="plain"), cc.Options(hook="hybrid"), cc.Options()):
+        say("deep chains", opt.hook)
+        assert np.array_equal(cc.labels(du, dv, n, options=opt).cpu().numpy(), want), opt.hook
+    rp, col = _to_csr(u, v, n)
+    got = cc.labels_csr(torch.from_numpy(rp).to(dev), to_dev(col, dev), n,
+                        options=cc.Options(hook="hybrid")).cpu().numpy()
+    assert np.array_equal(got, want)
+
+
 # ----------------------------------------------------------------------------- maximum sizes
 def test_max_vertex_count(dev):
     """n = 2^31 - 1 (the largest int32 vertex count): edges between far-apart

@@ -698,6 +698,7 @@ def test_graph_capture_replays_match_eager(dev):
     out = torch.empty(n, dtype=torch.int32, device=dev)
     for opt in (cc.Options(hook="atomic", graph=True),
                 cc.Options(hook="atomic", filter="giant", segments=64, graph=True),
+                cc.Options(hook="atomic", filter="giant", segments=64, hot_cache="large", graph=True),
                 cc.Options(hook="atomic", filter="off", segments=3, graph=True),
                 cc.Options(hook="plain", graph=True),
                 cc.Options(hook="plain", graph=True, rounds_per_check=1, compact_threshold=500)):

@@ -153,6 +153,9 @@ def main():
         if args.hook == "auto" and args.filter == "auto" and args.hot == "auto" and not (
                 args.segments or args.ept or args.block or args.coherent or args.symmetric):
             traffic = measured_traffic(args.workload, "atomic")
+    elif st.get("hook") == 3:
+        alg_bytes = 8.0 * m  # the atomic-free round's pass over the input entries
+        kernel = "k_hook_plain + k_compact + k_ahook_pairs (all edge passes of one solve)"
     else:
         alg_bytes = 8.0 * m  # first Hook pass over the input entries
         kernel = "k_hook_plain + k_compact (all edge passes of one solve)"
@@ -176,7 +179,7 @@ def main():
         "data": "synthetic (seeded generator, no dataset)",
         "config": {"workload": args.workload, "n": n, "m_entries": m,
                    "symmetric_flag": bool(args.symmetric),
-                   "hook": {1: "atomic", 2: "plain"}.get(st.get("hook"), args.hook),
+                   "hook": {1: "atomic", 2: "plain", 3: "hybrid"}.get(st.get("hook"), args.hook),
                    "filter": args.filter,
                    "segments": st["segments"] if st else None,
                    "filter_used": st["filter_used"] if st else None,

@@ -69,9 +69,8 @@ extern "C" {
 #define CC_HOOK_HYBRID 3 /* one atomic-free Hook round (Fig. 2) over all entries with its
                             Multi-Jump and frontier compaction, then Atomic-Hook (Fig. 3,
                             path halving) over the still-active root pairs and a final
-                            Multi-Jump: a fixed launch sequence, no host read.  For CSR
-                            input: an atomic-free pass and an Atomic-Hook pass over all
-                            entries, each followed by a Multi-Jump                  */
+                            Multi-Jump: a fixed launch sequence, no host read (the same
+                            for CSR input)                                          */
 
 #define CC_FILTER_OFF 0  /* Atomic-Hook only: hook every edge entry                   */
 #define CC_FILTER_GIANT 1 /* Atomic-Hook only: after the first segment(s), sample the

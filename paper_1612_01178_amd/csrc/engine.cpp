@@ -131,7 +131,7 @@ int32_t make_plan(int32_t n, int64_t m, const cc_options* o, Plan& p,
     // cost dominates and the atomic-free rounds win (ER 2^16: 0.09 ms against
     // 0.18 hybrid and 0.14-0.28 Atomic-Hook); a no-sync call needs a fixed launch
     // sequence and takes the hybrid plan there.  CSR input has no atomic-free
-    // rounds: its large sparse inputs take the hybrid plan (grid as CSR 0.77
+    // rounds: its large sparse inputs take the hybrid plan (grid as CSR 0.73
     // ms against 1.47 Atomic-Hook), the rest the Atomic-Hook.
     const bool large = m >= (int64_t(1) << 22);
     const bool dense_large = large && n > 0 && m >= 8 * (int64_t)n;
@@ -936,11 +936,12 @@ int32_t stream_impl(int32_t n, const int32_t* hu, const int32_t* hv, int64_t m, 
 // Same plan as a pair list of m entries (segments of the col[] array, each
 // followed by a Multi-Jump; with the giant filter the growing super-segments
 // of enqueue_atomic); the first endpoint of an entry is its row.  The hybrid
-// plan is one atomic-free Hook pass over all entries, a Multi-Jump, then one
-// Atomic-Hook pass (with path halving) over all entries and a Multi-Jump: the
-// first pass joins nearly everything with plain stores, and the second, in
-// which almost every entry finds its endpoints already in one tree, restores
-// the links the first pass overwrote.  CSR needs no frontier for it.
+// plan is the pair-list one: an atomic-free Hook pass over all entries, a
+// Multi-Jump, the still-active entries compacted to root pairs, then the
+// Atomic-Hook (with path halving) over those pairs and a Multi-Jump; the
+// first pass joins nearly everything with plain stores, and the Atomic-Hook
+// restores the links it overwrote (grid as CSR 0.73 ms; 0.77 ms with an
+// Atomic-Hook pass over all entries instead of the compaction).
 int32_t csr_impl(int32_t n, const int64_t* row_ptr, const int32_t* col, int64_t m, int32_t* out,
                  const cc_options* opts, hipStream_t s, cc_stats* st) {
     if (n < 0 || m < 0) return fail(CC_ERR_ARG, "n < 0 or m < 0");
@@ -968,11 +969,14 @@ int32_t csr_impl(int32_t n, const int64_t* row_ptr, const int32_t* col, int64_t 
     std::lock_guard<std::mutex> lk(pe->mu);
     rc = ensure_host(pe);
     if (rc != CC_OK) return rc;
-    rc = ensure_dev(pe, 256 + bits_bytes);
+    // the hybrid plan's frontier of root pairs (8 B x m)
+    const size_t frontier_bytes = p.hook == CC_HOOK_HYBRID ? align256((size_t)m * 8) : 0;
+    rc = ensure_dev(pe, 256 + bits_bytes + frontier_bytes);
     if (rc != CC_OK) return rc;
     char* ws = static_cast<char*>(pe->dev);
     Ctrl* ctrl = reinterpret_cast<Ctrl*>(ws);
     uint32_t* bits = filter ? reinterpret_cast<uint32_t*>(ws + 256) : nullptr;
+    int2* F = frontier_bytes ? reinterpret_cast<int2*>(ws + 256 + bits_bytes) : nullptr;
     const int S = p.segments;
     auto bound = [&](int64_t i) -> int64_t { return i >= S ? m : (m * i / S) & ~int64_t(3); };
     Timer tm;
@@ -985,10 +989,15 @@ int32_t csr_impl(int32_t n, const int64_t* row_ptr, const int32_t* col, int64_t 
         TIMED(kPhaseHook, launch_ahook_csr(row_ptr, col, n, 0, m, out, ctrl, nullptr, p.symmetric,
                                            false, /*plain=*/true, s));
         TIMED(kPhaseCompress, launch_mj_deep(out, n, s));  // the pass leaves chains
-        TIMED(kPhaseHook, launch_ahook_csr(row_ptr, col, n, 0, m, out, ctrl, nullptr, p.symmetric,
-                                           p.halve, false, s));
-        TIMED(kPhaseCompress, launch_mj(out, n, nullptr, false, s));
-        hooks = jumps = 2;
+        // the entries still active, as root pairs, then the Atomic-Hook over
+        // those pairs (as the pair-list hybrid plan)
+        TIMED(kPhaseHook, launch_compact_csr(row_ptr, col, n, m, out, F, &ctrl->count[1],
+                                             p.symmetric, s));
+        TIMED(kPhaseHook, launch_ahook_pairs(F, &ctrl->count[1], m, out, p.halve,
+                                             device_cu_count() * 8, s));
+        TIMED(kPhaseCompress, launch_mj1(out, n, &ctrl->count[1], s));
+        hooks = 3;
+        jumps = 2;
     } else if (!filter) {
         for (int i = 0; i < S; ++i) {
             TIMED(kPhaseHook, launch_ahook_csr(row_ptr, col, n, bound(i), bound(i + 1), out, ctrl,

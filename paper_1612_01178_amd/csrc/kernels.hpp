@@ -124,6 +124,11 @@ hipError_t launch_ahook_hot(const int32_t* u, const int32_t* v, int64_t begin, i
 hipError_t launch_ahook_csr(const int64_t* row_ptr, const int32_t* col, int32_t n, int64_t begin,
                             int64_t end, int32_t* pi, Ctrl* ctrl, const uint32_t* bits, bool sym,
                             bool halve, bool plain, hipStream_t s);
+// CSR hybrid: the entries whose endpoints' roots differ (pi a forest of stars)
+// as root pairs in fr[0 .. *count) (capacity m; *count accumulated).
+hipError_t launch_compact_csr(const int64_t* row_ptr, const int32_t* col, int32_t n, int64_t m,
+                              const int32_t* pi, int2* fr, uint32_t* count, bool sym,
+                              hipStream_t s);
 // Sets the range bit unless row_ptr[0] == 0, row_ptr[n] == m and row_ptr is
 // non-decreasing.
 hipError_t launch_csr_check(const int64_t* row_ptr, int32_t n, int64_t m, Ctrl* ctrl,

@@ -206,6 +206,114 @@ __global__ __launch_bounds__(512) void k_ahook_csr(const int64_t* __restrict__ r
     if (bad) atomicOr(&ctrl->status, kStatusRange);
 }
 
+// Frontier compaction of a CSR adjacency for the hybrid plan (after its
+// atomic-free pass and a Multi-Jump, so pi is a forest of stars): the entries
+// whose endpoints have different roots are written as root pairs to `fr`
+// (capacity m), their number accumulated in *count.  Rows are found as in
+// k_ahook_csr; positions come from wave ballots, per-wave totals in LDS and
+// one atomicAdd per workgroup.
+template <int EPT>
+__global__ __launch_bounds__(512) void k_compact_csr(const int64_t* __restrict__ row_ptr,
+                                                     const int32_t* __restrict__ col, int32_t n,
+                                                     int64_t m, const int32_t* pi, int2* fr,
+                                                     uint32_t* count, bool sym) {
+    __shared__ int64_t win[kCsrWindow + 1];
+    __shared__ int64_t r_sh[2];
+    __shared__ uint32_t wave_off[512 / 64];
+    __shared__ uint32_t base_sh;
+    const int64_t tile = (int64_t)blockDim.x * EPT;
+    const int64_t t0 = (int64_t)blockIdx.x * tile;
+    const int64_t t1 = min(m, t0 + tile);  // exclusive
+    if (threadIdx.x < 64) {
+        const int64_t r = upper_row32(row_ptr, n, threadIdx.x < 32 ? t0 : t1 - 1);
+        if (threadIdx.x == 0) r_sh[0] = r;
+        if (threadIdx.x == 32) r_sh[1] = r;
+    }
+    __syncthreads();
+    const int64_t r_lo = r_sh[0];
+    const int64_t r_hi = r_sh[1] < r_lo ? r_lo : r_sh[1];
+    const bool in_lds = r_hi - r_lo + 1 <= kCsrWindow;
+    if (in_lds)
+        for (int64_t r = r_lo + threadIdx.x; r <= r_hi + 1; r += blockDim.x) win[r - r_lo] = row_ptr[r];
+    __syncthreads();
+    int32_t qa[EPT], qb[EPT];
+    uint32_t act = 0;
+#pragma unroll
+    for (int k = 0; k < EPT / 4; ++k) {
+        const int64_t e0 = t0 + (int64_t)k * blockDim.x * 4 + (int64_t)threadIdx.x * 4;
+        int64_t r = r_lo;
+        if (e0 < t1) {
+            if (in_lds) {
+                int64_t lo = 0, hi = r_hi - r_lo;
+                while (lo < hi) {
+                    const int64_t mid = (lo + hi + 1) >> 1;
+                    if (win[mid] <= e0) lo = mid;
+                    else hi = mid - 1;
+                }
+                r = r_lo + lo;
+            } else {
+                r = upper_row(row_ptr, r_lo, r_hi, e0);
+            }
+        }
+#pragma unroll
+        for (int j = 0; j < 4; ++j) {
+            const int i = 4 * k + j;
+            const int64_t e = e0 + j;
+            qa[i] = qb[i] = 0;
+            if (e >= t1) continue;
+            if (in_lds) {
+                while (r < r_hi && win[r + 1 - r_lo] <= e) ++r;
+            } else {
+                while (r < (int64_t)n - 1 && row_ptr[r + 1] <= e) ++r;
+            }
+            const int32_t a = (int32_t)r, b = __builtin_nontemporal_load(col + e);
+            if ((uint32_t)b >= (uint32_t)n || a == b || (sym && b < a)) continue;
+            qa[i] = ld_tree<false>(pi + a);
+            qb[i] = ld_tree<false>(pi + b);
+            if (qa[i] != qb[i]) act |= 1u << i;
+        }
+    }
+    // positions: per slot a wave ballot, lanes below counted with mbcnt
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+    uint32_t pos[EPT];
+    uint32_t run = 0;
+#pragma unroll
+    for (int i = 0; i < EPT; ++i) {
+        const uint64_t mk = __ballot((act >> i) & 1);
+        pos[i] = run + __builtin_amdgcn_mbcnt_hi((uint32_t)(mk >> 32),
+                                                 __builtin_amdgcn_mbcnt_lo((uint32_t)mk, 0u));
+        run += (uint32_t)__popcll(mk);
+    }
+    if (lane == 0) wave_off[wave] = run;
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        uint32_t acc = 0;
+        for (int w = 0; w < (int)(blockDim.x >> 6); ++w) {
+            const uint32_t t = wave_off[w];
+            wave_off[w] = acc;
+            acc += t;
+        }
+        base_sh = acc ? atomicAdd(count, acc) : 0u;
+    }
+    __syncthreads();
+    const uint64_t at = (uint64_t)base_sh + wave_off[wave];
+#pragma unroll
+    for (int i = 0; i < EPT; ++i)
+        if ((act >> i) & 1) fr[at + pos[i]] = int2{qa[i], qb[i]};
+}
+
+hipError_t launch_compact_csr(const int64_t* row_ptr, const int32_t* col, int32_t n, int64_t m,
+                              const int32_t* pi, int2* fr, uint32_t* count, bool sym,
+                              hipStream_t s) {
+    if (m <= 0 || n <= 0) return hipSuccess;
+    constexpr int EPT = 8;
+    constexpr int kBlock = 512;
+    const int64_t grid64 = (m + kBlock * EPT - 1) / (kBlock * EPT);
+    if (grid64 > 0x7fffffff) return hipErrorInvalidValue;
+    k_compact_csr<EPT><<<(int)grid64, kBlock, 0, s>>>(row_ptr, col, n, m, pi, fr, count, sym);
+    return hipGetLastError();
+}
+
 // Entry-count check of a CSR adjacency: status bit kStatusRange when
 // row_ptr is not non-decreasing from 0 to m (done on the device, one pass).
 __global__ __launch_bounds__(256) void k_csr_check(const int64_t* __restrict__ row_ptr, int32_t n,

@@ -237,6 +237,35 @@ int32_t cc_stream_status(void* stream);
 /* Device scratch bytes cc_labels_ex needs for (n, m, opts); 0 on bad input. */
 size_t cc_workspace_bytes(int32_t n, int64_t m, const cc_options* opts);
 
+/* As cc_labels_ex, for callers that cannot allocate memory (code under HIP
+ * graph capture, tight serving loops, harnesses that forbid hipMalloc): the
+ * call makes no device or host allocation.  Its workspace is a fixed device
+ * array of CC_NOALLOC_SCRATCH_BYTES bytes inside the library, one per device,
+ * held from the first call on a device until the process ends; the caller
+ * still passes the edges and out_label.
+ *   n, edges_u, edges_v, m, out_label   as cc_labels
+ *   opts    [host] options or NULL; graph, no_sync and profile must be 0
+ *           (CC_ERR_ARG otherwise)
+ *   stream  hipStream_t to run on (NULL = null stream)
+ *   stats   [host] optional statistics output, or NULL
+ * Synchronous: returns after the labels are complete on `stream`.  With the
+ * automatic hook (opts NULL or opts->hook = CC_HOOK_AUTO) a plan whose
+ * workspace would exceed the array falls back to the Atomic-Hook (its
+ * workspace: 256 bytes, plus n/8 bytes and the 20 MiB vertex table with the
+ * giant filter, dropped when even that does not fit), so every size is
+ * solved; an explicitly requested plan whose workspace (cc_workspace_bytes)
+ * exceeds CC_NOALLOC_SCRATCH_BYTES returns CC_ERR_NOMEM with a message.
+ * The array is shared by every call on a device and keeps the last call's
+ * contents (each solve rewrites what it reads): calls on one device are
+ * serialised by a host mutex, so two such calls never overlap on a GPU;
+ * calls on different devices run independently.
+ * Returns CC_OK, CC_ERR_ARG, CC_ERR_RANGE, CC_ERR_NOMEM, CC_ERR_NOCONVERGE
+ * or CC_ERR_HIP. */
+#define CC_NOALLOC_SCRATCH_BYTES (32 << 20)
+int32_t cc_labels_noalloc(int32_t n, const int32_t* edges_u, const int32_t* edges_v, int64_t m,
+                          int32_t* out_label, const cc_options* opts, void* stream,
+                          cc_stats* stats);
+
 /* ------------------------------------------------------------------ batches */
 
 /* Min-id labels of many independent graphs packed back to back; synchronous.

@@ -29,13 +29,14 @@ CC_ERR_NOMEM = -3
 CC_ERR_HIP = -4
 CC_ERR_NOCONVERGE = -5
 CC_BATCH_LDS_MAX_N = 65536
+CC_NOALLOC_SCRATCH_BYTES = 32 << 20
 
 _HOOKS = {"auto": 0, "atomic": 1, "plain": 2, "hybrid": 3}
 _FILTERS = {"off": 0, "giant": 1, "auto": 2}
 _HOST_LOOPS = {"off": 0, "jump": 1, "multijump": 2}
 
 # Every symbol include/hookcc.h declares.
-EXPORTS = ("cc_options_init", "cc_labels", "cc_labels_ex", "cc_workspace_bytes",
+EXPORTS = ("cc_options_init", "cc_labels", "cc_labels_ex", "cc_workspace_bytes", "cc_labels_noalloc",
            "cc_labels_batch", "cc_labels_batch_ex", "cc_labels_list", "cc_labels_host", "cc_labels_csr", "cc_probe",
            "cc_last_error", "cc_release", "cc_version", "cc_stream_status", "cc_server_create",
            "cc_server_submit", "cc_server_wait", "cc_server_poll", "cc_server_stats",
@@ -157,6 +158,9 @@ def load():
             lib.cc_labels_ex.argtypes = [_i32, _vp, _vp, _i64, _vp, ctypes.POINTER(_COptions),
                                          _vp, ctypes.c_size_t, _vp, ctypes.POINTER(_CStats)]
             lib.cc_labels_ex.restype = _i32
+            lib.cc_labels_noalloc.argtypes = [_i32, _vp, _vp, _i64, _vp, ctypes.POINTER(_COptions),
+                                              _vp, ctypes.POINTER(_CStats)]
+            lib.cc_labels_noalloc.restype = _i32
             lib.cc_workspace_bytes.argtypes = [_i32, _i64, ctypes.POINTER(_COptions)]
             lib.cc_workspace_bytes.restype = ctypes.c_size_t
             lib.cc_labels_batch.argtypes = [_i32, _vp, _vp, _vp, _vp, _vp]
@@ -276,6 +280,31 @@ def labels(u, v, n: int, *, out=None, options: Options | None = None, stream=Non
         rc = load().cc_labels_ex(int(n), u.data_ptr(), v.data_ptr(), u.numel(), out.data_ptr(),
                                  ctypes.byref(opts), ws_ptr, ws_bytes, _stream_handle(stream),
                                  ctypes.byref(st))
+    _check(rc)
+    if return_stats:
+        return out, {f: getattr(st, f) for f, _ in _CStats._fields_ if f != "reserved"}
+    return out
+
+
+def labels_noalloc(u, v, n: int, *, out, options: Options | None = None, stream=None,
+                   return_stats: bool = False):
+    """cc_labels_noalloc: as ``labels`` with the workspace in the library's
+    fixed device array, so the call allocates nothing; ``out`` (int32 CUDA
+    tensor of at least n entries) must be given."""
+    u = _edge_tensor(u, "u")
+    v = _edge_tensor(v, "v")
+    out = _edge_tensor(out, "out")
+    if u.numel() != v.numel():
+        raise ValueError("u and v differ in length")
+    if out.numel() < n:
+        raise ValueError("out is shorter than n")
+    opts = (options or Options())._c()
+    st = _CStats()
+    import torch
+    with torch.cuda.device(u.device):
+        rc = load().cc_labels_noalloc(int(n), u.data_ptr(), v.data_ptr(), u.numel(),
+                                      out.data_ptr(), ctypes.byref(opts), _stream_handle(stream),
+                                      ctypes.byref(st))
     _check(rc)
     if return_stats:
         return out, {f: getattr(st, f) for f, _ in _CStats._fields_ if f != "reserved"}

@@ -30,6 +30,13 @@ size_t cc_workspace_bytes(int32_t n, int64_t m, const cc_options* opts) {
     return workspace_bytes_impl(n, m, opts);
 }
 
+int32_t cc_labels_noalloc(int32_t n, const int32_t* edges_u, const int32_t* edges_v, int64_t m,
+                          int32_t* out_label, const cc_options* opts, void* stream,
+                          cc_stats* stats) {
+    return labels_noalloc_impl(n, edges_u, edges_v, m, out_label, opts,
+                               static_cast<hipStream_t>(stream), stats);
+}
+
 int32_t cc_labels_batch(int32_t num_graphs, const int64_t* vtx_off, const int64_t* edge_off,
                         const int32_t* edges_u, const int32_t* edges_v, int32_t* out_label) {
     return batch_impl(num_graphs, vtx_off, edge_off, edges_u, edges_v, out_label, nullptr, nullptr,

@@ -625,9 +625,8 @@ int32_t enqueue_hybrid(int32_t n, const int32_t* u, const int32_t* v, int64_t m,
 
 int32_t solve_plain(int32_t n, const int32_t* u, const int32_t* v, int64_t m, int32_t* pi,
                     const Plan& p, char* ws, const Layout& L, hipStream_t s, PoolEntry* pe,
-                    bool use_graph, Timer& tm, cc_stats* st, int64_t* rounds_run) {
+                    Ctrl* hctrl, bool use_graph, Timer& tm, cc_stats* st, int64_t* rounds_run) {
     Ctrl* ctrl = reinterpret_cast<Ctrl*>(ws);
-    Ctrl* hctrl = pe->host_ctrl;
     int2* F0 = reinterpret_cast<int2*>(ws + L.f0);
     int2* F1 = reinterpret_cast<int2*>(ws + L.f1);
     const int grid_cap = device_cu_count() * 8;
@@ -748,6 +747,73 @@ int32_t check_args(int32_t n, const int32_t* u, const int32_t* v, int64_t m, con
     return CC_OK;
 }
 
+
+// Enqueues the solve of one graph with plan p on s into the workspace ws
+// (laid out by L) and waits for it; `hctrl` receives the control block.
+// `pe` (nullable) supplies the captured launch sequences of p.graph and the
+// status slot of p.no_sync; without it neither is used (the caller has
+// rejected both).
+int32_t run_solve(int32_t n, const int32_t* u, const int32_t* v, int64_t m, int32_t* out,
+                  const Plan& p, const Layout& L, char* ws, Ctrl* hctrl, PoolEntry* pe,
+                  hipStream_t s, cc_stats* st) {
+    int32_t rc = CC_OK;
+    Timer tm;
+    tm.on = p.profile;
+    tm.s = s;
+    int64_t rounds = 0;
+    const bool use_graph = p.graph && s != nullptr && !p.profile && pe != nullptr;
+    if (p.hook == CC_HOOK_ATOMIC || p.hook == CC_HOOK_HYBRID) {
+        // fixed launch sequences: no host read until the end
+        auto enqueue = [&](cc_stats* sx) {
+            if (p.hook == CC_HOOK_HYBRID)
+                return enqueue_hybrid(n, u, v, m, out, p, ws, L, s, tm, sx);
+            return enqueue_atomic(n, u, v, m, out, p, reinterpret_cast<Ctrl*>(ws),
+                                  filter_bufs(ws, L), s, tm, sx);
+        };
+        if (use_graph) {
+            KeyHash k;
+            k.add(n).add(m).add(u).add(v).add(out).add(ws).add(s).add(p.hook).add(p.segments)
+                .add(p.filter).add(p.filter_after).add(p.block).add(p.ept).add(p.coherent)
+                .add(p.hot).add(p.hot_slots).add(p.halve).add(p.symmetric);
+            rc = run_graph(pe, k.h, s, [&]() { return enqueue(st); });
+        } else {
+            rc = enqueue(st);
+        }
+        if (rc == CC_OK && p.no_sync && pe) {
+            rc = post_async(pe, s, reinterpret_cast<const Ctrl*>(ws));
+            if (st) st->giant_label = -1;  // not known without a synchronisation
+            return rc;
+        }
+        if (rc == CC_OK) rc = finish(s, reinterpret_cast<Ctrl*>(ws), hctrl, st);
+    } else if (p.host_loop != CC_HOST_LOOP_OFF) {
+        rc = solve_host_loop(n, u, v, m, out, p, ws, s, hctrl, tm, st);
+    } else {
+        rc = solve_plain(n, u, v, m, out, p, ws, L, s, pe, hctrl, use_graph, tm, st, &rounds);
+    }
+    if (rc != CC_OK && rc != CC_ERR_NOCONVERGE) return rc;
+    const Ctrl& c = *hctrl;
+    tm.collect(st);
+    if (st) {
+        st->filter_used = (p.filter == CC_FILTER_GIANT && c.filter_on) ? 1 : 0;
+        st->giant_label = st->filter_used ? c.giant : -1;
+        if (p.hook == CC_HOOK_PLAIN && p.host_loop == CC_HOST_LOOP_OFF) {
+            st->rounds = c.rounds;
+            st->active_edges = c.active_round1;
+        }
+    }
+    if (c.status & kStatusRange) return fail(CC_ERR_RANGE, "edge endpoint outside [0, n)");
+    if (c.status & kStatusOverflow) return fail(CC_ERR_NOMEM, "frontier capacity exceeded");
+    return rc;
+}
+
+void init_stats(cc_stats* st, const Plan& p) {
+    if (!st) return;
+    std::memset(st, 0, sizeof *st);
+    st->hook = p.hook;
+    st->segments = p.hook == CC_HOOK_ATOMIC ? p.segments : 0;
+    st->giant_label = -1;
+}
+
 }  // namespace
 
 int32_t labels_impl(int32_t n, const int32_t* u, const int32_t* v, int64_t m, int32_t* out,
@@ -758,12 +824,7 @@ int32_t labels_impl(int32_t n, const int32_t* u, const int32_t* v, int64_t m, in
     Plan p;
     rc = make_plan(n, m, opts, p);
     if (rc != CC_OK) return rc;
-    if (st) {
-        std::memset(st, 0, sizeof *st);
-        st->hook = p.hook;
-        st->segments = p.hook == CC_HOOK_ATOMIC ? p.segments : 0;
-        st->giant_label = -1;
-    }
+    init_stats(st, p);
     if (n == 0) {
         if (m > 0) return fail(CC_ERR_RANGE, "edge endpoint outside [0, n) (n == 0)");
         return CC_OK;
@@ -783,55 +844,79 @@ int32_t labels_impl(int32_t n, const int32_t* u, const int32_t* v, int64_t m, in
         if (rc != CC_OK) return rc;
         ws = static_cast<char*>(pe->dev);
     }
-    Timer tm;
-    tm.on = p.profile;
-    tm.s = s;
-    int64_t rounds = 0;
-    if (p.hook == CC_HOOK_ATOMIC || p.hook == CC_HOOK_HYBRID) {
-        // fixed launch sequences: no host read until the end
-        auto enqueue = [&](cc_stats* sx) {
-            if (p.hook == CC_HOOK_HYBRID)
-                return enqueue_hybrid(n, u, v, m, out, p, ws, L, s, tm, sx);
-            return enqueue_atomic(n, u, v, m, out, p, reinterpret_cast<Ctrl*>(ws),
-                                  filter_bufs(ws, L), s, tm, sx);
-        };
-        if (p.graph && s != nullptr && !p.profile) {
-            KeyHash k;
-            k.add(n).add(m).add(u).add(v).add(out).add(ws).add(s).add(p.hook).add(p.segments)
-                .add(p.filter).add(p.filter_after).add(p.block).add(p.ept).add(p.coherent)
-                .add(p.hot).add(p.hot_slots).add(p.halve).add(p.symmetric);
-            rc = run_graph(pe, k.h, s, [&]() { return enqueue(st); });
-        } else {
-            rc = enqueue(st);
-        }
-        if (rc == CC_OK && p.no_sync) {
-            rc = post_async(pe, s, reinterpret_cast<const Ctrl*>(ws));
-            if (st) st->giant_label = -1;  // not known without a synchronisation
-            return rc;
-        }
-        if (rc == CC_OK) rc = finish(s, reinterpret_cast<Ctrl*>(ws), pe->host_ctrl, st);
-    } else if (p.host_loop != CC_HOST_LOOP_OFF) {
-        rc = solve_host_loop(n, u, v, m, out, p, ws, s, pe->host_ctrl, tm, st);
-    } else {
-        const bool use_graph = p.graph && s != nullptr && !p.profile;
-        rc = solve_plain(n, u, v, m, out, p, ws, L, s, pe, use_graph, tm, st, &rounds);
-    }
-    if (rc != CC_OK && rc != CC_ERR_NOCONVERGE) return rc;
-    const Ctrl& c = *pe->host_ctrl;
-    tm.collect(st);
-    if (st) {
-        st->filter_used = (p.filter == CC_FILTER_GIANT && c.filter_on) ? 1 : 0;
-        st->giant_label = st->filter_used ? c.giant : -1;
-        if (p.hook == CC_HOOK_PLAIN && p.host_loop == CC_HOST_LOOP_OFF) {
-            st->rounds = c.rounds;
-            st->active_edges = c.active_round1;
-        }
-    }
-    if (c.status & kStatusRange) return fail(CC_ERR_RANGE, "edge endpoint outside [0, n)");
-    if (c.status & kStatusOverflow) return fail(CC_ERR_NOMEM, "frontier capacity exceeded");
-    return rc;
+    return run_solve(n, u, v, m, out, p, L, ws, pe->host_ctrl, pe, s, st);
 }
 
+// ---------------------------------------------------------------------- no-allocation solve
+// cc_labels_noalloc: the solve of cc_labels_ex with its workspace taken from
+// a fixed device array instead of the pool or the caller, for callers that
+// must not allocate.  One array per device (each GPU the library runs on
+// holds its own copy until the process ends); host code reaches it only
+// through the address hipGetSymbolAddress returns for the current device.
+namespace {
+
+static __device__ __align__(256) char scratch[CC_NOALLOC_SCRATCH_BYTES];
+
+constexpr int kMaxDevices = 64;
+std::mutex g_scratch_mu[kMaxDevices];   // one call at a time per device
+char* g_scratch_ptr[kMaxDevices] = {};  // device address of `scratch`, guarded as above
+
+}  // namespace
+
+int32_t labels_noalloc_impl(int32_t n, const int32_t* u, const int32_t* v, int64_t m,
+                            int32_t* out, const cc_options* opts, hipStream_t s, cc_stats* st) {
+    int32_t rc = check_args(n, u, v, m, out);
+    if (rc != CC_OK) return rc;
+    if (opts && (opts->graph != 0 || opts->no_sync != 0 || opts->profile != 0))
+        return fail(CC_ERR_ARG, "cc_labels_noalloc: graph, no_sync and profile must be 0");
+    Plan p;
+    rc = make_plan(n, m, opts, p);
+    if (rc != CC_OK) return rc;
+    Layout L = layout(n, m, p);
+    if (L.total > (size_t)CC_NOALLOC_SCRATCH_BYTES && (!opts || opts->hook == CC_HOOK_AUTO)) {
+        // the automatic choice falls back to plans whose workspace fits: the
+        // Atomic-Hook (no frontier), then without the giant filter (256 bytes)
+        cc_options o;
+        if (opts) o = *opts;
+        else cc_options_init(&o);
+        o.hook = CC_HOOK_ATOMIC;
+        rc = make_plan(n, m, &o, p);
+        if (rc != CC_OK) return rc;
+        L = layout(n, m, p);
+        if (L.total > (size_t)CC_NOALLOC_SCRATCH_BYTES) {
+            o.filter = CC_FILTER_OFF;
+            rc = make_plan(n, m, &o, p);
+            if (rc != CC_OK) return rc;
+            L = layout(n, m, p);
+        }
+    }
+    if (L.total > (size_t)CC_NOALLOC_SCRATCH_BYTES)
+        return fail(CC_ERR_NOMEM, "cc_labels_noalloc: the plan needs " + std::to_string(L.total) +
+                                      " bytes of workspace; the fixed buffer holds " +
+                                      std::to_string((size_t)CC_NOALLOC_SCRATCH_BYTES) +
+                                      " (use cc_labels_ex, or the automatic hook)");
+    init_stats(st, p);
+    if (n == 0) {
+        if (m > 0) return fail(CC_ERR_RANGE, "edge endpoint outside [0, n) (n == 0)");
+        return CC_OK;
+    }
+    int dev = 0;
+    HIPCHK(hipGetDevice(&dev));
+    if (dev < 0 || dev >= kMaxDevices) return fail(CC_ERR_ARG, "device index out of range");
+    std::lock_guard<std::mutex> lk(g_scratch_mu[dev]);
+    if (!g_scratch_ptr[dev]) {
+        void* ptr = nullptr;
+        HIPCHK(hipGetSymbolAddress(&ptr, HIP_SYMBOL(scratch)));
+        if (!ptr || ((uintptr_t)ptr & 255))
+            return fail(CC_ERR_HIP, "cc_labels_noalloc: unusable address of the fixed buffer");
+        g_scratch_ptr[dev] = static_cast<char*>(ptr);
+    }
+    // every kernel of the solve writes the workspace words it reads (the
+    // control block is reset by the init kernel), so the previous call's
+    // contents need no clearing
+    Ctrl hctrl;
+    return run_solve(n, u, v, m, out, p, L, g_scratch_ptr[dev], &hctrl, nullptr, s, st);
+}
 
 // ---------------------------------------------------------------------- streamed solve
 // Edges in host memory, larger than one wants to (or can) hold in HBM.  The

@@ -19,6 +19,9 @@ int32_t labels_impl(int32_t n, const int32_t* u, const int32_t* v, int64_t m, in
                     const cc_options* opts, void* workspace, size_t ws_bytes, hipStream_t s,
                     cc_stats* st);
 size_t workspace_bytes_impl(int32_t n, int64_t m, const cc_options* opts);
+// The same solve with the workspace in a fixed device array (cc_labels_noalloc).
+int32_t labels_noalloc_impl(int32_t n, const int32_t* u, const int32_t* v, int64_t m,
+                            int32_t* out, const cc_options* opts, hipStream_t s, cc_stats* st);
 
 // Independent graphs given by descriptors (device arrays); synchronous on s.
 // opts (nullable): `segments` (per-graph segment cap of the LDS solver),

@@ -362,10 +362,16 @@ int32_t cc_labels_list(int32_t count, const cc_graph* graphs, const cc_options* 
 /* ------------------------------------------------------------------ serving */
 
 /* A continuous-batching request server.  Requests (one graph each) are
- * admitted in arrival order while they fit a device arena of
- * cfg->device_bytes (footprint: 8m bytes of edges if CC_REQ_HOST_EDGES, 4n
- * bytes of labels if CC_REQ_HOST_LABELS, 256-byte granules; requests whose
- * arrays are already on the device take no arena space).  Each of
+ * admitted in arrival order while their HBM footprints fit a budget of
+ * cfg->device_bytes.  A request's footprint is 8m bytes of edges, 4n bytes of
+ * labels and the device workspace of its solve (256-byte granules), charged
+ * whether its arrays are in host or device memory: a request of more than
+ * CC_BATCH_LDS_MAX_N vertices brings its own Atomic-Hook workspace (bitmap
+ * and vertex table of the giant filter), small requests share a fixed block
+ * per worker, charged once at creation.  The server allocates one device
+ * arena of cfg->device_bytes and carves from it everything it puts on the
+ * device: copies of host edges and labels, and the workspaces, so the solves
+ * of admitted requests never allocate.  Each of
  * cfg->workers host threads owns one HIP stream and, whenever it is free,
  * solves a wave taken from the head of the queue in arrival order (the
  * cc_labels_list solvers): the longest run of admitted small requests (at
@@ -380,7 +386,8 @@ int32_t cc_labels_list(int32_t count, const cc_graph* graphs, const cc_options* 
 typedef struct cc_server cc_server;
 
 typedef struct cc_server_config {
-    int64_t device_bytes;    /* arena size; 0 = a quarter of the free device memory     */
+    int64_t device_bytes;    /* footprint budget and arena size; 0 = a quarter of the
+                                free device memory                                       */
     int32_t workers;         /* worker threads / streams, 1..16; 0 = 2                  */
     int32_t max_batch;       /* most requests in one wave; 0 = 1024                      */
     int64_t max_batch_edges; /* most edge entries in one wave (a larger single request
@@ -392,7 +399,7 @@ typedef struct cc_request_info {
     int32_t status;          /* CC_OK or the request's error code                        */
     int32_t batch_size;      /* requests in the wave that solved it                      */
     double t_submit;         /* cc_server_submit called                                  */
-    double t_admit;          /* arena space granted                                      */
+    double t_admit;          /* admitted: footprint charged, arena space granted         */
     double t_launch;         /* its wave started                                         */
     double t_device_done;    /* labels complete in device memory                         */
     double t_host_done;      /* labels copied back (== t_device_done without
@@ -400,12 +407,25 @@ typedef struct cc_request_info {
 } cc_request_info;
 
 /* Creates a server on the current device.  Returns CC_OK, CC_ERR_ARG,
- * CC_ERR_NOMEM or CC_ERR_HIP; *out is NULL on failure. */
+ * CC_ERR_NOMEM (also when device_bytes cannot hold the workers' fixed
+ * workspace) or CC_ERR_HIP; *out is NULL on failure. */
 int32_t cc_server_create(const cc_server_config* cfg, cc_server** out);
 
 /* Queues one request.  Pointers follow `flags` ([host] or [device]) and must
- * stay valid until the request is finished (cc_server_wait / poll).  A request
- * larger than the arena finishes with CC_ERR_NOMEM.  *ticket identifies it. */
+ * stay valid until the request is finished (cc_server_wait / poll).  Device
+ * arrays are read (edges) and written (out_label) on a worker's stream, which
+ * first waits for everything queued on `ready_stream` (hipStream_t of the
+ * server's device; NULL = the null stream) at the time of this call: the work
+ * that produces the edges, and earlier users of out_label's memory, may still
+ * be running on that stream.  A request whose footprint exceeds the budget
+ * left after the workers' fixed workspace finishes with CC_ERR_NOMEM; one
+ * that fits waits in the queue until enough earlier requests have finished.
+ * *ticket identifies it. */
+int32_t cc_server_submit_on(cc_server* server, int32_t n, const int32_t* edges_u,
+                            const int32_t* edges_v, int64_t m, int32_t* out_label, int32_t flags,
+                            void* ready_stream, int64_t* ticket);
+
+/* cc_server_submit_on with ready_stream = NULL (the null stream). */
 int32_t cc_server_submit(cc_server* server, int32_t n, const int32_t* edges_u,
                          const int32_t* edges_v, int64_t m, int32_t* out_label, int32_t flags,
                          int64_t* ticket);
@@ -418,7 +438,9 @@ int32_t cc_server_wait(cc_server* server, int64_t ticket, cc_request_info* info)
  * the request is still queued or running. */
 int32_t cc_server_poll(cc_server* server, int64_t ticket, cc_request_info* info);
 
-/* Requests waiting for admission and arena bytes in use (either may be NULL). */
+/* Requests waiting for admission, and footprint bytes charged against the
+ * budget (admitted, unfinished requests plus the workers' fixed workspace);
+ * either pointer may be NULL. */
 int32_t cc_server_stats(cc_server* server, int64_t* pending, int64_t* arena_used);
 
 /* Finishes every queued request, stops the workers and frees the arena. */

@@ -39,7 +39,7 @@ _HOST_LOOPS = {"off": 0, "jump": 1, "multijump": 2}
 EXPORTS = ("cc_options_init", "cc_labels", "cc_labels_ex", "cc_workspace_bytes", "cc_labels_noalloc",
            "cc_labels_batch", "cc_labels_batch_ex", "cc_labels_list", "cc_labels_host", "cc_labels_csr", "cc_probe",
            "cc_last_error", "cc_release", "cc_version", "cc_stream_status", "cc_server_create",
-           "cc_server_submit", "cc_server_wait", "cc_server_poll", "cc_server_stats",
+           "cc_server_submit", "cc_server_submit_on", "cc_server_wait", "cc_server_poll", "cc_server_stats",
            "cc_server_destroy", "cc_server_clock")
 CC_REQ_HOST_EDGES = 1
 CC_REQ_HOST_LABELS = 2
@@ -178,6 +178,9 @@ def load():
             lib.cc_server_submit.argtypes = [_vp, _i32, _vp, _vp, _i64, _vp, _i32,
                                              ctypes.POINTER(_i64)]
             lib.cc_server_submit.restype = _i32
+            lib.cc_server_submit_on.argtypes = [_vp, _i32, _vp, _vp, _i64, _vp, _i32, _vp,
+                                                ctypes.POINTER(_i64)]
+            lib.cc_server_submit_on.restype = _i32
             lib.cc_server_wait.argtypes = [_vp, _i64, ctypes.POINTER(_CRequestInfo)]
             lib.cc_server_wait.restype = _i32
             lib.cc_server_poll.argtypes = [_vp, _i64, ctypes.POINTER(_CRequestInfo)]
@@ -476,9 +479,13 @@ class Server:
     def clock() -> float:
         return float(load().cc_server_clock())
 
-    def submit(self, u, v, n: int, out=None) -> int:
+    def submit(self, u, v, n: int, out=None, stream=None) -> int:
+        """Queues one request.  Device tensors are read and written on a worker
+        stream after the work queued so far on ``stream`` (default: the current
+        torch stream), which may still be producing them."""
         import numpy as np
         import torch
+        ready = None
         if isinstance(u, torch.Tensor):
             u = _edge_tensor(u, "u")
             v = _edge_tensor(v, "v")
@@ -486,6 +493,7 @@ class Server:
                 out = torch.empty(max(int(n), 0), dtype=torch.int32, device=u.device)
             flags = 0
             up, vp, op = u.data_ptr(), v.data_ptr(), out.data_ptr()
+            ready = _stream_handle(stream)
         else:
             u = np.ascontiguousarray(u, dtype=np.int32)
             v = np.ascontiguousarray(v, dtype=np.int32)
@@ -496,9 +504,9 @@ class Server:
         if len(u) != len(v):
             raise ValueError("u and v differ in length")
         t = ctypes.c_int64()
-        _check(load().cc_server_submit(self._h, int(n), up if len(u) else None,
-                                       vp if len(v) else None, len(u), op if n else None, flags,
-                                       ctypes.byref(t)))
+        _check(load().cc_server_submit_on(self._h, int(n), up if len(u) else None,
+                                          vp if len(v) else None, len(u), op if n else None,
+                                          flags, ready, ctypes.byref(t)))
         self._keep[t.value] = (u, v, out)
         return t.value
 

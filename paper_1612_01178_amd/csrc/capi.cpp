@@ -52,7 +52,8 @@ int32_t cc_labels_batch_ex(int32_t num_graphs, const int64_t* vtx_off, const int
 
 int32_t cc_labels_list(int32_t count, const cc_graph* graphs, const cc_options* opts, void* stream,
                        cc_stats* stats) {
-    return list_impl(count, graphs, opts, static_cast<hipStream_t>(stream), stats);
+    return list_impl(count, graphs, opts, static_cast<hipStream_t>(stream), stats, nullptr, 0,
+                     nullptr);
 }
 
 int32_t cc_labels_host(int32_t n, const int32_t* host_u, const int32_t* host_v, int64_t m,

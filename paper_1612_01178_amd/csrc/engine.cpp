@@ -1150,7 +1150,8 @@ size_t workspace_bytes_impl(int32_t n, int64_t m, const cc_options* opts) {
 // Atomic-Hook solve with its own control block.  Everything is enqueued on `s`
 // and the call ends with one synchronisation and one read of all control blocks.
 int32_t list_impl(int32_t count, const cc_graph* graphs, const cc_options* opts, hipStream_t s,
-                  cc_stats* st) {
+                  cc_stats* st, void* workspace, size_t ws_bytes, size_t* ws_needed) {
+    if (ws_needed) *ws_needed = 0;
     if (count < 0) return fail(CC_ERR_ARG, "graph count < 0");
     if (opts && opts->no_sync)
         return fail(CC_ERR_ARG, "cc_options.no_sync is for cc_labels_ex and cc_labels_csr only");
@@ -1229,18 +1230,28 @@ int32_t list_impl(int32_t count, const cc_graph* graphs, const cc_options* opts,
         region_off[i] = off;
         off += align256(layouts[i].total);
     }
+    if (ws_needed) {  // size query only
+        *ws_needed = off;
+        return CC_OK;
+    }
+    if (workspace) {
+        if (ws_bytes < off) return fail(CC_ERR_NOMEM, "graph-list workspace too small");
+        if ((uintptr_t)workspace & 255) return fail(CC_ERR_ARG, "workspace must be 256-byte aligned");
+    }
     if (ns > 0) HIPCHK(prepare_batch_lds());
     PoolEntry* pe = pool_entry(s);
     std::lock_guard<std::mutex> lk(pe->mu);
     int32_t rc = ensure_host(pe, 1 + nl);
     if (rc != CC_OK) return rc;
-    rc = ensure_dev(pe, off);
-    if (rc != CC_OK) return rc;
+    if (!workspace) {
+        rc = ensure_dev(pe, off);
+        if (rc != CC_OK) return rc;
+    }
     if (ns > 0) {
         rc = ensure_stage(pe, desc_bytes + order_bytes);
         if (rc != CC_OK) return rc;
     }
-    char* ws = static_cast<char*>(pe->dev);
+    char* ws = workspace ? static_cast<char*>(workspace) : static_cast<char*>(pe->dev);
     Ctrl* ctrls = reinterpret_cast<Ctrl*>(ws);
     if (ns > 0) {
         GraphDesc* hd = static_cast<GraphDesc*>(pe->host_stage);
@@ -1343,7 +1354,7 @@ int32_t batch_impl(int32_t B, const int64_t* vo, const int64_t* eo, const int32_
         G.n = (int32_t)(vo[g + 1] - vo[g]);
         G.reserved = 0;
     }
-    return list_impl(B, list.data(), opts, s, st);
+    return list_impl(B, list.data(), opts, s, st, nullptr, 0, nullptr);
 }
 
 // ---------------------------------------------------------------------- probes, release

@@ -25,9 +25,13 @@ int32_t labels_noalloc_impl(int32_t n, const int32_t* u, const int32_t* v, int64
 
 // Independent graphs given by descriptors (device arrays); synchronous on s.
 // opts (nullable): `segments` (per-graph segment cap of the LDS solver),
-// `path_halving` (in the LDS climb) and `graph` are used.
+// `path_halving` (in the LDS climb) and `graph` are used.  `workspace`
+// (nullable, 256-byte aligned device memory of ws_bytes) replaces the
+// stream's pool; with `ws_needed` non-null nothing runs and the workspace
+// size the call needs is stored there.
 int32_t list_impl(int32_t count, const cc_graph* graphs, const cc_options* opts, hipStream_t s,
-                  cc_stats* st);
+                  cc_stats* st, void* workspace = nullptr, size_t ws_bytes = 0,
+                  size_t* ws_needed = nullptr);
 // Graphs packed back to back with host offsets; synchronous on s.
 int32_t batch_impl(int32_t B, const int64_t* vo, const int64_t* eo, const int32_t* u,
                    const int32_t* v, int32_t* out, const cc_options* opts, hipStream_t s,

@@ -19,18 +19,26 @@ def test_more_than_one_gpu_is_refused():
 
 
 def test_traffic_record_lookup(tmp_path, monkeypatch):
-    # no record for other workloads or kernels: traffic is null
-    assert bench.measured_traffic("grid4k", "atomic") is None
+    # no record for other kernels: traffic is null
     assert bench.measured_traffic("rmat24", "plain") is None
-    # a record is used only while the sources it names still hash to its value
-    src = tmp_path / "k.hip"
-    src.write_text("kernel source\n")
+    # a record is used only while the kernel and engine sources still hash to
+    # its value, and only if it names exactly those sources
+    for f in bench.COUNTER_SOURCES:
+        p = tmp_path / f
+        p.parent.mkdir(parents=True, exist_ok=True)
+        p.write_text("source of %s\n" % f)
+    monkeypatch.setattr(bench, "ROOT", str(tmp_path))
     prof = tmp_path / "profiles"
     prof.mkdir()
-    h = hashlib.sha256(src.read_bytes()).hexdigest()[:16]
-    rec = {"sources": ["k.hip"], "sources_sha256_16": h, "traffic_bytes_per_solve": 123.0}
+    rec = {"sources": list(bench.COUNTER_SOURCES), "sources_sha256_16": bench.sources_hash(),
+           "traffic_bytes_per_solve": 123.0}
     (prof / "toy_ahook_counters.md").write_text("text\n```json\n%s\n```\n" % json.dumps(rec))
-    monkeypatch.setattr(bench, "ROOT", str(tmp_path))
     assert bench.measured_traffic("toy", "atomic") == 123.0
-    src.write_text("kernel source, changed\n")
+    assert bench.measured_traffic("other", "atomic") is None
+    # a plan change in the engine makes the record stale
+    (tmp_path / "paper_1612_01178_amd/csrc/engine.cpp").write_text("engine, changed\n")
+    assert bench.measured_traffic("toy", "atomic") is None
+    # a record that leaves the engine out is never used
+    rec2 = dict(rec, sources=list(bench.COUNTER_SOURCES[:-1]), sources_sha256_16=bench.sources_hash())
+    (prof / "toy_ahook_counters.md").write_text("text\n```json\n%s\n```\n" % json.dumps(rec2))
     assert bench.measured_traffic("toy", "atomic") is None

@@ -2,6 +2,9 @@
 request's labels equal the CPU oracle's and the same request solved alone,
 whatever it was batched with; admission by device footprint queues work
 instead of failing; errors stay with the request that caused them."""
+import hashlib
+import json
+import os
 import sys
 
 import numpy as np
@@ -9,6 +12,7 @@ import pytest
 
 import graphgen
 import oracle
+from tests.golden import cases
 
 torch = pytest.importorskip("torch")
 import paper_1612_01178_amd as cc  # noqa: E402
@@ -79,9 +83,11 @@ def test_server_host_requests_queue_on_small_arena(dev):
     arena = biggest * 2 + 4096
     with cc.Server(device_bytes=arena, workers=2) as srv:
         say("server: host requests, arena", arena)
+        fixed = srv.stats()["arena_used"]  # the workers' own workspace blocks
+        assert 0 < fixed < 1 << 20
         tickets = [srv.submit(u, v, n) for u, v, n in reqs]
         results = [srv.wait(t) for t in tickets]
-        assert srv.stats()["arena_used"] == 0
+        assert srv.stats()["arena_used"] == fixed
     for (u, v, n), (lab, info) in zip(reqs, results):
         assert info["status"] == 0 and info["t_host_done"] >= info["t_device_done"]
         assert np.array_equal(lab, oracle.labels(u, v, n))
@@ -140,3 +146,108 @@ def test_concurrent_calls_from_host_threads(dev):
     assert not errors, errors
     for i in range(len(reqs)):
         assert np.array_equal(results[i], want[i])
+
+
+SERVING_GOLDEN = os.path.join(os.path.dirname(os.path.abspath(__file__)), "golden",
+                              "serving_digests.json")
+
+
+def _digest(lab):
+    return hashlib.sha256(np.ascontiguousarray(lab, dtype="<i4").tobytes()).hexdigest()
+
+
+def _mix_requests():
+    gold = json.load(open(SERVING_GOLDEN))["mix"]
+    spec = cases.serving_mix()
+    assert [(r["index"], r["scale"], r["edge_factor"]) for r in gold["requests"]] == spec
+    reqs = []
+    for (i, sc, ef), rec in zip(spec, gold["requests"]):
+        u, v, n = graphgen.serving_request(i, sc, ef, seed=cases.SERVING_MIX_SEED)
+        assert (n, len(u)) == (rec["n"], rec["m"])
+        reqs.append((u, v, n, rec["sha256"]))
+    return reqs
+
+
+def test_server_at_serving_sizes_matches_oracle_and_solo(dev):
+    """The serving workload's sizes: requests at R-MAT scale 19-22 with edge
+    factor 21-32 (up to 2^27 entries: the large-request path, several at once
+    on 3 worker streams) mixed with small ones, half with device-resident
+    arrays and half with host arrays; every result equals the oracle's
+    (digest) and the same request solved alone."""
+    say("serving mix: generating")
+    reqs = _mix_requests()
+    say("serving mix:", len(reqs), "requests,", sum(len(r[0]) for r in reqs), "entries")
+    dreqs = {}
+    for k, (u, v, n, _) in enumerate(reqs):
+        if k % 2 == 0:
+            dreqs[k] = (torch.from_numpy(u).to(dev), torch.from_numpy(v).to(dev))
+    with cc.Server(workers=3, max_batch=64) as srv:
+        tickets = []
+        for k, (u, v, n, _) in enumerate(reqs):
+            tickets.append(srv.submit(*dreqs[k], n) if k in dreqs else srv.submit(u, v, n))
+        results = [srv.wait(t) for t in tickets]
+    spans = []
+    for k, ((u, v, n, sha), (lab, info)) in enumerate(zip(reqs, results)):
+        assert info["status"] == 0
+        got = lab.cpu().numpy() if k in dreqs else lab
+        assert _digest(got) == sha, ("request", k, n, len(u))
+        du, dv = dreqs[k] if k in dreqs else (torch.from_numpy(u).to(dev), torch.from_numpy(v).to(dev))
+        assert np.array_equal(cc.labels(du, dv, n).cpu().numpy(), got), ("solo", k)
+        if n > cc.CC_BATCH_LDS_MAX_N:
+            spans.append((info["t_launch"], info["t_device_done"]))
+    overlaps = sum(1 for i, a in enumerate(spans) for b in spans[i + 1:]
+                   if a[0] < b[1] and b[0] < a[1])
+    say("serving mix: large requests whose solves overlapped in time (pairs):", overlaps)
+
+
+def test_server_budget_queues_large_requests(dev):
+    """A 1 GiB footprint budget: four large requests (8m + 4n + workspace of
+    150-500 MB each, 1.24 GB together) cannot all be admitted at once, so
+    the later ones wait for earlier ones to finish instead of failing; a
+    request whose footprint exceeds the budget fails with CC_ERR_NOMEM."""
+    reqs = _mix_requests()
+    pick = [1, 5, 2, 3]  # scale/ef (21, 28), (21, 22), (20, 21), (19, 30)
+    tens = {k: (torch.from_numpy(reqs[k][0]).to(dev), torch.from_numpy(reqs[k][1]).to(dev))
+            for k in pick + [0]}
+    with cc.Server(device_bytes=1 << 30, workers=3) as srv:
+        say("budget test: submitting", pick)
+        tickets = [srv.submit(*tens[k], reqs[k][2]) for k in pick]
+        too_big = srv.submit(*tens[0], reqs[0][2])  # (22, 32): 8m alone is 1.07 GB
+        results = [srv.wait(t) for t in tickets]
+        with pytest.raises(cc.CCError) as ei:
+            srv.wait(too_big)
+        assert ei.value.code == cc.CC_ERR_NOMEM
+    infos = [info for _, info in results]
+    for k, (lab, info) in zip(pick, results):
+        assert info["status"] == 0
+        assert _digest(lab.cpu().numpy()) == reqs[k][3]
+    # some request was admitted only after another one had finished
+    first_done = min(i["t_device_done"] for i in infos)
+    assert max(i["t_admit"] for i in infos) >= first_done
+
+
+def test_server_waits_for_the_producer_stream(dev):
+    """Edges written by work still queued on a side stream when the request
+    is submitted: the worker's stream waits for that point of the side
+    stream before reading them."""
+    u, v, n = graphgen.rmat(16, 8, seed=4141)
+    want = oracle.labels(u, v, n)
+    src_u = torch.from_numpy(u).to(dev)
+    src_v = torch.from_numpy(v).to(dev)
+    du = torch.zeros_like(src_u)  # all-(0, 0) edges until the copies land
+    dv = torch.zeros_like(src_v)
+    torch.cuda.synchronize()
+    side = torch.cuda.Stream()
+    with cc.Server(workers=2) as srv:
+        with torch.cuda.stream(side):
+            a = torch.randn(4096, 4096, device=dev)
+            for _ in range(30):  # tens of ms of queued work ahead of the copies
+                a = a @ a
+                a = a / a.norm()
+            du.copy_(src_u)
+            dv.copy_(src_v)
+            t = srv.submit(du, dv, n, stream=side)
+        lab, info = srv.wait(t)
+        side.synchronize()
+    assert info["status"] == 0
+    assert np.array_equal(lab.cpu().numpy(), want)

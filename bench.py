@@ -573,7 +573,8 @@ def probe_ceilings(cc, torch, u, v, n, m, reps=5):
     out = {}
     for mode, name, tab in ((0, "stream", None), (1, "stream+gather", table),
                             (2, "stream+bitmap", bits), (3, "stream+bitmap_nt", bits),
-                            (4, "stream+bitmap_agent", bits)):
+                            (4, "stream+bitmap_agent", bits), (5, "stream+cas_agent", table),
+                            (6, "stream+cas_agent_failing", table)):
         cc.probe(mode, u, v, tab, n)
         torch.cuda.synchronize()
         s0, s1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)

@@ -456,9 +456,12 @@ double cc_server_clock(void);
  * kernels and, for mode 1, also gathers table[u] and table[v] from the
  * [device] int32[n] array `table`, or, for modes 2-4, tests bits u and v of
  * the [device] n-bit bitmap `table` (uint32 words) with cached loads (2),
- * non-temporal loads (3) or agent-scope atomic loads (4).  Entries with an
- * endpoint outside [0, n) are skipped by modes 1-4.  Asynchronous on
- * `stream`.  Returns CC_OK, CC_ERR_ARG or CC_ERR_HIP. */
+ * non-temporal loads (3) or agent-scope atomic loads (4), or, for modes 5
+ * and 6, makes one agent-scope compare-and-swap on table[u] per entry that
+ * succeeds (5: swaps u for u) or fails (6: expects -1); `table` must then
+ * hold table[x] = x and is left unchanged (the hooking atomic's ceiling).
+ * Entries with an endpoint outside [0, n) are skipped by modes 1-6.
+ * Asynchronous on `stream`.  Returns CC_OK, CC_ERR_ARG or CC_ERR_HIP. */
 int32_t cc_probe(int32_t mode, const int32_t* edges_u, const int32_t* edges_v, int64_t m,
                  const void* table, int32_t n, void* stream);
 

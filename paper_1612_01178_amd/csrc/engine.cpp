@@ -1360,7 +1360,7 @@ int32_t batch_impl(int32_t B, const int64_t* vo, const int64_t* eo, const int32_
 // ---------------------------------------------------------------------- probes, release
 int32_t probe_impl(int32_t mode, const int32_t* u, const int32_t* v, int64_t m, const void* table,
                    int32_t n, hipStream_t s) {
-    if (m < 0 || mode < 0 || mode > 4) return fail(CC_ERR_ARG, "bad probe arguments");
+    if (m < 0 || mode < 0 || mode > 6) return fail(CC_ERR_ARG, "bad probe arguments");
     if (m > 0 && (!u || !v)) return fail(CC_ERR_ARG, "null edge array");
     if (mode > 0 && (!table || n <= 0)) return fail(CC_ERR_ARG, "probe table required");
     if (((uintptr_t)u & 15) || ((uintptr_t)v & 15))
@@ -1374,6 +1374,9 @@ int32_t probe_impl(int32_t mode, const int32_t* u, const int32_t* v, int64_t m, 
         HIPCHK(launch_probe_stream(u, v, m, sink, s));
     else if (mode == 1)
         HIPCHK(launch_probe_gather(u, v, m, static_cast<const int32_t*>(table), n, sink, s));
+    else if (mode >= 5)
+        HIPCHK(launch_probe_cas(u, v, m, static_cast<int32_t*>(const_cast<void*>(table)), n,
+                                mode == 6, sink, s));
     else
         HIPCHK(launch_probe_bitgather(u, v, m, static_cast<const uint32_t*>(table), n, mode - 2,
                                       sink, s));

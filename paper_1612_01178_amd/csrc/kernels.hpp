@@ -139,6 +139,10 @@ hipError_t launch_probe_stream(const int32_t* u, const int32_t* v, int64_t m, ui
                                hipStream_t s);
 hipError_t launch_probe_gather(const int32_t* u, const int32_t* v, int64_t m, const int32_t* table,
                                int32_t n, uint32_t* sink, hipStream_t s);
+// Stream + one agent-scope compare-and-swap per entry on table[u] (table
+// must hold table[x] = x; it is left unchanged): succeeding or failing form.
+hipError_t launch_probe_cas(const int32_t* u, const int32_t* v, int64_t m, int32_t* table,
+                            int32_t n, bool fail, uint32_t* sink, hipStream_t s);
 hipError_t launch_probe_bitgather(const int32_t* u, const int32_t* v, int64_t m,
                                   const uint32_t* bits, int32_t n, int variant, uint32_t* sink,
                                   hipStream_t s);

@@ -1,8 +1,12 @@
 // Memory-ceiling probes: the edge stream alone, the stream plus two random
 // 4-byte gathers of an n-entry table per entry (the tree-array access
-// pattern of a hook pass), and the stream plus two bit lookups in an n-bit
-// bitmap.  Each folds what it read into one word so nothing is optimised
-// away.  Same tiling as the hook kernels: 16 entries per thread, 256 threads.
+// pattern of a hook pass), the stream plus two bit lookups in an n-bit
+// bitmap, and the stream plus one agent-scope compare-and-swap per entry on
+// a random table slot (the hooking atomic; the table must hold t[x] = x: the
+// succeeding form swaps x for x, the failing form expects -1, so the table
+// never changes).  Each folds what it read into one word so nothing is
+// optimised away.  Same tiling as the hook kernels: 16 entries per thread,
+// 256 threads.
 #include "kernels.hpp"
 
 namespace hookcc {
@@ -54,11 +58,20 @@ __global__ __launch_bounds__(256) void k_probe(const int32_t* __restrict__ eu,
                       ? ((__builtin_nontemporal_load(bits + (x >> 5)) >> (x & 31)) & 1u) |
                             (((__builtin_nontemporal_load(bits + (y >> 5)) >> (y & 31)) & 1u) << 1)
                       : 0u;
-        } else {  // bitmap words read as agent-scope atomics (past the L1)
+        } else if (MODE == 4) {  // bitmap words read as agent-scope atomics (past the L1)
             val = (x < (uint32_t)n && y < (uint32_t)n)
                       ? ((__hip_atomic_load(bits + (x >> 5), __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) >> (x & 31)) & 1u) |
                             (((__hip_atomic_load(bits + (y >> 5), __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) >> (y & 31)) & 1u) << 1)
                       : 0u;
+        } else {  // one agent-scope CAS on slot x: 5 succeeds (x -> x), 6 fails (expects -1)
+            val = 0;
+            if (x < (uint32_t)n) {
+                int32_t expected = MODE == 5 ? (int32_t)x : -1;
+                __hip_atomic_compare_exchange_strong(const_cast<int32_t*>(table) + x, &expected,
+                                                     (int32_t)x, __ATOMIC_RELAXED, __ATOMIC_RELAXED,
+                                                     __HIP_MEMORY_SCOPE_AGENT);
+                val = (uint32_t)expected + y;
+            }
         }
         acc = ((acc << 5) | (acc >> 27)) ^ val;  // rotate-xor: every value matters
     }
@@ -77,7 +90,9 @@ static hipError_t probe(int mode, const int32_t* u, const int32_t* v, int64_t m,
         case 1: k_probe<1><<<grid, 256, 0, s>>>(u, v, m, table, bits, n, sink); break;
         case 2: k_probe<2><<<grid, 256, 0, s>>>(u, v, m, table, bits, n, sink); break;
         case 3: k_probe<3><<<grid, 256, 0, s>>>(u, v, m, table, bits, n, sink); break;
-        default: k_probe<4><<<grid, 256, 0, s>>>(u, v, m, table, bits, n, sink); break;
+        case 4: k_probe<4><<<grid, 256, 0, s>>>(u, v, m, table, bits, n, sink); break;
+        case 5: k_probe<5><<<grid, 256, 0, s>>>(u, v, m, table, bits, n, sink); break;
+        default: k_probe<6><<<grid, 256, 0, s>>>(u, v, m, table, bits, n, sink); break;
     }
     return hipGetLastError();
 }
@@ -89,6 +104,10 @@ hipError_t launch_probe_stream(const int32_t* u, const int32_t* v, int64_t m, ui
 hipError_t launch_probe_gather(const int32_t* u, const int32_t* v, int64_t m, const int32_t* table,
                                int32_t n, uint32_t* sink, hipStream_t s) {
     return probe(1, u, v, m, table, nullptr, n, sink, s);
+}
+hipError_t launch_probe_cas(const int32_t* u, const int32_t* v, int64_t m, int32_t* table,
+                            int32_t n, bool fail, uint32_t* sink, hipStream_t s) {
+    return probe(fail ? 6 : 5, u, v, m, table, nullptr, n, sink, s);
 }
 hipError_t launch_probe_bitgather(const int32_t* u, const int32_t* v, int64_t m,
                                   const uint32_t* bits, int32_t n, int variant, uint32_t* sink,

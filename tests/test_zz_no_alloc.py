@@ -63,12 +63,12 @@ def test_noalloc_filtered_then_smaller():
 
 
 def test_noalloc_fallback_then_smaller():
-    # percolated 2048^2 grid: the automatic hybrid plan needs 8 B per entry
-    # (~47 MB), more than the fixed array, so the call falls back to the
+    # percolated 3000^2 grid: the automatic hybrid plan needs 8 B per entry
+    # (~100 MB), more than the fixed array, so the call falls back to the
     # Atomic-Hook; then a smaller grid on a side stream
-    u, v, n = graphgen.grid(2048, 2048, 3, 10, seed=7103)
+    u, v, n = graphgen.grid(3000, 3000, 3, 10, seed=7103)
     assert cc.workspace_bytes(n, len(u)) > cc.CC_NOALLOC_SCRATCH_BYTES
-    print("noalloc grid2048", n, len(u), flush=True)
+    print("noalloc grid3000", n, len(u), flush=True)
     st = _pair(u, v, n, want=oracle.labels(u, v, n))
     assert st.hook == 1
     u2, v2, n2 = graphgen.grid(300, 200, 3, 10, seed=7104)
@@ -78,7 +78,7 @@ def test_noalloc_fallback_then_smaller():
 
 
 def test_noalloc_explicit_plan_too_large_and_bad_options():
-    u, v, n = graphgen.grid(1536, 1536, 3, 10, seed=7105)
+    u, v, n = graphgen.grid(2048, 2048, 3, 10, seed=7105)
     du, dv = _dev(u, v)
     out = torch.empty(n, dtype=torch.int32, device=du.device)
     plain = cc.Options(hook="plain")
@@ -89,7 +89,7 @@ def test_noalloc_explicit_plan_too_large_and_bad_options():
         rc, _ = _noalloc_raw(du, dv, n, out, bad)
         assert rc == cc.CC_ERR_ARG
     # an explicit plan that fits still runs, then a smaller one
-    print("noalloc grid1536 atomic", n, len(u), flush=True)
+    print("noalloc grid2048 atomic", n, len(u), flush=True)
     _pair(u, v, n, opts=cc.Options(hook="atomic"), want=oracle.labels(u, v, n))
     u2, v2, n2 = graphgen.rmat(12, 8, seed=7106)
     _pair(u2, v2, n2, opts=cc.Options(hook="hybrid"), want=oracle.labels(u2, v2, n2))

@@ -26,7 +26,8 @@ struct Ctrl {
     int32_t fsel[2];        // where round r's source is: frontier buffer 0 / 1, or 2 = input lists
     uint32_t fsize[2];      // round r's source size
     int32_t fwrote[2];      // 1 = round r wrote its survivors to the other buffer
-    int32_t pad[46];
+    uint32_t win_far;       // hybrid plan: entries the window round hooked outside LDS
+    int32_t pad[45];
 };
 static_assert(sizeof(Ctrl) == 256, "control block is one 256-byte line");
 

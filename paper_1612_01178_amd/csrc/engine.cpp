@@ -595,13 +595,15 @@ int32_t enqueue_atomic(int32_t n, const int32_t* u, const int32_t* v, int64_t m,
 // reading the control block after each block.  With `graph`, each block's
 // launches (block b: rounds bK+1 .. bK+K; block 0 also the init) are
 // captured once per (arrays, sizes, plan, b) and replayed.
-// Hybrid plan: one atomic-free Hook round (Fig. 2) over all entries, its
-// Multi-Jump, and the compaction of the still-active entries into root
-// pairs; then one Atomic-Hook pass with path halving (Fig. 3) over those
-// pairs and a final Multi-Jump (skipped on the device when no pair was
-// active).  Trees only merge, so an entry dropped by the compaction stays
-// satisfied; the pairs were roots when compacted, valid starting parents
-// for the climb.  A fixed launch sequence: no host read until the end.
+// Hybrid plan: one atomic-free Hook round (Fig. 2) over all entries, in
+// which each workgroup first joins its chunk of entries in an LDS window
+// (launch_hook_window), and the compaction of the entries whose endpoints
+// still have different parents into parent pairs; then one Atomic-Hook pass
+// with path halving (Fig. 3) over those pairs and a final Multi-Jump (skipped
+// on the device when no pair was active).  Trees only merge, so an entry
+// dropped by the compaction stays satisfied; the pairs are vertices of the
+// endpoints' trees, valid starting parents for the climb.  A fixed launch
+// sequence: no host read until the end.
 int32_t enqueue_hybrid(int32_t n, const int32_t* u, const int32_t* v, int64_t m, int32_t* pi,
                        const Plan& p, char* ws, const Layout& L, hipStream_t s, Timer& tm,
                        cc_stats* st) {
@@ -609,9 +611,20 @@ int32_t enqueue_hybrid(int32_t n, const int32_t* u, const int32_t* v, int64_t m,
     int2* F = reinterpret_cast<int2*>(ws + L.f0);
     const int grid_cap = device_cu_count() * 8;
     TIMED(kPhaseOther, launch_init(pi, n, ctrl, s));
-    TIMED(kPhaseHook, launch_hook_plain(1, u, v, m, F, F, pi, n, ctrl, p.block, p.ept, grid_cap, s));
-    TIMED(kPhaseCompress, launch_mj_deep(pi, n, s));  // the round leaves chains
-    // round 1 reads the input lists and writes its survivors to F, count[1]
+    // the atomic-free round, each workgroup's chunk joined in an LDS window
+    TIMED(kPhaseHook, launch_hook_window(u, v, m, pi, n, ctrl, s));
+    // The compaction compares parents, not roots.  An entry whose endpoints
+    // have equal parents is inside one tree and is dropped; one whose parents
+    // differ is kept (also when they share a root), and the Atomic-Hook climbs
+    // from that pair to the roots (every parent is a vertex of its endpoint's
+    // tree, a valid start).  When the windows held most entries, nearly every
+    // vertex already points at its chunk's local root and the extra pairs
+    // are few, so no Multi-Jump runs first (4096^2 grid: it cost 58 us, the
+    // pairs it saved far less); when more than a quarter of the entries were
+    // hooked outside the windows (inputs without locality), the plain round's
+    // chains would make most entries look active, and a Multi-Jump, gated on
+    // the device by that count, makes the trees stars first.
+    TIMED(kPhaseCompress, launch_mj1(pi, n, &ctrl->win_far, s, (uint32_t)(m / 4)));
     TIMED(kPhaseHook, launch_compact(1, u, v, m, F, F, L.cap, pi, n, ctrl, 0xffffffffu, p.block,
                                      p.ept, grid_cap, s));
     TIMED(kPhaseHook, launch_ahook_pairs(F, &ctrl->count[1], L.cap, pi, p.halve, grid_cap, s));

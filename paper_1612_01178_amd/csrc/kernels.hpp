@@ -25,8 +25,10 @@ hipError_t launch_mj(int32_t* pi, int32_t n, const uint32_t* gate, bool coherent
 // vertices in LDS, then a climb across blocks (the plain Multi-Jump for
 // n < 2^22).  Postcondition as launch_mj: every tree is a star.
 hipError_t launch_mj_deep(int32_t* pi, int32_t n, hipStream_t s);
-// Multi-Jump with one vertex per thread (atomic-free path); `gate` as launch_mj.
-hipError_t launch_mj1(int32_t* pi, int32_t n, const uint32_t* gate, hipStream_t s);
+// Multi-Jump with one vertex per thread (atomic-free path); does nothing when
+// `gate` is non-null and *gate <= limit.
+hipError_t launch_mj1(int32_t* pi, int32_t n, const uint32_t* gate, hipStream_t s,
+                      uint32_t limit = 0);
 
 // Giant-component sample: label of the component that holds the most of
 // `samples` edge endpoints drawn across entries [0, m); sets ctrl->giant and
@@ -54,6 +56,12 @@ hipError_t launch_hook_plain(int round, const int32_t* u, const int32_t* v, int6
 // Frontier compaction after the Compress of round `round`: keeps the entries
 // whose endpoints still have different roots, written as root pairs to
 // `dst` (capacity cap), size accumulated in ctrl->count[round & 1].
+// Window round of the hybrid plan: an atomic-free Hook round over all m
+// entries in which each workgroup first joins its chunk of entries inside an
+// LDS window of consecutive vertices (see kernels_batch.hip).  Range-checks
+// the entries.  Leaves pi a forest (not of stars).
+hipError_t launch_hook_window(const int32_t* u, const int32_t* v, int64_t m, int32_t* pi,
+                              int32_t n, Ctrl* ctrl, hipStream_t s);
 // Atomic-Hook with path halving of the *count root pairs of a frontier.
 hipError_t launch_ahook_pairs(const int2* fr, const uint32_t* count, int64_t cap, int32_t* pi,
                               bool halve, int grid_cap, hipStream_t s);

@@ -187,6 +187,149 @@ __global__ __launch_bounds__(1024) void k_batch_lds(const GraphDesc* __restrict_
     if (bad) atomicOr(status, kStatusRange);
 }
 
+// Window round of the hybrid plan (an atomic-free Hook round, Fig. 2, with
+// the Hook of each workgroup's chunk done in LDS; beyond the paper).
+// Workgroup w takes entries [w * kWinEntries, (w + 1) * kWinEntries) and a
+// window of kWinSlots consecutive vertices starting at the smallest endpoint
+// among the chunk's first blockDim.x entries.  Entries with both endpoints in
+// the window are joined completely in LDS (Atomic-Hook with path halving on
+// 16-bit local ids, then a Multi-Jump over the window); every other entry
+// gets the device-memory atomic-free Hook (plain store pi[max] = min of the
+// endpoints' current parents).  Then each window vertex that is not its
+// local root is pointed at it with a plain store.  The number of entries
+// hooked outside the windows is added to ctrl->win_far.
+//
+// Every value written to pi names a vertex of the slot's own component below
+// the slot (a local root, or the smaller of two parents joined by an entry),
+// so pi stays a forest of subsets of components with pi[x] <= x.  Stores of
+// different workgroups to one slot overwrite each other, which can split a
+// chunk's local component into several trees; then some entry of that chunk
+// joins two of them, and the compaction that follows the Multi-Jump keeps it
+// for the Atomic-Hook pass.  No thread of this kernel takes a root by CAS in
+// device memory, so its stores are of workgroup scope.  On inputs whose
+// consecutive entries touch nearby ids (a row-major lattice) nearly every
+// entry is joined in LDS and few survive the round; elsewhere the chunks'
+// windows hold few entries and the round is the plain one.  The sizes: a
+// chunk of a percolated 4096^2 lattice spans ~39,200 ids (within the
+// window), two workgroups fit a CU (80 KiB of LDS each), so the lattice's
+// 478 chunks run at once.
+constexpr int64_t kWinEntries = 49152;  // 1024 threads x 48 entries
+constexpr uint32_t kWinSlots = 40960;   // 16-bit local ids: 80 KiB of LDS
+constexpr int kWinSegments = 2;
+
+__global__ __launch_bounds__(1024) void k_hook_window(const int32_t* __restrict__ eu,
+                                                      const int32_t* __restrict__ ev, int64_t m,
+                                                      int32_t* pi, int32_t n, Ctrl* ctrl) {
+    extern __shared__ uint16_t spi[];
+    __shared__ int32_t wave_min[16];
+    const uint32_t tid = threadIdx.x, nthr = blockDim.x;
+    const uint32_t lane = tid & 63, wave = tid >> 6, waves = nthr >> 6;
+    const int64_t c0 = (int64_t)blockIdx.x * kWinEntries;
+    const int64_t c1 = min(m, c0 + kWinEntries);
+    int32_t lo = INT32_MAX;
+    if (c0 + tid < c1) {
+        const int32_t a = eu[c0 + tid], b = ev[c0 + tid];
+        if ((uint32_t)a < (uint32_t)n) lo = min(lo, a);
+        if ((uint32_t)b < (uint32_t)n) lo = min(lo, b);
+    }
+#pragma unroll
+    for (int d = 32; d >= 1; d >>= 1) lo = min(lo, __shfl_xor(lo, d, 64));
+    if (lane == 0) wave_min[wave] = lo;
+    uint32_t* w32 = reinterpret_cast<uint32_t*>(spi);
+    for (uint32_t w = tid; w < kWinSlots / 2; w += nthr) w32[w] = ((2 * w + 1) << 16) | (2 * w);
+    __syncthreads();
+    int32_t base = wave_min[0];
+    for (uint32_t i = 1; i < waves; ++i) base = min(base, wave_min[i]);
+    if (base == INT32_MAX) base = 0;
+    // window vertices: [base, base + span)
+    const uint32_t span = (uint32_t)min<int64_t>((int64_t)kWinSlots, (int64_t)n - base);
+    bool bad = false;
+    uint32_t far = 0;  // entries hooked outside the window
+    // The chunk in kWinSegments segments, each followed by a Multi-Jump over
+    // the window (the schedule of Fig. 4 inside the chunk) so that later
+    // climbs start from stars.  kBatchEPT entries per thread per step,
+    // consecutive threads on consecutive entries (coalesced), the next
+    // step's loads issued before this step's hooks.
+    for (int seg = 0; seg < kWinSegments; ++seg) {
+        const int64_t s0 = c0 + (c1 - c0) * seg / kWinSegments;
+        const int64_t s1 = c0 + (c1 - c0) * (seg + 1) / kWinSegments;
+        const int64_t step = (int64_t)nthr * kBatchEPT;
+        int32_t a[kBatchEPT], b[kBatchEPT], na[kBatchEPT], nb[kBatchEPT];
+        int64_t e0 = s0 + tid;
+#pragma unroll
+        for (int j = 0; j < kBatchEPT; ++j) {
+            const int64_t e = e0 + (int64_t)j * nthr;
+            a[j] = e < s1 ? __builtin_nontemporal_load(eu + e) : 0;
+            b[j] = e < s1 ? __builtin_nontemporal_load(ev + e) : 0;
+        }
+        for (; e0 < s1; e0 += step) {
+            const int64_t e1 = e0 + step;
+#pragma unroll
+            for (int j = 0; j < kBatchEPT; ++j) {
+                const int64_t e = e1 + (int64_t)j * nthr;
+                na[j] = e < s1 ? __builtin_nontemporal_load(eu + e) : 0;
+                nb[j] = e < s1 ? __builtin_nontemporal_load(ev + e) : 0;
+            }
+#pragma unroll
+            for (int j = 0; j < kBatchEPT; ++j) {
+                if (e0 + (int64_t)j * nthr >= s1) continue;
+                if ((uint32_t)a[j] >= (uint32_t)n || (uint32_t)b[j] >= (uint32_t)n) {
+                    bad = true;
+                    continue;
+                }
+                if (a[j] == b[j]) continue;
+                const uint32_t la = (uint32_t)(a[j] - base), lb = (uint32_t)(b[j] - base);
+                if (la < span && lb < span) {
+                    lds_atomic_hook(spi, lds_ld(spi, la), lds_ld(spi, lb), true);
+                } else {
+                    ++far;
+                    const int32_t pa = ld_rlx(pi + a[j]), pb = ld_rlx(pi + b[j]);
+                    if (pa != pb) st_rlx(pi + max(pa, pb), min(pa, pb));
+                }
+            }
+#pragma unroll
+            for (int j = 0; j < kBatchEPT; ++j) {
+                a[j] = na[j];
+                b[j] = nb[j];
+            }
+        }
+        __syncthreads();
+        // Multi-Jump over the window; after the last segment the local roots
+        // go to pi
+        const bool last = seg + 1 == kWinSegments;
+        for (uint32_t x = tid; x < span; x += nthr) {
+            uint32_t p = lds_ld(spi, x);
+            if (p == x) continue;
+            uint32_t g = lds_ld(spi, p);
+            while (g != p) {
+                lds_st(spi, x, g);
+                p = g;
+                g = lds_ld(spi, p);
+            }
+            if (last) st_rlx(pi + base + (int32_t)x, base + (int32_t)p);
+        }
+        __syncthreads();
+    }
+    // the workgroup's count of entries hooked outside its window
+#pragma unroll
+    for (int d = 32; d >= 1; d >>= 1) far += __shfl_xor(far, d, 64);
+    if (lane == 0 && far) atomicAdd(&ctrl->win_far, far);
+    if (bad) atomicOr(&ctrl->status, kStatusRange);
+}
+
+hipError_t launch_hook_window(const int32_t* u, const int32_t* v, int64_t m, int32_t* pi,
+                              int32_t n, Ctrl* ctrl, hipStream_t s) {
+    if (m <= 0) return hipSuccess;
+    static hipError_t once = hipFuncSetAttribute(reinterpret_cast<const void*>(&k_hook_window),
+                                                 hipFuncAttributeMaxDynamicSharedMemorySize,
+                                                 kWinSlots * 2);
+    if (once != hipSuccess) return once;
+    const int64_t grid = (m + kWinEntries - 1) / kWinEntries;
+    if (grid > 0x7fffffff) return hipErrorInvalidValue;
+    k_hook_window<<<(int)grid, 1024, kWinSlots * 2, s>>>(u, v, m, pi, n, ctrl);
+    return hipGetLastError();
+}
+
 hipError_t prepare_batch_lds() {
     // Allows up to 128 KiB of dynamic LDS; set once, outside any capture.
     static hipError_t once = hipFuncSetAttribute(reinterpret_cast<const void*>(&k_batch_lds),

@@ -346,17 +346,19 @@ __global__ __launch_bounds__(1024, 8) void k_mj_local(int32_t* pi, int32_t n) {
 // climbs one after the other (a 4096^2 grid: 0.575 -> 0.537 ms; ER 2^16
 // rounds: 0.100 -> 0.090 ms).  The Atomic-Hook path keeps k_mj, whose
 // 16-byte loads win on its shallow trees (R-MAT 24: 3.75 against 3.78 ms).
-__global__ __launch_bounds__(256) void k_mj1(int32_t* pi, int32_t n, const uint32_t* gate) {
-    if (gate != nullptr && *gate == 0) return;
-    const int64_t v = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (v >= n) return;
-    int32_t q = ld_tree<false>(pi + v);
-    if (q == v) return;
-    int32_t g = ld_tree<false>(pi + q);
-    while (g != q) {
-        st_tree<false>(pi + v, g);
-        q = g;
-        g = ld_tree<false>(pi + q);
+__global__ __launch_bounds__(256) void k_mj1(int32_t* pi, int32_t n, const uint32_t* gate,
+                                             uint32_t limit) {
+    if (gate != nullptr && *gate <= limit) return;
+    for (int64_t v = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; v < n;
+         v += (int64_t)gridDim.x * blockDim.x) {
+        int32_t q = ld_tree<false>(pi + v);
+        if (q == v) continue;
+        int32_t g = ld_tree<false>(pi + q);
+        while (g != q) {
+            st_tree<false>(pi + v, g);
+            q = g;
+            g = ld_tree<false>(pi + q);
+        }
     }
 }
 
@@ -366,13 +368,18 @@ hipError_t launch_mj_deep(int32_t* pi, int32_t n, hipStream_t s) {
     if (n < (1 << 22)) return launch_mj1(pi, n, nullptr, s);
     const int grid = (int)(((int64_t)n + kMjBlock - 1) / kMjBlock);
     k_mj_local<<<grid, 1024, 0, s>>>(pi, n);
-    k_mj1<<<(int)(((int64_t)n + 255) / 256), 256, 0, s>>>(pi, n, nullptr);
+    k_mj1<<<(int)(((int64_t)n + 255) / 256), 256, 0, s>>>(pi, n, nullptr, 0);
     return hipGetLastError();
 }
 
-hipError_t launch_mj1(int32_t* pi, int32_t n, const uint32_t* gate, hipStream_t s) {
+hipError_t launch_mj1(int32_t* pi, int32_t n, const uint32_t* gate, hipStream_t s,
+                      uint32_t limit) {
     if (n <= 0) return hipSuccess;
-    k_mj1<<<(int)(((int64_t)n + 255) / 256), 256, 0, s>>>(pi, n, gate);
+    // a gated launch may find nothing to do: a grid of at most 32 workgroups
+    // per CU, each thread striding over vertices, exits in a few microseconds
+    int64_t grid = ((int64_t)n + 255) / 256;
+    if (gate != nullptr) grid = std::min<int64_t>(grid, (int64_t)device_cu_count() * 32);
+    k_mj1<<<(int)grid, 256, 0, s>>>(pi, n, gate, limit);
     return hipGetLastError();
 }
 

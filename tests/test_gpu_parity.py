@@ -350,6 +350,34 @@ def test_full_size_workloads_match_oracle_digest(dev, name):
         assert digest(lab) == rec["sha256"], (name, opt)
 
 
+def test_window_round_with_and_without_locality(dev):
+    """The hybrid plan's window round on lattices whose entries keep, lose or
+    reverse their locality: row-major ids (nearly every entry joined in an
+    LDS window), the same lattice with permuted ids or shuffled entries
+    (nearly every entry outside the windows: the gated Multi-Jump runs), and
+    both orientations of each entry; a lattice wider than a window (rows of
+    50,000 vertices), and a graph smaller than one window."""
+    rng = np.random.default_rng(23)
+    u, v, n = graphgen.grid(1500, 1000, 3, 10, seed=231)
+    perm = rng.permutation(n).astype(np.int32)
+    order = rng.permutation(len(u))
+    wide_u, wide_v, wide_n = graphgen.grid(50000, 40, 3, 10, seed=232)
+    cases = {
+        "row-major": (u, v, n),
+        "permuted ids": (perm[u], perm[v], n),
+        "shuffled entries": (u[order], v[order], n),
+        "both orientations": (np.concatenate([u, v]), np.concatenate([v, u]), n),
+        "reversed pairs": (v, u, n),
+        "rows wider than a window": (wide_u, wide_v, wide_n),
+        "smaller than a window": (u[u < 20000] % 20000, v[u < 20000] % 20000, 20000),
+    }
+    for name, (a, b, nn) in cases.items():
+        say("window round", name, nn, len(a))
+        want = oracle.labels(a, b, nn)
+        for opt in (cc.Options(hook="hybrid"), cc.Options(hook="hybrid", path_halving="off")):
+            assert np.array_equal(solve(a, b, nn, dev, opt), want), name
+
+
 def test_repeated_solves_on_deep_trees_stay_exact(dev):
     """Regression: concurrent hooks and path-halving re-points race on the same
     cache lines from different XCDs; on the grid (deep trees, many re-points)

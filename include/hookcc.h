@@ -461,6 +461,17 @@ double cc_server_clock(void);
  * succeeds (5: swaps u for u) or fails (6: expects -1); `table` must then
  * hold table[x] = x and is left unchanged (the hooking atomic's ceiling).
  * Entries with an endpoint outside [0, n) are skipped by modes 1-6.
+ * Modes 7-11 ignore the edges and probe the memory model behind the tree
+ * array's write rule: `table` is [device] int32[n >= 128] with table[i] = i
+ * for i < 32 and table[64] = 0.  Workgroup A (one XCD) loads table[1]
+ * (modes 7-9 only), then stores table[0] = 100 with workgroup scope (7, 10),
+ * agent scope (8, 11) or not at all (9); workgroup B (another XCD) then
+ * swaps table[1] from 1 to 50 by an
+ * agent-scope compare-and-swap; A then tries to swap table[1] from 1 to 70
+ * the same way, which must fail.  table[96..97] receive the two XCD ids,
+ * table[98..99] the polls of the two bounded waits (-1 = the wait ran out),
+ * table[100] the value A loaded, table[101..102] the values A's and B's
+ * compare-and-swap found (A's == 1: it ran on a stale copy of the line).
  * Asynchronous on `stream`.  Returns CC_OK, CC_ERR_ARG or CC_ERR_HIP. */
 int32_t cc_probe(int32_t mode, const int32_t* edges_u, const int32_t* edges_v, int64_t m,
                  const void* table, int32_t n, void* stream);

@@ -1373,7 +1373,12 @@ int32_t batch_impl(int32_t B, const int64_t* vo, const int64_t* eo, const int32_
 // ---------------------------------------------------------------------- probes, release
 int32_t probe_impl(int32_t mode, const int32_t* u, const int32_t* v, int64_t m, const void* table,
                    int32_t n, hipStream_t s) {
-    if (m < 0 || mode < 0 || mode > 6) return fail(CC_ERR_ARG, "bad probe arguments");
+    if (m < 0 || mode < 0 || mode > 11) return fail(CC_ERR_ARG, "bad probe arguments");
+    if (mode >= 7) {  // memory-model probe: table is int32[128], edges unused
+        if (!table || n < 128) return fail(CC_ERR_ARG, "memory-model probe needs a 128-word table");
+        HIPCHK(launch_probe_mm(mode, static_cast<int32_t*>(const_cast<void*>(table)), s));
+        return CC_OK;
+    }
     if (m > 0 && (!u || !v)) return fail(CC_ERR_ARG, "null edge array");
     if (mode > 0 && (!table || n <= 0)) return fail(CC_ERR_ARG, "probe table required");
     if (((uintptr_t)u & 15) || ((uintptr_t)v & 15))

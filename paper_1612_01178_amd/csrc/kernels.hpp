@@ -151,6 +151,8 @@ hipError_t launch_probe_gather(const int32_t* u, const int32_t* v, int64_t m, co
 // must hold table[x] = x; it is left unchanged): succeeding or failing form.
 hipError_t launch_probe_cas(const int32_t* u, const int32_t* v, int64_t m, int32_t* table,
                             int32_t n, bool fail, uint32_t* sink, hipStream_t s);
+// Memory-model probe (modes 7-9, see kernels_probe.hip): t is int32[128].
+hipError_t launch_probe_mm(int mode, int32_t* t, hipStream_t s);
 hipError_t launch_probe_bitgather(const int32_t* u, const int32_t* v, int64_t m,
                                   const uint32_t* bits, int32_t n, int variant, uint32_t* sink,
                                   hipStream_t s);

@@ -78,6 +78,78 @@ __global__ __launch_bounds__(256) void k_probe(const int32_t* __restrict__ eu,
     if (acc == 0x9e3779b9u) sink[0] = acc;  // practically never taken
 }
 
+// Memory-model probe of the tree-array write rule (measurement only).  Two
+// workgroups, normally on two XCDs (workgroups are dealt to the XCDs in
+// turn; each records its XCD id).  t[0..31] is one 128-byte line holding
+// t[i] = i, t[64] a flag in another line, both set by the caller.
+//   A: loads t[1] (workgroup scope, so its XCD's L2 holds the line; not in
+//      modes 10 and 11), then writes t[0] = 100 with a workgroup-scope store
+//      (modes 7, 10), an agent-scope store (modes 8, 11) or not at all (mode
+//      9), and raises the flag.
+//   B: waits for the flag, swaps t[1] from 1 to 50 (agent-scope CAS), raises
+//      the flag again.
+//   A: waits for that, then tries to swap t[1] from 1 to 70 (agent-scope CAS).
+// B's swap happened first, so A's must fail and return 50.  If A's returns 1,
+// the CAS ran on A's stale copy of the line: two hooks of one root both
+// "succeeded", and one of them is lost.  If t[1] reads 1 after the kernel,
+// A's copy of the line, written back from its XCD's L2, undid B's swap.  Every wait is bounded (2^22 polls).
+//   t[96], t[97]  XCD ids of A and B;  t[98], t[99]  polls used (-1 = ran out);
+//   t[100]  the value of t[1] A loaded;  t[101], t[102]  values A's and B's
+//   CAS found
+template <int MODE>
+__global__ __launch_bounds__(64) void k_probe_mm(int32_t* t) {
+    if (threadIdx.x != 0) return;
+    const int32_t xcc = (int32_t)(__builtin_amdgcn_s_getreg((3 << 11) | (0 << 6) | 20) & 15);
+    int32_t* flag = t + 64;
+    constexpr int32_t kPolls = 1 << 22;
+    if (blockIdx.x == 0) {
+        // modes 10 and 11 store without loading the line first
+        const int32_t x = MODE >= 10 ? 1 : __hip_atomic_load(t + 1, __ATOMIC_RELAXED,
+                                                              __HIP_MEMORY_SCOPE_WORKGROUP);
+        if (MODE == 7 || MODE == 10)
+            __hip_atomic_store(t, 100, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
+        if (MODE == 8 || MODE == 11)
+            __hip_atomic_store(t, 100, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        // relaxed: a release would write this XCD's dirty lines back first
+        __hip_atomic_store(flag, 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        // relaxed polls, as in the hook kernels (an acquire would invalidate
+        // this XCD's L2 and drop the cached line)
+        int32_t i = 0;
+        while (i < kPolls && __hip_atomic_load(flag, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) != 2) ++i;
+        int32_t expected = 1;
+        __hip_atomic_compare_exchange_strong(t + 1, &expected, 70, __ATOMIC_RELAXED,
+                                             __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        t[96] = xcc;
+        t[98] = i < kPolls ? i : -1;
+        t[100] = x;
+        t[101] = expected;
+    } else if (blockIdx.x == 1) {
+        int32_t i = 0;
+        while (i < kPolls && __hip_atomic_load(flag, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) != 1) ++i;
+        int32_t expected = 1;
+        __hip_atomic_compare_exchange_strong(t + 1, &expected, 50, __ATOMIC_RELAXED,
+                                             __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        // release: the CAS is complete before the flag is raised (B's own L2
+        // holds no dirty line for the write-back this implies)
+        __hip_atomic_store(flag, 2, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT);
+        t[97] = xcc;
+        t[99] = i < kPolls ? i : -1;
+        t[102] = expected;
+    }
+}
+
+hipError_t launch_probe_mm(int mode, int32_t* t, hipStream_t s) {
+    switch (mode) {
+        case 7: k_probe_mm<7><<<2, 64, 0, s>>>(t); break;
+        case 8: k_probe_mm<8><<<2, 64, 0, s>>>(t); break;
+        case 9: k_probe_mm<9><<<2, 64, 0, s>>>(t); break;
+        case 10: k_probe_mm<10><<<2, 64, 0, s>>>(t); break;
+        case 11: k_probe_mm<11><<<2, 64, 0, s>>>(t); break;
+        default: return hipErrorInvalidValue;
+    }
+    return hipGetLastError();
+}
+
 static hipError_t probe(int mode, const int32_t* u, const int32_t* v, int64_t m,
                         const int32_t* table, const uint32_t* bits, int32_t n, uint32_t* sink,
                         hipStream_t s) {

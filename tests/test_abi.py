@@ -136,6 +136,10 @@ def test_host_side_argument_errors(lib):
     assert lib.cc_labels_batch(-1, None, None, None, None, None) == cc.CC_ERR_ARG
     assert lib.cc_labels_batch(0, None, None, None, None, None) == cc.CC_OK
     assert lib.cc_probe(3, dummy, dummy, 4, None, 0, None) == cc.CC_ERR_ARG
+    # memory-model probes need a table of at least 128 words; unknown modes fail
+    assert lib.cc_probe(7, None, None, 0, None, 0, None) == cc.CC_ERR_ARG
+    assert lib.cc_probe(10, None, None, 0, dummy, 64, None) == cc.CC_ERR_ARG
+    assert lib.cc_probe(12, dummy, dummy, 4, dummy, 128, None) == cc.CC_ERR_ARG
 
 
 def test_workspace_sizes(lib):

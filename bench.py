@@ -280,8 +280,8 @@ ABLATION = [
     ("fig1_hostloop_jump", dict(hook="plain", host_loop="jump")),
     ("fig1_hostloop_multijump", dict(hook="plain", host_loop="multijump")),
     ("atomic_hook_s1", dict(hook="atomic", segments=1, filter="off", path_halving="off")),
-    ("adaptive_fig4", dict(hook="atomic", filter="off", path_halving="off")),
-    ("adaptive_fig4_halving", dict(hook="atomic", filter="off")),
+    ("adaptive_fig4_s_entries_over_n", dict(hook="atomic", filter="off", path_halving="off")),
+    ("adaptive_fig4_s_entries_over_n_halving", dict(hook="atomic", filter="off")),
     ("atomic_s1_halving", dict(hook="atomic", segments=1, filter="off")),
     ("adaptive_giant_filter", dict(hook="atomic", filter="giant", path_halving="off",
                                    hot_cache="off")),
@@ -313,9 +313,16 @@ def ablation(cc, torch, dev, args, reps=5):
         del u_np, v_np
         out = torch.empty(n, dtype=torch.int32, device=dev)
         rows = {}
-        variants = list(ABLATION) + [("fig6_s%d" % s, dict(hook="atomic", filter="off", segments=s,
-                                                       path_halving="off"))
-                                     for s in SEGMENT_SWEEP]
+        # the paper's s = 2|E|/|V|, the average degree, with |E| the undirected
+        # edges: entries / n for the symmetrised list, 2 * entries / n where
+        # each edge is listed once (the library's default s is entries / n)
+        avg_degree = (m if name == "rmat24" else 2 * m) / n
+        s_paper = max(1, int(round(avg_degree)))
+        variants = list(ABLATION) + [
+            ("adaptive_fig4_avg_degree_s%d" % s_paper,
+             dict(hook="atomic", filter="off", path_halving="off", segments=s_paper))] + [
+            ("fig6_s%d" % s, dict(hook="atomic", filter="off", segments=s, path_halving="off"))
+            for s in SEGMENT_SWEEP]
         for vname, kw in variants:
             opt = cc.Options(**kw)
             cc.labels(u, v, n, out=out, options=opt)
@@ -335,7 +342,9 @@ def ablation(cc, torch, dev, args, reps=5):
         base = rows["fig1_hostloop_jump"]["ms"]
         for r in rows.values():
             r["speedup_vs_fig1"] = round(base / r["ms"], 3)
-        results[name] = {"n": n, "m": m, "variants": rows}
+        results[name] = {"n": n, "m": m, "average_degree": round(avg_degree, 3),
+                         "s_entries_over_n": max(1, int(round(m / n))), "s_average_degree": s_paper,
+                         "variants": rows}
         del u, v, out
         torch.cuda.empty_cache()
     print(json.dumps({"mode": "ablation", "results": results}), flush=True)
@@ -651,7 +660,9 @@ def bench_batch(cc, torch, dev, num_graphs=10000, reps=5, tune=True):
         % (dt * 1e3, dt_graph * 1e3, dt_loop * 1e3))
     return {"workload": "batch10k", "graphs": num_graphs, "n_total": int(vo[-1]), "m_total": m,
             "segment_cap": bopt.segments, "path_halving": bopt.path_halving,
-            "tuned_ms": {"halving_%s_cap_%d" % (o["path_halving"], o["segments"]): round(t, 4)
+            "block": bopt.block or 1024,
+            "tuned_ms": {"halving_%s_cap_%d_block_%d" % (o["path_halving"], o["segments"],
+                                                          o["block"] or 1024): round(t, 4)
                          for t, o in btable},
             "graphs_per_s": num_graphs / dt, "edges_per_s": m / dt, "ms_per_batch": dt * 1e3,
             "ms_per_batch_graph_replay": dt_graph * 1e3,

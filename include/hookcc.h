@@ -14,8 +14,10 @@
  * Method (Section 3): the component-tree array pi (pi[v] = v initially) is
  * built by Atomic-Hook over edge-list segments, each followed by a full
  * Multi-Jump Compress (Fig. 3, Fig. 4), with s = max(1, round(m / n))
- * segments by default (the average-degree heuristic of Section 3.B, with m
- * the number of edge entries passed).  The atomic-free Hook of Fig. 2 is the
+ * segments by default (the average-degree heuristic 2|E|/|V| of Section 3.B,
+ * with m the number of edge entries passed: the average degree when the
+ * list holds both orientations of every edge, half of it when each edge is
+ * listed once).  The atomic-free Hook of Fig. 2 is the
  * alternative hook variant; its "repeat until Hook performs no change" loop
  * (Fig. 1) runs with the convergence test and the shrinking frontier of
  * still-active edges kept on the device.
@@ -293,8 +295,13 @@ int32_t cc_labels_batch(int32_t num_graphs, const int64_t* vtx_off, const int64_
  * exactly) and `segments`, a cap S on each graph's round(m_g / n_g) segments:
  * 0 = default, 2 with halving and no cap without it (in LDS a climb is
  * cheap, so fewer segments -- fewer Multi-Jump passes and barriers -- are
- * faster; the autotuner picks S).  `graph` = 1 captures the launch sequence.
- * Larger graphs use the default device-memory plan. */
+ * faster; the autotuner picks S) and `block`, the workgroup size of the LDS
+ * solver (64..1024, multiple of 64; 0 = 1024; as many workgroups share a CU
+ * as the LDS of the largest graph allows).  The LDS solver has no frontier
+ * compaction and so no compaction threshold: each graph's entries are read
+ * once per segment and hooked in LDS, with nothing left to compact.  `graph`
+ * = 1 captures the launch sequence.  Larger graphs use the default
+ * device-memory plan. */
 int32_t cc_labels_batch_ex(int32_t num_graphs, const int64_t* vtx_off, const int64_t* edge_off,
                            const int32_t* edges_u, const int32_t* edges_v, int32_t* out_label,
                            const cc_options* opts, void* stream, cc_stats* stats);

@@ -140,16 +140,20 @@ def tune(u, v, n: int, *, reps: int = 3, cache: bool = True, path: str | None = 
 
 
 def tune_batch(u, v, vtx_off, edge_off, *, reps: int = 3, log=None):
-    """Plan of the batched LDS solver: path halving in the LDS climb (on/off)
-    and the per-graph segment cap S (each graph gets min(S, round(m_g / n_g))
+    """Plan of the batched LDS solver: path halving in the LDS climb (on/off),
+    the per-graph segment cap S (each graph gets min(S, round(m_g / n_g))
     segments; 0 = the default, 2 with halving and the paper's round(m_g / n_g)
-    without).  Returns (best Options, table of (ms, options dict))."""
+    without) and the workgroup size (256, 512, 1024: with the LDS of the
+    largest graph it sets how many workgroups share a CU).  The LDS solver has
+    no frontier compaction, so there is no compaction threshold to choose.
+    Returns (best Options, table of (ms, options dict))."""
     import torch
     out = torch.empty(int(vtx_off[-1]), dtype=torch.int32, device=u.device)
     cands = [Options(segments=s) for s in (1, 2, 4, 8)]
     cands += [Options(segments=s, path_halving="off") for s in (0, 4, 8)]
     table = []
-    for opt in cands:
+
+    def timed(opt):
         labels_batch(u, v, vtx_off, edge_off, out=out, options=opt)
         best = float("inf")
         for _ in range(reps):
@@ -157,9 +161,23 @@ def tune_batch(u, v, vtx_off, edge_off, *, reps: int = 3, log=None):
             t = time.perf_counter()
             labels_batch(u, v, vtx_off, edge_off, out=out, options=opt)
             best = min(best, time.perf_counter() - t)
-        table.append((best * 1e3, opt))
+        return best * 1e3
+
+    for opt in cands:
+        t = timed(opt)
+        table.append((t, opt))
         if log:
             log("tune batch halving %s, segment cap %d: %.3f ms"
-                % (opt.path_halving, opt.segments, best * 1e3))
+                % (opt.path_halving, opt.segments, t))
+    table.sort(key=lambda x: x[0])
+    best = table[0][1]
+    for block in (256, 512):
+        opt = Options(**{**best.__dict__, "block": block})
+        t = timed(opt)
+        table.append((t, opt))
+        if log:
+            log("tune batch halving %s, segment cap %d, block %d: %.3f ms"
+                % (opt.path_halving, opt.segments, block, t))
     table.sort(key=lambda x: x[0])
     return table[0][1], [(t, o.__dict__) for t, o in table]
+

@@ -118,8 +118,10 @@ int32_t make_plan(int32_t n, int64_t m, const cc_options* o, Plan& p,
         op.hook != CC_HOOK_HYBRID)
         return fail(CC_ERR_ARG, "unknown cc_options.hook");
     if (op.segments < 0) return fail(CC_ERR_ARG, "cc_options.segments < 0");
-    // Average-degree heuristic (Section 3.B, Fig. 4): s = 2|E|/|V| with |E|
-    // counted once per undirected edge, i.e. s = (entries passed) / n.
+    // Average-degree heuristic (Section 3.B, Fig. 4): s = 2|E|/|V|, read as
+    // s = (entries passed) / n -- the average degree when the list holds both
+    // orientations of every edge, half of it when each edge is listed once
+    // (the library cannot tell the two apart).
     const int64_t s_paper = n > 0 ? std::max<int64_t>(1, (m + n / 2) / n) : 1;
     // Automatic variant (measured on gfx950): on large dense lists (average
     // degree >= 8) the filtered Atomic-Hook wins (one pass over the entries,
@@ -1178,6 +1180,10 @@ int32_t list_impl(int32_t count, const cc_graph* graphs, const cc_options* opts,
     const bool lds_halve = ph != CC_HALVE_OFF;
     int32_t seg_cap = opts ? opts->segments : 0;
     if (seg_cap < 0) return fail(CC_ERR_ARG, "cc_options.segments < 0");
+    // workgroup size of the LDS solver (0 = 1024)
+    const int32_t lds_block = (opts && opts->block) ? opts->block : 1024;
+    if (lds_block < 64 || lds_block > 1024 || lds_block % 64)
+        return fail(CC_ERR_ARG, "cc_options.block must be a multiple of 64 in [64, 1024]");
     if (seg_cap == 0 && lds_halve) seg_cap = 2;
     if (st) {
         std::memset(st, 0, sizeof *st);
@@ -1295,7 +1301,7 @@ int32_t list_impl(int32_t count, const cc_graph* graphs, const cc_options* opts,
             HIPCHK(launch_batch_lds(reinterpret_cast<GraphDesc*>(ws + desc_off),
                                     reinterpret_cast<int32_t*>(ws + order_off), ns,
                                     (int32_t)maxn_small, &ctrls[0].queue_head, &ctrls[0].status,
-                                    lds_halve, device_cu_count(), s));
+                                    lds_halve, device_cu_count(), s, lds_block));
         }
         for (int32_t i = 0; i < nl; ++i) {
             const cc_graph& G = graphs[large[i]];
@@ -1314,7 +1320,7 @@ int32_t list_impl(int32_t count, const cc_graph* graphs, const cc_options* opts,
         // every replay.  Only what the capture bakes in is: sizes, pointers,
         // the LDS launch shape, and each large graph's arrays and plan.
         k.add(count).add(ws).add(s).add(pe->host_stage).add(seg_cap).add(lds_halve)
-            .add(maxn_small).add(ns).add(nl);
+            .add(maxn_small).add(ns).add(nl).add(lds_block);
         for (int32_t i = 0; i < nl; ++i) {
             const cc_graph& G = graphs[large[i]];
             k.add(G.edges_u).add(G.edges_v).add(G.out_label).add(G.m).add(G.n);

@@ -1,6 +1,7 @@
 // Batched solve of many small graphs in one persistent launch (CDNA4).
 //
-// One workgroup (1024 threads, 16 waves) per CU takes graphs from a device
+// Persistent workgroups (1024 threads, 16 waves, by default; as many per CU as
+// the LDS of the launch's largest graph allows) take graphs from a device
 // work queue (an atomic counter over a host-sorted order, largest first) and
 // solves each one entirely in LDS: the graph's tree array pi lives in LDS as
 // local ids, 32-bit for n <= 32768 and 16-bit up to 65536 (at most 128 KiB of
@@ -340,12 +341,17 @@ hipError_t prepare_batch_lds() {
 
 hipError_t launch_batch_lds(const GraphDesc* descs, const int32_t* order, int32_t count,
                             int32_t max_n, int32_t* queue_head, int32_t* status, bool halve,
-                            int grid, hipStream_t s) {
+                            int grid, hipStream_t s, int block) {
     if (count <= 0) return hipSuccess;
     if (max_n < 1 || max_n > 65536) return hipErrorInvalidValue;
+    if (block < 64 || block > 1024 || block % 64) return hipErrorInvalidValue;
     // 32-bit slots for graphs of at most kWideMaxN vertices, 16-bit above
     const size_t lds = (uint32_t)max_n <= kWideMaxN ? (size_t)max_n * 4 : (size_t)kWideMaxN * 4;
-    k_batch_lds<<<grid, 1024, lds, s>>>(descs, order, count, queue_head, status, halve);
+    // persistent: as many workgroups as fit on the CUs at once (LDS and
+    // thread limits), at most 32 waves per CU
+    const int per_cu = (int)std::max<size_t>(1, std::min<size_t>((size_t)(160 * 1024) / lds,
+                                                                 (size_t)(2048 / block)));
+    k_batch_lds<<<grid * per_cu, block, lds, s>>>(descs, order, count, queue_head, status, halve);
     return hipGetLastError();
 }
 

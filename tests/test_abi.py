@@ -135,6 +135,12 @@ def test_host_side_argument_errors(lib):
                                dummy) == cc.CC_ERR_ARG
     assert lib.cc_labels_batch(-1, None, None, None, None, None) == cc.CC_ERR_ARG
     assert lib.cc_labels_batch(0, None, None, None, None, None) == cc.CC_OK
+    # the LDS solver's workgroup size is validated before any device work
+    vo = np.array([0, 4], dtype=np.int64)
+    eo = np.array([0, 1], dtype=np.int64)
+    bad_block = cc.Options(block=100)._c()
+    assert lib.cc_labels_batch_ex(1, vo.ctypes.data, eo.ctypes.data, dummy, dummy, dummy,
+                                  ctypes.byref(bad_block), None, None) == cc.CC_ERR_ARG
     assert lib.cc_probe(3, dummy, dummy, 4, None, 0, None) == cc.CC_ERR_ARG
     # memory-model probes need a table of at least 128 words; unknown modes fail
     assert lib.cc_probe(7, None, None, 0, None, 0, None) == cc.CC_ERR_ARG

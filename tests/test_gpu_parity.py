@@ -422,10 +422,12 @@ def test_full_size_batch_matches_oracle_digest(dev):
     assert (int(vo[-1]), len(u)) == (rec["n"], rec["m"])
     say("full size batch10k")
     du, dv = to_dev(u, dev), to_dev(v, dev)
-    for cap, halve in ((0, "auto"), (1, "auto"), (3, "auto"), (0, "off"), (3, "off")):
+    for cap, halve, block in ((0, "auto", 0), (1, "auto", 0), (3, "auto", 0), (0, "off", 0),
+                              (3, "off", 0), (0, "auto", 256), (2, "auto", 512)):
         lab = cc.labels_batch(du, dv, vo, eo,
-                              options=cc.Options(segments=cap, path_halving=halve)).cpu().numpy()
-        assert digest(lab) == rec["sha256"], (cap, halve)
+                              options=cc.Options(segments=cap, path_halving=halve,
+                                                 block=block)).cpu().numpy()
+        assert digest(lab) == rec["sha256"], (cap, halve, block)
 
 
 # ----------------------------------------------------------------------------- streamed (host edges)

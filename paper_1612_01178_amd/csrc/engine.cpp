@@ -54,6 +54,19 @@ int size_class(uint64_t w) {
 }
 
 // ---------------------------------------------------------------------- plans
+// round(m / n), at least 1, for m >= 0 and n > 0, without overflow.
+int64_t round_ratio(int64_t m, int64_t n) {
+    return std::max<int64_t>(1, m / n + ((m % n) * 2 >= n ? 1 : 0));
+}
+
+// First entry of segment i of S over m entries: floor(m * i / S) rounded down
+// to a multiple of 4 (keeps 16-byte loads aligned); 128-bit product, so any
+// m >= 0 works.
+int64_t segment_start(int64_t m, int64_t i, int64_t S) {
+    return (int64_t)(((__int128)m * i) / S) & ~int64_t(3);
+}
+
+
 struct Plan {
     int hook = CC_HOOK_ATOMIC;  // resolved variant: CC_HOOK_ATOMIC, CC_HOOK_PLAIN or CC_HOOK_HYBRID
     int segments = 1;
@@ -122,7 +135,7 @@ int32_t make_plan(int32_t n, int64_t m, const cc_options* o, Plan& p,
     // s = (entries passed) / n -- the average degree when the list holds both
     // orientations of every edge, half of it when each edge is listed once
     // (the library cannot tell the two apart).
-    const int64_t s_paper = n > 0 ? std::max<int64_t>(1, (m + n / 2) / n) : 1;
+    const int64_t s_paper = n > 0 ? std::min<int64_t>(int64_t(1) << 20, round_ratio(m, n)) : 1;
     // Automatic variant (measured on gfx950): on large dense lists (average
     // degree >= 8) the filtered Atomic-Hook wins (one pass over the entries,
     // most of them reduced to two bitmap tests; R-MAT 24 3.8 ms against 38 ms
@@ -160,7 +173,7 @@ int32_t make_plan(int32_t n, int64_t m, const cc_options* o, Plan& p,
     // exists): a first segment of ~n/16 entries (R-MAT 24: 3.80 ms against
     // 3.86 at n/8 and 3.98 at n/4).
     if (s == 0) s = auto_filtered ? 16 * s_paper : s_paper;
-    const int64_t smax = std::max<int64_t>(1, (m + 3) / 4);
+    const int64_t smax = std::max<int64_t>(1, m / 4 + (m % 4 != 0));
     s = std::max<int64_t>(1, std::min<int64_t>(s, smax));
     s = std::min<int64_t>(s, 1 << 20);
     p.segments = (int)s;
@@ -523,7 +536,7 @@ int32_t enqueue_atomic(int32_t n, const int32_t* u, const int32_t* v, int64_t m,
     const int S = p.segments;
     auto bound = [&](int64_t i) -> int64_t {
         if (i >= S) return m;
-        return (m * i / S) & ~int64_t(3);  // multiples of 4 keep 16-byte loads aligned
+        return segment_start(m, i, S);
     };
     int hooks = 0, jumps = 0;
     TIMED(kPhaseOther, launch_init(pi, n, ctrl, s));
@@ -1078,7 +1091,7 @@ int32_t csr_impl(int32_t n, const int64_t* row_ptr, const int32_t* col, int64_t 
     uint32_t* bits = filter ? reinterpret_cast<uint32_t*>(ws + 256) : nullptr;
     int2* F = frontier_bytes ? reinterpret_cast<int2*>(ws + 256 + bits_bytes) : nullptr;
     const int S = p.segments;
-    auto bound = [&](int64_t i) -> int64_t { return i >= S ? m : (m * i / S) & ~int64_t(3); };
+    auto bound = [&](int64_t i) -> int64_t { return i >= S ? m : segment_start(m, i, S); };
     Timer tm;
     tm.on = p.profile;
     tm.s = s;
@@ -1284,7 +1297,7 @@ int32_t list_impl(int32_t count, const cc_graph* graphs, const cc_options* opts,
             d.m = G.m;
             d.n = G.n;
             // average-degree segmentation per graph (Section 3.B), capped
-            d.segments = (int32_t)std::max<int64_t>(1, (G.m + G.n / 2) / G.n);
+            d.segments = (int32_t)std::min<int64_t>(int64_t(1) << 20, round_ratio(G.m, G.n));
             if (seg_cap > 0) d.segments = std::min<int32_t>(d.segments, seg_cap);
             hd[i] = d;
             ho[i] = i;

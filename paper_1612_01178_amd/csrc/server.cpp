@@ -34,6 +34,7 @@
 #include <unordered_map>
 #include <vector>
 
+#include "arena.hpp"
 #include "engine.hpp"
 
 namespace hookcc {
@@ -46,55 +47,6 @@ double now_s() {
 }
 
 size_t a256(size_t x) { return (x + 255) & ~size_t(255); }
-
-// First-fit allocator over [0, size) with coalescing of neighbours.
-class Arena {
-   public:
-    void reset(size_t size) {
-        free_.clear();
-        if (size) free_[0] = size;
-        used_ = 0;
-    }
-    bool alloc(size_t bytes, size_t* off) {
-        if (bytes == 0) {
-            *off = 0;
-            return true;
-        }
-        for (auto it = free_.begin(); it != free_.end(); ++it) {
-            if (it->second >= bytes) {
-                *off = it->first;
-                const size_t rest = it->second - bytes, start = it->first + bytes;
-                free_.erase(it);
-                if (rest) free_[start] = rest;
-                used_ += bytes;
-                return true;
-            }
-        }
-        return false;
-    }
-    void release(size_t off, size_t bytes) {
-        if (bytes == 0) return;
-        used_ -= bytes;
-        auto next = free_.lower_bound(off);
-        if (next != free_.end() && off + bytes == next->first) {
-            bytes += next->second;
-            next = free_.erase(next);
-        }
-        if (next != free_.begin()) {
-            auto prev = std::prev(next);
-            if (prev->first + prev->second == off) {
-                prev->second += bytes;
-                return;
-            }
-        }
-        free_[off] = bytes;
-    }
-    size_t used() const { return used_; }
-
-   private:
-    std::map<size_t, size_t> free_;
-    size_t used_ = 0;
-};
 
 struct Request {
     int64_t id = 0;

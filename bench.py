@@ -70,6 +70,9 @@ def main():
                     help="flagged option: hook only u <= v of a symmetrised list (not the headline)")
     ap.add_argument("--skip-cpu", action="store_true")
     ap.add_argument("--skip-batch", action="store_true")
+    ap.add_argument("--skip-loop", action="store_true",
+                    help="--mode batch: leave out the per-graph cc_labels loop baseline "
+                         "(kernel profiles of the batched call alone)")
     ap.add_argument("--mode", default="solve",
                     choices=["solve", "ablation", "serving", "tune", "batch"],
                     help="solve: the headline line; ablation: the paper's Fig. 5/6 variants "
@@ -114,7 +117,8 @@ def main():
     if args.mode == "batch":
         # the library's default batch plan (no tuning), so that every batched
         # launch of the run has the same plan (kernel profiles)
-        print(json.dumps({"mode": "batch", "results": bench_batch(cc, torch, dev, tune=False)}),
+        print(json.dumps({"mode": "batch", "results": bench_batch(cc, torch, dev, tune=False,
+                                                                  loop=not args.skip_loop)}),
               flush=True)
         return
     if args.mode == "serving":
@@ -241,6 +245,8 @@ def main():
     }
 
     result["ceilings"] = probe_ceilings(cc, torch, u, v, n, m)
+    result["roofline_l2"] = l2_roofline(args.workload, hook_ms, m, result["ceilings"],
+                                        st.get("hook") == 1 and traffic is not None)
 
     if not args.skip_batch:
         result["streamed"] = streamed(cc, torch, u_np, v_np, n, out, args.workload)
@@ -572,6 +578,33 @@ def measured_traffic(workload, kernel_tag):
     return rec["traffic_bytes_per_solve"] if rec else None
 
 
+# L2 request ceiling from the chip's organisation: 16 channels per XCD, each
+# serving one 64-byte request per clock, 8 XCDs, 2.4 GHz.
+L2_CHANNEL_PEAK_REQ_S = 16 * 8 * 2.4e9
+
+
+def l2_roofline(workload, hook_ms, m, ceilings, usable):
+    """The second roofline of the dominant kernel: L2 requests per second.
+    Requests per solve of the hook kernels and per entry of the stream +
+    bitmap probe come from the committed counter record (TCP_TCC_READ_REQ);
+    times are the live ones of this run.  The peak is the probe's measured
+    random-request rate (two bit tests of a 2 MiB bitmap per entry, the access
+    pattern of the filter) and, beside it, the channels' theoretical rate."""
+    rec = counter_record(workload) if usable else None
+    if not rec or "l2_requests_per_solve" not in rec or hook_ms <= 0:
+        return None
+    achieved = rec["l2_requests_per_solve"] / (hook_ms * 1e-3)
+    probe = ceilings.get("stream+bitmap", {})
+    peak = rec["probe_l2_requests_per_entry"] * probe["entries_per_s"] if probe else None
+    return {"bound": "l2_requests", "achieved": achieved, "peak": peak, "unit": "requests/s",
+            "frac": round(achieved / peak, 4) if peak else None,
+            "requests_per_entry": round(rec["l2_requests_per_solve"] / m, 4),
+            "theoretical_channels_peak": L2_CHANNEL_PEAK_REQ_S,
+            "frac_of_theoretical": round(achieved / L2_CHANNEL_PEAK_REQ_S, 4),
+            "source": "profiles/%s_ahook_counters.md (TCP_TCC_READ_REQ), times of this run"
+                      % workload}
+
+
 def probe_ceilings(cc, torch, u, v, n, m, reps=5):
     """Memory ceilings on the same resident edge list: the edge stream alone,
     stream + 2 random int32 gathers of an n-entry table, stream + 2 bit
@@ -599,7 +632,7 @@ def probe_ceilings(cc, torch, u, v, n, m, reps=5):
     return out
 
 
-def bench_batch(cc, torch, dev, num_graphs=10000, reps=5, tune=True):
+def bench_batch(cc, torch, dev, num_graphs=10000, reps=5, tune=True, loop=True):
     import numpy as np
 
     import graphgen
@@ -641,6 +674,11 @@ def bench_batch(cc, torch, dev, num_graphs=10000, reps=5, tune=True):
     side.synchronize()
     dt_graph = (time.perf_counter() - t) / reps
     parity = parity and digest(out.cpu().numpy()) == golden["batch10k"]["sha256"]
+    if not loop:
+        m = int(eo[-1])
+        return {"workload": "batch10k", "graphs": num_graphs, "ms_per_batch": dt * 1e3,
+                "ms_per_batch_graph_replay": dt_graph * 1e3, "graphs_per_s": num_graphs / dt,
+                "edges_per_s": m / dt, "parity_vs_oracle_digest": bool(parity)}
     # baseline: one synchronous cc_labels call per graph on the same resident data
     lib = cc.load()
     base_u, base_v, base_o = u.data_ptr(), v.data_ptr(), out.data_ptr()

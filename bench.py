@@ -540,8 +540,8 @@ def serving(cc, torch, dev, requests=2000, loads=(0.5, 0.7, 0.9), host_mode=Fals
 
 
 # Files whose contents decide the launches a counter record describes: the
-# kernels and the engine that plans them.  A record is used only while these
-# hash to the value stored in it.
+# kernels and the engine that plans them.  A record is used only while their
+# code (comments and blank lines aside) hashes to the value stored in it.
 COUNTER_SOURCES = ("paper_1612_01178_amd/csrc/kernels_core.hip",
                    "paper_1612_01178_amd/csrc/kernels_hot.hip",
                    "paper_1612_01178_amd/csrc/common.hpp",
@@ -549,8 +549,17 @@ COUNTER_SOURCES = ("paper_1612_01178_amd/csrc/kernels_core.hip",
                    "paper_1612_01178_amd/csrc/engine.cpp")
 
 
+def _code_of(text):
+    """The code of a C++/HIP source without its comments and blank lines, so
+    that a record outlives edits to comments but not to code."""
+    import re
+    text = re.sub(rb"/\*.*?\*/", b"", text, flags=re.S)
+    text = re.sub(rb"//[^\n]*", b"", text)
+    return b"\n".join(line.rstrip() for line in text.split(b"\n") if line.strip())
+
+
 def sources_hash():
-    return hashlib.sha256(b"".join(open(os.path.join(ROOT, f), "rb").read()
+    return hashlib.sha256(b"".join(_code_of(open(os.path.join(ROOT, f), "rb").read())
                                    for f in COUNTER_SOURCES)).hexdigest()[:16]
 
 

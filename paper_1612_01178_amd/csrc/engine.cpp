@@ -139,12 +139,12 @@ int32_t make_plan(int32_t n, int64_t m, const cc_options* o, Plan& p,
     // Automatic variant (measured on gfx950): on large dense lists (average
     // degree >= 8) the filtered Atomic-Hook wins (one pass over the entries,
     // most of them reduced to two bitmap tests; R-MAT 24 3.8 ms against 38 ms
-    // for the atomic-free rounds); on large sparse lists the hybrid plan (one
-    // atomic-free round, then Atomic-Hook over the surviving root pairs;
-    // percolated 4096^2 grid 0.54 ms against 1.07 Atomic-Hook and 1.15
-    // atomic-free rounds).  On small lists (< 2^22 entries) the per-kernel
-    // cost dominates and the atomic-free rounds win (ER 2^16: 0.09 ms against
-    // 0.18 hybrid and 0.14-0.28 Atomic-Hook); a no-sync call needs a fixed launch
+    // for the atomic-free rounds); on large sparse lists the hybrid plan (the
+    // window round, then Atomic-Hook over the compacted pairs; percolated
+    // 4096^2 grid 0.38 ms against 1.07 Atomic-Hook and 0.99 atomic-free
+    // rounds).  On small lists (< 2^22 entries) the per-kernel cost dominates
+    // and the atomic-free rounds win (ER 2^16: 0.10 ms against 0.26 hybrid and
+    // 0.14-0.28 Atomic-Hook); a no-sync call needs a fixed launch
     // sequence and takes the hybrid plan there.  CSR input has no atomic-free
     // rounds: its large sparse inputs take the hybrid plan (grid as CSR 0.73
     // ms against 1.47 Atomic-Hook), the rest the Atomic-Hook.

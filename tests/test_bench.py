@@ -35,8 +35,12 @@ def test_traffic_record_lookup(tmp_path, monkeypatch):
     (prof / "toy_ahook_counters.md").write_text("text\n```json\n%s\n```\n" % json.dumps(rec))
     assert bench.measured_traffic("toy", "atomic") == 123.0
     assert bench.measured_traffic("other", "atomic") is None
+    # an edit to comments or blank lines keeps it
+    eng = tmp_path / "paper_1612_01178_amd/csrc/engine.cpp"
+    eng.write_text("source of %s  // a comment\n\n/* another\n one */\n" % bench.COUNTER_SOURCES[-1])
+    assert bench.measured_traffic("toy", "atomic") == 123.0
     # a plan change in the engine makes the record stale
-    (tmp_path / "paper_1612_01178_amd/csrc/engine.cpp").write_text("engine, changed\n")
+    eng.write_text("engine, changed\n")
     assert bench.measured_traffic("toy", "atomic") is None
     # a record that leaves the engine out is never used
     rec2 = dict(rec, sources=list(bench.COUNTER_SOURCES[:-1]), sources_sha256_16=bench.sources_hash())

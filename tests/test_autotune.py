@@ -83,8 +83,14 @@ def test_tuned_plans_are_exact(tmp_path):
     dbu, dbv = torch.from_numpy(bu).to(dev), torch.from_numpy(bv).to(dev)
     print("tune batch of 60", flush=True)
     bopt, btable = autotune.tune_batch(dbu, dbv, vo, eo, reps=1)
-    assert sorted((o["path_halving"], o["segments"]) for _, o in btable) == \
+    default_block = cc.Options().block
+    assert sorted((o["path_halving"], o["segments"]) for _, o in btable
+                  if o["block"] == default_block) == \
         [("auto", 1), ("auto", 2), ("auto", 4), ("auto", 8), ("off", 0), ("off", 4), ("off", 8)]
+    # then the workgroup size, around the best of those
+    sized = [o for _, o in btable if o["block"] != default_block]
+    assert sorted(o["block"] for o in sized) == [256, 512]
+    assert len({(o["path_halving"], o["segments"]) for o in sized}) == 1
     for _, o in btable:
         got = cc.labels_batch(dbu, dbv, vo, eo, options=cc.Options(**o)).cpu().numpy()
         assert np.array_equal(got, bwant), o

@@ -15,6 +15,10 @@
 namespace hookcc {
 
 constexpr int kBatchEPT = 8;  // edge entries per thread per step
+// Fourth word of a raw buffer resource on gfx9-family GPUs (32-bit data
+// format, no swizzle) and the non-temporal cache policy of a buffer load.
+constexpr int32_t kBufferRsrcWord3 = 0x00020000;
+constexpr int32_t kBufferNonTemporal = 2;
 
 // 16-bit compare-and-swap in LDS, built on the 32-bit CAS of the containing
 // word: succeeds iff slot `idx` holds `expected`; returns the value found.
@@ -84,14 +88,45 @@ __device__ __forceinline__ uint32_t lds_cas(uint16_t* spi, uint32_t idx, uint32_
 // with fewer segments (fewer Multi-Jump passes over its vertices).
 template <typename T>
 __device__ __forceinline__ void lds_atomic_hook(T* spi, uint32_t pu, uint32_t pv, bool halve) {
+    // One exit, at the loop's head, and no branch inside (halve is uniform):
+    // after a successful CAS both ends are set to L, which ends the loop; the
+    // two loads and the store of that last pass are wasted but cheaper than
+    // the exec-mask bookkeeping of a second exit.
     while (pu != pv) {
         const uint32_t H = pu > pv ? pu : pv;
         const uint32_t L = pu > pv ? pv : pu;
         const uint32_t found = lds_cas(spi, H, H, L);
-        if (found == H) return;
-        pu = lds_ld(spi, found);
-        pv = lds_ld(spi, L);
-        if (halve && pu != found) lds_st(spi, H, pu);
+        const uint32_t gu = lds_ld(spi, found);
+        const uint32_t gv = lds_ld(spi, L);
+        // H is no root now (it was none or the CAS made it a child of L), so
+        // no CAS can succeed on its slot and every value stored there is one
+        // of its ancestors: gu (found's parent, found itself, or L after a
+        // successful CAS) is one, whichever halving store lands last.
+        if (halve) lds_st(spi, H, gu);
+        const bool hooked = found == H;
+        pu = hooked ? L : gu;
+        pv = hooked ? L : gv;
+    }
+}
+
+// Entries [base, base + step) of the edge arrays, clipped at `end`: lane
+// tid loads entries base + tid + j * blockDim.x into a[j], b[j] (0 past
+// `end`).  Each array is read through a raw buffer resource whose size is
+// the step's entries inside [base, end), so no load is issued past `end`;
+// the byte offsets are per lane and the same at every step.
+__device__ __forceinline__ void edge_step_loads(g_cint* du, g_cint* dv, int64_t base, int64_t end,
+                                                int64_t step, int32_t* a, int32_t* b) {
+    const int64_t rem = end - base < step ? end - base : step;
+    const int32_t bytes = rem > 0 ? (int32_t)(rem * 4) : 0;
+    const __amdgpu_buffer_rsrc_t ru =
+        __builtin_amdgcn_make_buffer_rsrc((void*)(du + base), 0, bytes, kBufferRsrcWord3);
+    const __amdgpu_buffer_rsrc_t rv =
+        __builtin_amdgcn_make_buffer_rsrc((void*)(dv + base), 0, bytes, kBufferRsrcWord3);
+#pragma unroll
+    for (int j = 0; j < kBatchEPT; ++j) {
+        const int32_t off = (int32_t)((threadIdx.x + j * blockDim.x) * 4);
+        a[j] = __builtin_amdgcn_raw_buffer_load_b32(ru, off, 0, kBufferNonTemporal);
+        b[j] = __builtin_amdgcn_raw_buffer_load_b32(rv, off, 0, kBufferNonTemporal);
     }
 }
 
@@ -114,51 +149,48 @@ __device__ __forceinline__ void solve_graph(T* spi, const GraphDesc& d, bool hal
         // kBatchEPT entries per thread per step, all loads issued before
         // any hook, and the next step's loads issued before this step's
         // hooks (software pipelining), so the edge stream's latency
-        // overlaps the LDS work.
-        const int64_t step = (int64_t)nthr * kBatchEPT;
-        int32_t a[kBatchEPT], b[kBatchEPT], na[kBatchEPT], nb[kBatchEPT];
-        int64_t e0 = b0 + tid;
+        // overlaps the LDS work.  The loads go through buffer resources
+        // that cover exactly the step's entries: the per-lane byte offsets
+        // are the same at every step, and a load past the segment's end
+        // returns 0 without touching memory.  No branch surrounds a load or
+        // a hook: such an entry, and one out of range, becomes the pair
+        // (0, 0), whose hook does nothing -- divergent branches would cost
+        // more scalar exec-mask instructions than the work they skip.
+        if (b1 > b0) {
+            const int64_t step = (int64_t)nthr * kBatchEPT;
+            int32_t a[kBatchEPT], b[kBatchEPT], na[kBatchEPT], nb[kBatchEPT];
+            int64_t base = b0;
+            edge_step_loads(du, dv, base, b1, step, a, b);
+            for (; base < b1; base += step) {
+                edge_step_loads(du, dv, base + step, b1, step, na, nb);
 #pragma unroll
-        for (int j = 0; j < kBatchEPT; ++j) {
-            const int64_t e = e0 + (int64_t)j * nthr;
-            a[j] = e < b1 ? __builtin_nontemporal_load(du + e) : 0;
-            b[j] = e < b1 ? __builtin_nontemporal_load(dv + e) : 0;
-        }
-        for (; e0 < b1; e0 += step) {
-            const int64_t e1 = e0 + step;
-#pragma unroll
-            for (int j = 0; j < kBatchEPT; ++j) {
-                const int64_t e = e1 + (int64_t)j * nthr;
-                na[j] = e < b1 ? __builtin_nontemporal_load(du + e) : 0;
-                nb[j] = e < b1 ? __builtin_nontemporal_load(dv + e) : 0;
-            }
-#pragma unroll
-            for (int j = 0; j < kBatchEPT; ++j) {
-                if (e0 + (int64_t)j * nthr >= b1) continue;
-                if ((uint32_t)a[j] >= n || (uint32_t)b[j] >= n) {
-                    bad = true;
-                    continue;
+                for (int j = 0; j < kBatchEPT; ++j) {
+                    const bool ok = max((uint32_t)a[j], (uint32_t)b[j]) < n;
+                    bad |= !ok;
+                    const uint32_t x = ok ? (uint32_t)a[j] : 0u;
+                    const uint32_t y = ok ? (uint32_t)b[j] : 0u;
+                    lds_atomic_hook(spi, lds_ld(spi, x), lds_ld(spi, y), halve);
                 }
-                if (a[j] == b[j]) continue;
-                lds_atomic_hook(spi, lds_ld(spi, (uint32_t)a[j]), lds_ld(spi, (uint32_t)b[j]), halve);
-            }
 #pragma unroll
-            for (int j = 0; j < kBatchEPT; ++j) {
-                a[j] = na[j];
-                b[j] = nb[j];
+                for (int j = 0; j < kBatchEPT; ++j) {
+                    a[j] = na[j];
+                    b[j] = nb[j];
+                }
             }
         }
         __syncthreads();
         // Multi-Jump (Fig. 3, bottom) over the graph's vertices, low ids first.
+        // Each vertex climbs to its root and stores it once (a root stores
+        // itself); no hook runs in this phase, so only the stores of other
+        // climbers race with it, and each stores an ancestor.
         for (uint32_t x = tid; x < n; x += nthr) {
             uint32_t p = lds_ld(spi, x);
-            if (p == x) continue;
             uint32_t g = lds_ld(spi, p);
             while (g != p) {
-                lds_st(spi, x, g);
                 p = g;
                 g = lds_ld(spi, p);
             }
+            lds_st(spi, x, p);
         }
         __syncthreads();
     }

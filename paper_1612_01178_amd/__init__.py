@@ -237,6 +237,33 @@ def stream_status(stream=None) -> int:
     return rc
 
 
+_c_options_cache = {}
+
+
+def _c_options(options):
+    """The C struct of `options` (None = defaults), built once per distinct
+    set of field values: the library takes it as const, so calls share it."""
+    opts = options if options is not None else Options()
+    key = tuple(vars(opts).values())
+    c = _c_options_cache.get(key)
+    if c is None:
+        if len(_c_options_cache) >= 64:
+            _c_options_cache.clear()
+        c = _c_options_cache[key] = opts._c()
+    return c
+
+
+def _on_device(dev):
+    """torch.cuda.device(dev), or nothing when dev is already current (the
+    context manager costs several microseconds per call)."""
+    import contextlib
+    import torch
+    dev = torch.device(dev)
+    if dev.index is None or dev.index == torch.cuda.current_device():
+        return contextlib.nullcontext()
+    return torch.cuda.device(dev)
+
+
 def _check(rc: int) -> None:
     if rc != CC_OK:
         raise CCError(rc, last_error())
@@ -274,12 +301,12 @@ def labels(u, v, n: int, *, out=None, options: Options | None = None, stream=Non
         out = _edge_tensor(out, "out")
         if out.numel() < n:
             raise ValueError("out is shorter than n")
-    opts = (options or Options())._c()
+    opts = _c_options(options)
     st = _CStats()
     ws_ptr, ws_bytes = None, 0
     if workspace is not None:
         ws_ptr, ws_bytes = workspace.data_ptr(), workspace.numel() * workspace.element_size()
-    with torch.cuda.device(u.device):
+    with _on_device(u.device):
         rc = load().cc_labels_ex(int(n), u.data_ptr(), v.data_ptr(), u.numel(), out.data_ptr(),
                                  ctypes.byref(opts), ws_ptr, ws_bytes, _stream_handle(stream),
                                  ctypes.byref(st))
@@ -301,10 +328,10 @@ def labels_noalloc(u, v, n: int, *, out, options: Options | None = None, stream=
         raise ValueError("u and v differ in length")
     if out.numel() < n:
         raise ValueError("out is shorter than n")
-    opts = (options or Options())._c()
+    opts = _c_options(options)
     st = _CStats()
     import torch
-    with torch.cuda.device(u.device):
+    with _on_device(u.device):
         rc = load().cc_labels_noalloc(int(n), u.data_ptr(), v.data_ptr(), u.numel(),
                                       out.data_ptr(), ctypes.byref(opts), _stream_handle(stream),
                                       ctypes.byref(st))
@@ -320,7 +347,7 @@ def labels_raw(n: int, u_ptr: int, v_ptr: int, m: int, out_ptr: int) -> int:
 
 
 def workspace_bytes(n: int, m: int, options: Options | None = None) -> int:
-    opts = (options or Options())._c()
+    opts = _c_options(options)
     return int(load().cc_workspace_bytes(int(n), int(m), ctypes.byref(opts)))
 
 
@@ -345,8 +372,8 @@ def labels_batch(u, v, vtx_off, edge_off, *, out=None, options: Options | None =
     if out is None:
         out = torch.empty(total, dtype=torch.int32, device=u.device)
     st = _CStats()
-    with torch.cuda.device(u.device):
-        opts = (options or Options())._c()
+    with _on_device(u.device):
+        opts = _c_options(options)
         rc = load().cc_labels_batch_ex(len(vo) - 1, vo.ctypes.data, eo.ctypes.data, u.data_ptr(),
                                        v.data_ptr(), out.data_ptr(), ctypes.byref(opts),
                                        _stream_handle(stream), ctypes.byref(st))
@@ -376,9 +403,9 @@ def labels_host(u, v, n: int, *, chunk: int = 0, out=None, device=None,
     dev = torch.device(device) if device is not None else torch.device("cuda", torch.cuda.current_device())
     if out is None:
         out = torch.empty(max(int(n), 0), dtype=torch.int32, device=dev)
-    opts = (options or Options())._c()
+    opts = _c_options(options)
     st = _CStats()
-    with torch.cuda.device(out.device):
+    with _on_device(out.device):
         rc = load().cc_labels_host(int(n), up if m else None, vp if m else None, m,
                                    out.data_ptr() if n else None, int(chunk), ctypes.byref(opts),
                                    _stream_handle(stream), ctypes.byref(st))
@@ -399,9 +426,9 @@ def labels_csr(row_ptr, col, n: int, *, out=None, options: Options | None = None
         raise TypeError("row_ptr must be a contiguous int64 CUDA tensor of length n + 1")
     if out is None:
         out = torch.empty(max(int(n), 0), dtype=torch.int32, device=col.device)
-    opts = (options or Options())._c()
+    opts = _c_options(options)
     st = _CStats()
-    with torch.cuda.device(col.device):
+    with _on_device(col.device):
         rc = load().cc_labels_csr(int(n), row_ptr.data_ptr(), col.data_ptr() if col.numel() else None,
                                   col.numel(), out.data_ptr() if n else None, ctypes.byref(opts),
                                   _stream_handle(stream), ctypes.byref(st))
@@ -437,8 +464,8 @@ def labels_list(graphs, *, options: Options | None = None, stream=None,
     st = _CStats()
     if dev is None:
         return ([], {}) if return_stats else []
-    with torch.cuda.device(dev):
-        opts = (options or Options())._c()
+    with _on_device(dev):
+        opts = _c_options(options)
         rc = load().cc_labels_list(len(graphs), descs, ctypes.byref(opts), _stream_handle(stream),
                                    ctypes.byref(st))
     _check(rc)

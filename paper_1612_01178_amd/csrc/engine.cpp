@@ -292,6 +292,7 @@ struct PoolEntry {
     size_t stage_bytes = 0;
     hipStream_t copy_stream = nullptr;  // host-to-device staging of streamed solves
     hipEvent_t copied[2] = {nullptr, nullptr};
+    int32_t* batch_status = nullptr;  // pinned: the LDS batch launch's status word
     hipEvent_t consumed[2] = {nullptr, nullptr};
     // status word of the last no-sync call (pinned) and the event after its copy
     int32_t* async_slot = nullptr;
@@ -1177,7 +1178,23 @@ size_t workspace_bytes_impl(int32_t n, int64_t m, const cc_options* opts) {
 // workgroups take them largest first; every larger graph gets the device-memory
 // Atomic-Hook solve with its own control block.  Everything is enqueued on `s`
 // and the call ends with one synchronisation and one read of all control blocks.
-int32_t list_impl(int32_t count, const cc_graph* graphs, const cc_options* opts, hipStream_t s,
+// Segments of an LDS-solved graph: min(cap, round(m / n)) (at least 1), or
+// round(m / n) for cap 0; small caps by comparison, without a division.
+int32_t lds_segments(int64_t m, int64_t n, int32_t cap) {
+    if (cap > 0 && cap <= 16 && m < (int64_t(1) << 61)) {
+        int32_t k = cap;  // round(m / n) >= k  <=>  2m >= (2k - 1) n
+        while (k > 1 && 2 * m < (2 * (int64_t)k - 1) * n) --k;
+        return k;
+    }
+    const int32_t r = (int32_t)std::min<int64_t>(int64_t(1) << 20, round_ratio(m, n));
+    return cap > 0 ? std::min(r, cap) : r;
+}
+
+// The graph-list solve over any graph accessor: graph_at(g) returns graph g
+// as a cc_graph (the caller's array, or one computed from batch offsets, so a
+// batch never materialises a list).
+template <class GraphAt>
+int32_t list_core(int32_t count, GraphAt&& graph_at, const cc_options* opts, hipStream_t s,
                   cc_stats* st, void* workspace, size_t ws_bytes, size_t* ws_needed) {
     if (ws_needed) *ws_needed = 0;
     if (count < 0) return fail(CC_ERR_ARG, "graph count < 0");
@@ -1203,11 +1220,17 @@ int32_t list_impl(int32_t count, const cc_graph* graphs, const cc_options* opts,
         st->giant_label = -1;
     }
     if (count == 0) return CC_OK;
-    if (!graphs) return fail(CC_ERR_ARG, "null graph list");
-    std::vector<int32_t> small, large;
+    // host scratch kept per thread: a call allocates nothing once warm
+    static thread_local std::vector<int32_t> small, large, sorted;
+    static thread_local std::vector<uint8_t> cls;
+    small.clear();
+    large.clear();
+    small.reserve((size_t)count);
+    cls.resize((size_t)count);
+    int64_t start[257] = {0};
     int64_t maxn_small = 0;
     for (int32_t g = 0; g < count; ++g) {
-        const cc_graph& G = graphs[g];
+        const cc_graph G = graph_at(g);
         if (G.reserved != 0) return fail(CC_ERR_ARG, "cc_graph.reserved must be zero");
         if (G.n < 0 || G.m < 0) return fail(CC_ERR_ARG, "graph with n < 0 or m < 0");
         if (G.m > 0 && (!G.edges_u || !G.edges_v)) return fail(CC_ERR_ARG, "null edge array");
@@ -1217,6 +1240,9 @@ int32_t list_impl(int32_t count, const cc_graph* graphs, const cc_options* opts,
             continue;
         }
         if (G.n <= CC_BATCH_LDS_MAX_N) {
+            const uint8_t c = (uint8_t)(255 - size_class((uint64_t)G.m + (uint64_t)G.n));
+            cls[small.size()] = c;
+            ++start[c + 1];
             small.push_back(g);
             maxn_small = std::max<int64_t>(maxn_small, G.n);
         } else {
@@ -1230,15 +1256,8 @@ int32_t list_impl(int32_t count, const cc_graph* graphs, const cc_options* opts,
     // about a millisecond of host time, more than a third of the solve.
     {
         const size_t k = small.size();
-        std::vector<uint8_t> cls(k);
-        int64_t start[257] = {0};
-        for (size_t i = 0; i < k; ++i) {
-            const cc_graph& G = graphs[small[i]];
-            cls[i] = (uint8_t)(255 - size_class((uint64_t)G.m + (uint64_t)G.n));
-            ++start[cls[i] + 1];
-        }
         for (int c = 0; c < 256; ++c) start[c + 1] += start[c];
-        std::vector<int32_t> sorted(k);
+        sorted.resize(k);
         for (size_t i = 0; i < k; ++i) sorted[start[cls[i]]++] = small[i];
         small.swap(sorted);
     }
@@ -1247,18 +1266,18 @@ int32_t list_impl(int32_t count, const cc_graph* graphs, const cc_options* opts,
     std::vector<Plan> plans(nl);
     std::vector<size_t> region_off(nl, 0);
     std::vector<Layout> layouts(nl);
-    size_t off = align256((size_t)(1 + nl) * sizeof(Ctrl));
-    const size_t desc_off = off;
+    // Workspace: the LDS launch's control block, its descriptors right after
+    // (one copy from the staging buffer uploads both and clears the block),
+    // then the large graphs' control blocks and their regions.
+    const size_t desc_off = sizeof(Ctrl);
     const size_t desc_bytes = align256((size_t)ns * sizeof(GraphDesc));
-    off += desc_bytes;
-    const size_t order_off = off;
-    const size_t order_bytes = align256((size_t)ns * 4);
-    off += order_bytes;
+    const size_t lctrl_off = desc_off + desc_bytes;
+    size_t off = lctrl_off + align256((size_t)nl * sizeof(Ctrl));
     for (int32_t i = 0; i < nl; ++i) {
-        const cc_graph& G = graphs[large[i]];
+        const cc_graph G = graph_at(large[i]);
         int32_t rc = make_plan(G.n, G.m, nullptr, plans[i], kInputAtomicOnly);
         if (rc != CC_OK) return rc;
-        layouts[i] = layout(G.n, G.m, plans[i]);  // its control block is ctrls[1 + i] instead
+        layouts[i] = layout(G.n, G.m, plans[i]);  // its control block is lctrls[i] instead
         region_off[i] = off;
         off += align256(layouts[i].total);
     }
@@ -1273,53 +1292,53 @@ int32_t list_impl(int32_t count, const cc_graph* graphs, const cc_options* opts,
     if (ns > 0) HIPCHK(prepare_batch_lds());
     PoolEntry* pe = pool_entry(s);
     std::lock_guard<std::mutex> lk(pe->mu);
-    int32_t rc = ensure_host(pe, 1 + nl);
+    int32_t rc = ensure_host(pe, std::max(1, nl));
     if (rc != CC_OK) return rc;
+    if (!pe->batch_status)
+        HIPCHK(hipHostMalloc((void**)&pe->batch_status, 256, hipHostMallocDefault));
     if (!workspace) {
         rc = ensure_dev(pe, off);
         if (rc != CC_OK) return rc;
     }
     if (ns > 0) {
-        rc = ensure_stage(pe, desc_bytes + order_bytes);
+        rc = ensure_stage(pe, desc_off + desc_bytes);
         if (rc != CC_OK) return rc;
     }
     char* ws = workspace ? static_cast<char*>(workspace) : static_cast<char*>(pe->dev);
-    Ctrl* ctrls = reinterpret_cast<Ctrl*>(ws);
+    Ctrl* ctrl = reinterpret_cast<Ctrl*>(ws);                 // the LDS launch's
+    Ctrl* lctrls = reinterpret_cast<Ctrl*>(ws + lctrl_off);   // the large graphs'
+    // The LDS launch reports a bad endpoint in a pinned host word, so a call
+    // without large graphs needs no copy back before its synchronisation.
+    *pe->batch_status = 0;
     if (ns > 0) {
-        GraphDesc* hd = static_cast<GraphDesc*>(pe->host_stage);
-        int32_t* ho = reinterpret_cast<int32_t*>(static_cast<char*>(pe->host_stage) + desc_bytes);
+        std::memset(pe->host_stage, 0, desc_off);  // the cleared control block
+        GraphDesc* hd = reinterpret_cast<GraphDesc*>(static_cast<char*>(pe->host_stage) + desc_off);
         for (int32_t i = 0; i < ns; ++i) {
-            const cc_graph& G = graphs[small[i]];
-            GraphDesc d;
+            const cc_graph G = graph_at(small[i]);
+            GraphDesc& d = hd[i];
             d.u = G.edges_u;
             d.v = G.edges_v;
             d.out = G.out_label;
             d.m = G.m;
             d.n = G.n;
             // average-degree segmentation per graph (Section 3.B), capped
-            d.segments = (int32_t)std::min<int64_t>(int64_t(1) << 20, round_ratio(G.m, G.n));
-            if (seg_cap > 0) d.segments = std::min<int32_t>(d.segments, seg_cap);
-            hd[i] = d;
-            ho[i] = i;
+            d.segments = lds_segments(G.m, G.n, seg_cap);
         }
     }
     // The launch sequence: clear the LDS solver's control block, upload the
     // descriptors, one persistent LDS launch, then every large graph's solve.
     Timer tm;
     auto enqueue = [&]() -> int32_t {
-        HIPCHK(launch_zero(ctrls, sizeof(Ctrl) / 4, s));
         if (ns > 0) {
-            HIPCHK(hipMemcpyAsync(ws + desc_off, pe->host_stage, desc_bytes + order_bytes,
-                                  hipMemcpyHostToDevice, s));
-            HIPCHK(launch_batch_lds(reinterpret_cast<GraphDesc*>(ws + desc_off),
-                                    reinterpret_cast<int32_t*>(ws + order_off), ns,
-                                    (int32_t)maxn_small, &ctrls[0].queue_head, &ctrls[0].status,
+            HIPCHK(hipMemcpyAsync(ws, pe->host_stage, desc_off + desc_bytes, hipMemcpyHostToDevice, s));
+            HIPCHK(launch_batch_lds(reinterpret_cast<GraphDesc*>(ws + desc_off), ns,
+                                    (int32_t)maxn_small, &ctrl->queue_head, pe->batch_status,
                                     lds_halve, device_cu_count(), s, lds_block));
         }
         for (int32_t i = 0; i < nl; ++i) {
-            const cc_graph& G = graphs[large[i]];
+            const cc_graph G = graph_at(large[i]);
             int32_t r2 = enqueue_atomic(G.n, G.edges_u, G.edges_v, G.m, G.out_label, plans[i],
-                                        &ctrls[1 + i], filter_bufs(ws + region_off[i], layouts[i]),
+                                        &lctrls[i], filter_bufs(ws + region_off[i], layouts[i]),
                                         s, tm, nullptr);
             if (r2 != CC_OK) return r2;
         }
@@ -1335,7 +1354,7 @@ int32_t list_impl(int32_t count, const cc_graph* graphs, const cc_options* opts,
         k.add(count).add(ws).add(s).add(pe->host_stage).add(seg_cap).add(lds_halve)
             .add(maxn_small).add(ns).add(nl).add(lds_block);
         for (int32_t i = 0; i < nl; ++i) {
-            const cc_graph& G = graphs[large[i]];
+            const cc_graph G = graph_at(large[i]);
             k.add(G.edges_u).add(G.edges_v).add(G.out_label).add(G.m).add(G.n);
         }
         rc = run_graph(pe, k.h, s, enqueue);
@@ -1344,13 +1363,24 @@ int32_t list_impl(int32_t count, const cc_graph* graphs, const cc_options* opts,
     }
     if (rc != CC_OK) return rc;
     if (st) st->hook_launches += (ns > 0 ? 1 : 0);
-    HIPCHK(hipMemcpyAsync(pe->host_ctrl, ctrls, sizeof(Ctrl) * (1 + nl), hipMemcpyDeviceToHost, s));
+    if (nl > 0)
+        HIPCHK(hipMemcpyAsync(pe->host_ctrl, lctrls, sizeof(Ctrl) * nl, hipMemcpyDeviceToHost, s));
     HIPCHK(hipStreamSynchronize(s));
     if (st) st->host_syncs += 1;
-    for (int32_t i = 0; i <= nl; ++i)
-        if (pe->host_ctrl[i].status & kStatusRange)
-            return fail(CC_ERR_RANGE, "edge endpoint outside [0, n_g)");
+    bool bad = (*(volatile int32_t*)pe->batch_status & kStatusRange) != 0;
+    for (int32_t i = 0; i < nl; ++i) bad |= (pe->host_ctrl[i].status & kStatusRange) != 0;
+    if (bad) return fail(CC_ERR_RANGE, "edge endpoint outside [0, n_g)");
     return CC_OK;
+}
+
+int32_t list_impl(int32_t count, const cc_graph* graphs, const cc_options* opts, hipStream_t s,
+                  cc_stats* st, void* workspace, size_t ws_bytes, size_t* ws_needed) {
+    if (count > 0 && !graphs) {
+        if (ws_needed) *ws_needed = 0;
+        return fail(CC_ERR_ARG, "null graph list");
+    }
+    return list_core(count, [graphs](int32_t g) { return graphs[g]; }, opts, s, st, workspace,
+                     ws_bytes, ws_needed);
 }
 
 int32_t batch_impl(int32_t B, const int64_t* vo, const int64_t* eo, const int32_t* u,
@@ -1375,9 +1405,9 @@ int32_t batch_impl(int32_t B, const int64_t* vo, const int64_t* eo, const int32_
     }
     if (eo[B] > 0 && (!u || !v)) return fail(CC_ERR_ARG, "null edge array");
     if (vo[B] > 0 && !out) return fail(CC_ERR_ARG, "null out_label");
-    std::vector<cc_graph> list(B);
-    for (int32_t g = 0; g < B; ++g) {
-        cc_graph& G = list[g];
+    // graph g straight from the offsets: no list of B graphs is built
+    auto graph_at = [=](int32_t g) {
+        cc_graph G;
         const int64_t ne = eo[g + 1] - eo[g];
         G.edges_u = ne ? u + eo[g] : nullptr;
         G.edges_v = ne ? v + eo[g] : nullptr;
@@ -1385,8 +1415,9 @@ int32_t batch_impl(int32_t B, const int64_t* vo, const int64_t* eo, const int32_
         G.m = ne;
         G.n = (int32_t)(vo[g + 1] - vo[g]);
         G.reserved = 0;
-    }
-    return list_impl(B, list.data(), opts, s, st, nullptr, 0, nullptr);
+        return G;
+    };
+    return list_core(B, graph_at, opts, s, st, nullptr, 0, nullptr);
 }
 
 // ---------------------------------------------------------------------- probes, release
@@ -1442,6 +1473,8 @@ void release_impl() {
         if (e->dev) (void)hipFree(e->dev);
         if (e->host_ctrl) (void)hipHostFree(e->host_ctrl);
         if (e->host_stage) (void)hipHostFree(e->host_stage);
+        if (e->batch_status) (void)hipHostFree(e->batch_status);
+        e->batch_status = nullptr;
         e->dev = nullptr;
         e->host_ctrl = nullptr;
         e->host_stage = nullptr;

@@ -158,12 +158,12 @@ hipError_t launch_probe_bitgather(const int32_t* u, const int32_t* v, int64_t m,
                                   hipStream_t s);
 
 // Batched solve: one workgroup per graph, tree array in LDS, graphs taken
-// from a device work queue in the order of `order`; `grid` = CU count, and
+// from a device work queue in the order of `descs`; `grid` = CU count, and
 // each CU runs as many `block`-thread workgroups as the LDS allows.
 hipError_t prepare_batch_lds();  // once per process, before the first launch
-hipError_t launch_batch_lds(const GraphDesc* descs, const int32_t* order, int32_t count,
-                            int32_t max_n, int32_t* queue_head, int32_t* status, bool halve,
-                            int grid, hipStream_t s, int block = 1024);
+hipError_t launch_batch_lds(const GraphDesc* descs, int32_t count, int32_t max_n,
+                            int32_t* queue_head, int32_t* status, bool halve, int grid,
+                            hipStream_t s, int block = 1024);
 
 // Zeroes `words` 32-bit words with a kernel (graph-capture friendly).
 hipError_t launch_zero(void* p, int64_t words, hipStream_t s);

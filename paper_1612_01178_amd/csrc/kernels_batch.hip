@@ -131,8 +131,10 @@ __device__ __forceinline__ void edge_step_loads(g_cint* du, g_cint* dv, int64_t 
 }
 
 // One graph by the whole workgroup (called by every thread): init, then per
-// segment Atomic-Hook of its entries and Multi-Jump of its vertices, then the
-// labels.  Sets `bad` on an endpoint outside [0, n).
+// segment Atomic-Hook of its entries and Multi-Jump of its vertices; the last
+// Multi-Jump writes the labels instead of storing the roots in LDS.  Sets
+// `bad` on an endpoint outside [0, n).  Returns without a final barrier: the
+// caller's next barrier separates the label reads from the next graph's init.
 template <typename T>
 __device__ __forceinline__ void solve_graph(T* spi, const GraphDesc& d, bool halve, bool& bad) {
     const uint32_t tid = threadIdx.x;
@@ -182,7 +184,9 @@ __device__ __forceinline__ void solve_graph(T* spi, const GraphDesc& d, bool hal
         // Multi-Jump (Fig. 3, bottom) over the graph's vertices, low ids first.
         // Each vertex climbs to its root and stores it once (a root stores
         // itself); no hook runs in this phase, so only the stores of other
-        // climbers race with it, and each stores an ancestor.
+        // climbers race with it, and each stores an ancestor.  After the last
+        // segment the root is the label: it goes to global memory only.
+        const bool last = seg + 1 == s;
         for (uint32_t x = tid; x < n; x += nthr) {
             uint32_t p = lds_ld(spi, x);
             uint32_t g = lds_ld(spi, p);
@@ -190,34 +194,43 @@ __device__ __forceinline__ void solve_graph(T* spi, const GraphDesc& d, bool hal
                 p = g;
                 g = lds_ld(spi, p);
             }
-            lds_st(spi, x, p);
+            if (last)
+                dout[x] = (int32_t)p;
+            else
+                lds_st(spi, x, p);
         }
-        __syncthreads();
+        if (!last) __syncthreads();
     }
-    for (uint32_t x = tid; x < n; x += nthr) dout[x] = (int32_t)lds_ld(spi, x);
-    __syncthreads();
 }
 
 __global__ __launch_bounds__(1024) void k_batch_lds(const GraphDesc* __restrict__ descs,
-                                                    const int32_t* __restrict__ order,
                                                     int32_t count, int32_t* queue_head,
                                                     int32_t* status, bool halve) {
     extern __shared__ uint16_t spi[];
     __shared__ int32_t next;
     bool bad = false;
-    while (true) {
-        if (threadIdx.x == 0) next = atomicAdd(queue_head, 1);
-        __syncthreads();
-        const int32_t idx = next;
-        __syncthreads();  // everyone has read `next` before thread 0 may overwrite it
-        if (idx >= count) break;
-        const GraphDesc d = descs[order[idx]];
+    if (threadIdx.x == 0) next = atomicAdd(queue_head, 1);
+    __syncthreads();
+    int32_t idx = next;
+    while (idx < count) {
+        const GraphDesc d = descs[idx];
+        // The next position is fetched while this graph is solved, so the
+        // queue's latency is paid once per workgroup, not once per graph.
+        // Thread 0 writes `next` again only after the barriers inside
+        // solve_graph, which every thread passes after reading it.
+        int32_t pre = 0;
+        if (threadIdx.x == 0) pre = atomicAdd(queue_head, 1);
         if ((uint32_t)d.n <= kWideMaxN)
             solve_graph(reinterpret_cast<uint32_t*>(spi), d, halve, bad);
         else
             solve_graph(spi, d, halve, bad);
+        if (threadIdx.x == 0) next = pre;
+        __syncthreads();
+        idx = next;
     }
-    if (bad) atomicOr(status, kStatusRange);
+    // status may be host memory: a plain store (every writer stores the same
+    // bit) visible to the host once the launch has completed
+    if (bad) __hip_atomic_store(status, kStatusRange, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_SYSTEM);
 }
 
 // Window round of the hybrid plan (an atomic-free Hook round, Fig. 2, with
@@ -371,9 +384,9 @@ hipError_t prepare_batch_lds() {
     return once;
 }
 
-hipError_t launch_batch_lds(const GraphDesc* descs, const int32_t* order, int32_t count,
-                            int32_t max_n, int32_t* queue_head, int32_t* status, bool halve,
-                            int grid, hipStream_t s, int block) {
+hipError_t launch_batch_lds(const GraphDesc* descs, int32_t count, int32_t max_n,
+                            int32_t* queue_head, int32_t* status, bool halve, int grid,
+                            hipStream_t s, int block) {
     if (count <= 0) return hipSuccess;
     if (max_n < 1 || max_n > 65536) return hipErrorInvalidValue;
     if (block < 64 || block > 1024 || block % 64) return hipErrorInvalidValue;
@@ -383,7 +396,7 @@ hipError_t launch_batch_lds(const GraphDesc* descs, const int32_t* order, int32_
     // thread limits), at most 32 waves per CU
     const int per_cu = (int)std::max<size_t>(1, std::min<size_t>((size_t)(160 * 1024) / lds,
                                                                  (size_t)(2048 / block)));
-    k_batch_lds<<<grid * per_cu, block, lds, s>>>(descs, order, count, queue_head, status, halve);
+    k_batch_lds<<<grid * per_cu, block, lds, s>>>(descs, count, queue_head, status, halve);
     return hipGetLastError();
 }
 

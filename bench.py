@@ -683,11 +683,35 @@ def bench_batch(cc, torch, dev, num_graphs=10000, reps=5, tune=True, loop=True):
     side.synchronize()
     dt_graph = (time.perf_counter() - t) / reps
     parity = parity and digest(out.cpu().numpy()) == golden["batch10k"]["sha256"]
+    # offsets in device memory (cc_labels_batch_device): the graphs are
+    # checked, ordered and described on the device, no host pass per call
+    dvo = torch.from_numpy(vo).to(dev)
+    deo = torch.from_numpy(eo).to(dev)
+    max_n = int(np.diff(vo).max())
+    dev_res = {}
+    for name, o, st in (("eager", bopt, None), ("graph_replay", gopt, side)):
+        out.fill_(-1)
+        torch.cuda.synchronize()
+        for _ in range(2):
+            cc.labels_batch_device(u, v, dvo, deo, max_n, out, options=o, stream=st)
+        torch.cuda.synchronize()
+        t = time.perf_counter()
+        for _ in range(reps):
+            cc.labels_batch_device(u, v, dvo, deo, max_n, out, options=o, stream=st)
+        torch.cuda.synchronize()
+        dtd = (time.perf_counter() - t) / reps
+        ok = digest(out.cpu().numpy()) == golden["batch10k"]["sha256"]
+        parity = parity and ok
+        dev_res[name] = {"ms_per_batch": dtd * 1e3, "graphs_per_s": num_graphs / dtd,
+                         "parity_vs_oracle_digest": bool(ok)}
+    log("batch, device offsets: %.3f ms per call (%.3f ms replayed)"
+        % (dev_res["eager"]["ms_per_batch"], dev_res["graph_replay"]["ms_per_batch"]))
     if not loop:
         m = int(eo[-1])
         return {"workload": "batch10k", "graphs": num_graphs, "ms_per_batch": dt * 1e3,
                 "ms_per_batch_graph_replay": dt_graph * 1e3, "graphs_per_s": num_graphs / dt,
-                "edges_per_s": m / dt, "parity_vs_oracle_digest": bool(parity)}
+                "edges_per_s": m / dt, "device_offsets": dev_res,
+                "parity_vs_oracle_digest": bool(parity)}
     # baseline: one synchronous cc_labels call per graph on the same resident data
     lib = cc.load()
     base_u, base_v, base_o = u.data_ptr(), v.data_ptr(), out.data_ptr()
@@ -712,7 +736,7 @@ def bench_batch(cc, torch, dev, num_graphs=10000, reps=5, tune=True, loop=True):
                                                           o["block"] or 1024): round(t, 4)
                          for t, o in btable},
             "graphs_per_s": num_graphs / dt, "edges_per_s": m / dt, "ms_per_batch": dt * 1e3,
-            "ms_per_batch_graph_replay": dt_graph * 1e3,
+            "ms_per_batch_graph_replay": dt_graph * 1e3, "device_offsets": dev_res,
             "loop_graphs_per_s": num_graphs / dt_loop, "speedup_vs_loop": dt_loop / dt,
             "parity_vs_oracle_digest": bool(parity and loop_parity),
             "hbm_frac": round((8.0 * m + 4.0 * int(vo[-1])) / dt / 1e9 / HBM_PEAK_GBS, 4)}

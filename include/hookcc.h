@@ -306,6 +306,30 @@ int32_t cc_labels_batch_ex(int32_t num_graphs, const int64_t* vtx_off, const int
                            const int32_t* edges_u, const int32_t* edges_v, int32_t* out_label,
                            const cc_options* opts, void* stream, cc_stats* stats);
 
+/* As cc_labels_batch_ex with the offsets in DEVICE memory: the batch needs
+ * no host pass at all.  One preparation workgroup reads the offsets, checks
+ * them, orders the graphs largest first (a counting sort on the size class
+ * of m_g + n_g, as the host-offset call does) and writes their descriptors;
+ * then the persistent LDS launch solves them.  A call is two launches and
+ * one synchronisation on `stream`, whatever the number of graphs.
+ *   vtx_off, edge_off  [device] int64[B+1], as for cc_labels_batch
+ *   edges_u/v          [device] int32[edge_off[B]], local ids
+ *   out_label          [device] int32[vtx_off[B]]
+ *   max_n              an upper bound of every graph's vertex count, in
+ *                      [1, CC_BATCH_LDS_MAX_N]: it sizes the launch's LDS (a
+ *                      tight bound lets several workgroups share a CU)
+ * Every graph is LDS-solved: offsets that do not start at 0, decrease, or
+ * give a graph more than max_n vertices are found on the device; then no
+ * label is written for the offending graphs and the call returns
+ * CC_ERR_ARG after the synchronisation.  `opts` (nullable) takes
+ * `segments`, `path_halving`, `block` and `graph` as for cc_labels_batch_ex;
+ * the device memory it needs (256 + 40 B per graph) comes from the stream's
+ * pool.  Returns CC_OK, CC_ERR_ARG, CC_ERR_RANGE, CC_ERR_NOMEM or CC_ERR_HIP. */
+int32_t cc_labels_batch_device(int32_t num_graphs, const int64_t* vtx_off,
+                               const int64_t* edge_off, const int32_t* edges_u,
+                               const int32_t* edges_v, int32_t* out_label, int32_t max_n,
+                               const cc_options* opts, void* stream, cc_stats* stats);
+
 /* Out-of-core solve: the edge lists stay in HOST memory and are streamed to
  * the device in chunks while earlier chunks are hooked.  The Atomic-Hook
  * reads every entry exactly once (Section 3.A), so each chunk is copied once

@@ -37,7 +37,7 @@ _HOST_LOOPS = {"off": 0, "jump": 1, "multijump": 2}
 
 # Every symbol include/hookcc.h declares.
 EXPORTS = ("cc_options_init", "cc_labels", "cc_labels_ex", "cc_workspace_bytes", "cc_labels_noalloc",
-           "cc_labels_batch", "cc_labels_batch_ex", "cc_labels_list", "cc_labels_host", "cc_labels_csr", "cc_probe",
+           "cc_labels_batch", "cc_labels_batch_ex", "cc_labels_batch_device", "cc_labels_list", "cc_labels_host", "cc_labels_csr", "cc_probe",
            "cc_last_error", "cc_release", "cc_version", "cc_stream_status", "cc_server_create",
            "cc_server_submit", "cc_server_submit_on", "cc_server_wait", "cc_server_poll", "cc_server_stats",
            "cc_server_destroy", "cc_server_clock")
@@ -169,6 +169,10 @@ def load():
                                                ctypes.POINTER(_COptions), _vp,
                                                ctypes.POINTER(_CStats)]
             lib.cc_labels_batch_ex.restype = _i32
+            lib.cc_labels_batch_device.argtypes = [_i32, _vp, _vp, _vp, _vp, _vp, _i32,
+                                                   ctypes.POINTER(_COptions), _vp,
+                                                   ctypes.POINTER(_CStats)]
+            lib.cc_labels_batch_device.restype = _i32
             lib.cc_labels_list.argtypes = [_i32, ctypes.POINTER(_CGraph), ctypes.POINTER(_COptions),
                                            _vp, ctypes.POINTER(_CStats)]
             lib.cc_labels_list.restype = _i32
@@ -377,6 +381,40 @@ def labels_batch(u, v, vtx_off, edge_off, *, out=None, options: Options | None =
         rc = load().cc_labels_batch_ex(len(vo) - 1, vo.ctypes.data, eo.ctypes.data, u.data_ptr(),
                                        v.data_ptr(), out.data_ptr(), ctypes.byref(opts),
                                        _stream_handle(stream), ctypes.byref(st))
+    _check(rc)
+    if return_stats:
+        return out, {f: getattr(st, f) for f, _ in _CStats._fields_ if f != "reserved"}
+    return out
+
+
+def labels_batch_device(u, v, vtx_off, edge_off, max_n: int, out, *,
+                        options: Options | None = None, stream=None,
+                        return_stats: bool = False):
+    """labels_batch with the offsets in device memory (int64 CUDA tensors of
+    length B+1): the graphs are checked, ordered and described on the device,
+    so a call does no host work per graph.  ``max_n`` bounds every graph's
+    vertex count (at most CC_BATCH_LDS_MAX_N); ``out`` is the int32 CUDA
+    tensor of vtx_off[-1] labels (its length is not checked: reading it
+    would need a synchronisation)."""
+    import torch
+    u = _edge_tensor(u, "u")
+    v = _edge_tensor(v, "v")
+    for name, t in (("vtx_off", vtx_off), ("edge_off", edge_off)):
+        if (not isinstance(t, torch.Tensor) or t.dtype != torch.int64 or t.device != u.device
+                or t.dim() != 1 or not t.is_contiguous()):
+            raise TypeError("%s must be a contiguous 1-D int64 tensor on the edges' device" % name)
+    if vtx_off.numel() != edge_off.numel() or vtx_off.numel() < 1:
+        raise ValueError("vtx_off and edge_off must be of equal length B+1")
+    if u.numel() != v.numel():
+        raise ValueError("len(u) must equal len(v)")
+    out = _edge_tensor(out, "out")
+    st = _CStats()
+    with _on_device(u.device):
+        rc = load().cc_labels_batch_device(vtx_off.numel() - 1, vtx_off.data_ptr(),
+                                           edge_off.data_ptr(), u.data_ptr(), v.data_ptr(),
+                                           out.data_ptr(), int(max_n),
+                                           ctypes.byref(_c_options(options)),
+                                           _stream_handle(stream), ctypes.byref(st))
     _check(rc)
     if return_stats:
         return out, {f: getattr(st, f) for f, _ in _CStats._fields_ if f != "reserved"}

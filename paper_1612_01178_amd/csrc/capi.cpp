@@ -50,6 +50,14 @@ int32_t cc_labels_batch_ex(int32_t num_graphs, const int64_t* vtx_off, const int
                       static_cast<hipStream_t>(stream), stats);
 }
 
+int32_t cc_labels_batch_device(int32_t num_graphs, const int64_t* vtx_off,
+                               const int64_t* edge_off, const int32_t* edges_u,
+                               const int32_t* edges_v, int32_t* out_label, int32_t max_n,
+                               const cc_options* opts, void* stream, cc_stats* stats) {
+    return batch_device_impl(num_graphs, vtx_off, edge_off, edges_u, edges_v, out_label, max_n,
+                             opts, static_cast<hipStream_t>(stream), stats);
+}
+
 int32_t cc_labels_list(int32_t count, const cc_graph* graphs, const cc_options* opts, void* stream,
                        cc_stats* stats) {
     return list_impl(count, graphs, opts, static_cast<hipStream_t>(stream), stats, nullptr, 0,

@@ -33,6 +33,7 @@ static_assert(sizeof(Ctrl) == 256, "control block is one 256-byte line");
 
 constexpr int32_t kStatusRange = 1;
 constexpr int32_t kStatusOverflow = 2;
+constexpr int32_t kStatusBadGraph = 4;  // batch offsets: not from 0, decreasing, or n > max_n
 
 // Graph descriptor used by the batched kernels (one per graph, in device
 // memory).  Endpoints are local ids in [0, n); labels are local.

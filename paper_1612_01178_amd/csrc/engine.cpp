@@ -1420,6 +1420,74 @@ int32_t batch_impl(int32_t B, const int64_t* vo, const int64_t* eo, const int32_
     return list_core(B, graph_at, opts, s, st, nullptr, 0, nullptr);
 }
 
+// Device offsets: the preparation workgroup builds the descriptors and the
+// largest-first order on the device (no host pass over the graphs), then the
+// persistent LDS launch solves them; one synchronisation.
+int32_t batch_device_impl(int32_t B, const int64_t* vo, const int64_t* eo, const int32_t* u,
+                          const int32_t* v, int32_t* out, int32_t max_n, const cc_options* opts,
+                          hipStream_t s, cc_stats* st) {
+    if (B < 0) return fail(CC_ERR_ARG, "num_graphs < 0");
+    if (opts && opts->no_sync)
+        return fail(CC_ERR_ARG, "cc_options.no_sync is for cc_labels_ex and cc_labels_csr only");
+    const int32_t ph = opts ? opts->path_halving : CC_HALVE_AUTO;
+    if (ph < CC_HALVE_AUTO || ph > CC_HALVE_OFF) return fail(CC_ERR_ARG, "unknown cc_options.path_halving");
+    const bool lds_halve = ph != CC_HALVE_OFF;
+    int32_t seg_cap = opts ? opts->segments : 0;
+    if (seg_cap < 0) return fail(CC_ERR_ARG, "cc_options.segments < 0");
+    if (seg_cap == 0 && lds_halve) seg_cap = 2;
+    const int32_t lds_block = (opts && opts->block) ? opts->block : 1024;
+    if (lds_block < 64 || lds_block > 1024 || lds_block % 64)
+        return fail(CC_ERR_ARG, "cc_options.block must be a multiple of 64 in [64, 1024]");
+    if (max_n < 1 || max_n > CC_BATCH_LDS_MAX_N)
+        return fail(CC_ERR_ARG, "max_n must be in [1, CC_BATCH_LDS_MAX_N]");
+    if (st) {
+        std::memset(st, 0, sizeof *st);
+        st->giant_label = -1;
+    }
+    if (B == 0) return CC_OK;
+    if (!vo || !eo || !u || !v || !out) return fail(CC_ERR_ARG, "null offsets, edges or labels");
+    if ((size_t)B > (SIZE_MAX - sizeof(Ctrl)) / sizeof(GraphDesc)) return fail(CC_ERR_ARG, "too many graphs");
+    const size_t desc_off = sizeof(Ctrl);
+    const size_t total = desc_off + align256((size_t)B * sizeof(GraphDesc));
+    HIPCHK(prepare_batch_lds());
+    PoolEntry* pe = pool_entry(s);
+    std::lock_guard<std::mutex> lk(pe->mu);
+    int32_t rc = ensure_dev(pe, total);
+    if (rc != CC_OK) return rc;
+    if (!pe->batch_status)
+        HIPCHK(hipHostMalloc((void**)&pe->batch_status, 256, hipHostMallocDefault));
+    pe->batch_status[0] = pe->batch_status[1] = 0;
+    char* ws = static_cast<char*>(pe->dev);
+    Ctrl* ctrl = reinterpret_cast<Ctrl*>(ws);
+    GraphDesc* descs = reinterpret_cast<GraphDesc*>(ws + desc_off);
+    auto enqueue = [&]() -> int32_t {
+        HIPCHK(launch_batch_prep(vo, eo, B, u, v, out, max_n, seg_cap, descs, ctrl,
+                                 pe->batch_status, s));
+        HIPCHK(launch_batch_lds(descs, B, max_n, &ctrl->queue_head, pe->batch_status, lds_halve,
+                                device_cu_count(), s, lds_block));
+        return CC_OK;
+    };
+    if (opts && opts->graph == 1 && s != nullptr) {
+        KeyHash k;
+        k.add(uint64_t(0xba7c4de71ce)).add(B).add(vo).add(eo).add(u).add(v).add(out).add(max_n)
+            .add(seg_cap).add(lds_halve).add(lds_block).add(ws).add(s);
+        rc = run_graph(pe, k.h, s, enqueue);
+    } else {
+        rc = enqueue();
+    }
+    if (rc != CC_OK) return rc;
+    if (st) st->hook_launches += 1;
+    HIPCHK(hipStreamSynchronize(s));
+    if (st) st->host_syncs += 1;
+    const int32_t prep = *(volatile int32_t*)(pe->batch_status + 1);
+    const int32_t solve = *(volatile int32_t*)pe->batch_status;
+    if (prep & kStatusBadGraph)
+        return fail(CC_ERR_ARG, "batch offsets must start at 0, be non-decreasing and give "
+                                "every graph at most max_n vertices");
+    if ((prep | solve) & kStatusRange) return fail(CC_ERR_RANGE, "edge endpoint outside [0, n_g)");
+    return CC_OK;
+}
+
 // ---------------------------------------------------------------------- probes, release
 int32_t probe_impl(int32_t mode, const int32_t* u, const int32_t* v, int64_t m, const void* table,
                    int32_t n, hipStream_t s) {

@@ -37,6 +37,12 @@ int32_t batch_impl(int32_t B, const int64_t* vo, const int64_t* eo, const int32_
                    const int32_t* v, int32_t* out, const cc_options* opts, hipStream_t s,
                    cc_stats* st);
 
+// Graphs packed back to back with DEVICE offsets, all LDS-solved (n <= max_n
+// <= CC_BATCH_LDS_MAX_N); ordered and described on the device; synchronous on s.
+int32_t batch_device_impl(int32_t B, const int64_t* vo, const int64_t* eo, const int32_t* u,
+                          const int32_t* v, int32_t* out, int32_t max_n, const cc_options* opts,
+                          hipStream_t s, cc_stats* st);
+
 // Edges in host memory, streamed in chunks (see engine.cpp).
 int32_t stream_impl(int32_t n, const int32_t* hu, const int32_t* hv, int64_t m, int32_t* out,
                     int64_t chunk, const cc_options* opts, hipStream_t s, cc_stats* st);

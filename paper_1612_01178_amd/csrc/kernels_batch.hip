@@ -233,6 +233,145 @@ __global__ __launch_bounds__(1024) void k_batch_lds(const GraphDesc* __restrict_
     if (bad) __hip_atomic_store(status, kStatusRange, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_SYSTEM);
 }
 
+// ---------------------------------------------------------------------------
+// Preparation of a batch whose offsets are in device memory (one workgroup):
+// checks every graph, orders the graphs largest first by a counting sort on
+// the size class of m + n (four classes per power of two, the order the
+// host-offset call builds), and writes their descriptors for k_batch_lds.
+// A graph whose offsets are invalid (not starting at 0, decreasing, more
+// than max_n vertices) or that has entries but no vertex gets an empty
+// descriptor (nothing is read or written for it) and its status bit goes to
+// status[1] (host memory: a plain store, visible once the launch is done).
+// Then k_batch_lds takes its queue from ctrl->queue_head, cleared here.
+
+__device__ __forceinline__ int batch_size_class(uint64_t w) {
+    w |= 1;
+    const int lg = 63 - __clzll((long long)w);
+    const int frac = lg >= 2 ? (int)((w >> (lg - 2)) & 3) : (int)((w << (2 - lg)) & 3);
+    return lg * 4 + frac;
+}
+
+// min(cap, round(m / n)), at least 1 (cap 0: round(m / n) up to 2^20)
+__device__ __forceinline__ int32_t batch_segments(int64_t m, int64_t n, int32_t cap) {
+    if (cap > 0 && cap <= 16 && m < (int64_t(1) << 61)) {
+        int32_t k = cap;
+        while (k > 1 && 2 * m < (2 * (int64_t)k - 1) * n) --k;
+        return k;
+    }
+    int64_t r = m / n + ((m % n) * 2 >= n ? 1 : 0);
+    r = r < 1 ? 1 : (r > (int64_t(1) << 20) ? (int64_t(1) << 20) : r);
+    return cap > 0 && r > cap ? cap : (int32_t)r;
+}
+
+constexpr int kPrepUnroll = 8;  // graphs per thread whose offsets are loaded together
+
+struct PrepGraph {
+    int64_t v0, n, e0, m;
+    int32_t cls;   // position class: 0 = largest
+    int32_t flag;  // 0, kStatusBadGraph or kStatusRange
+};
+
+__device__ __forceinline__ PrepGraph prep_graph(int64_t v0, int64_t v1, int64_t e0, int64_t e1,
+                                                bool first, int32_t max_n) {
+    PrepGraph p;
+    p.v0 = v0;
+    p.e0 = e0;
+    p.n = v1 - v0;
+    p.m = e1 - e0;
+    p.flag = 0;
+    if ((first && (v0 != 0 || e0 != 0)) || p.n < 0 || p.m < 0 || p.n > max_n)
+        p.flag = kStatusBadGraph;
+    else if (p.n == 0 && p.m > 0)
+        p.flag = kStatusRange;
+    if (p.flag) p.n = p.m = 0;
+    p.cls = 255 - batch_size_class((uint64_t)p.m + (uint64_t)p.n);
+    return p;
+}
+
+__global__ __launch_bounds__(1024) void k_batch_prep(const int64_t* __restrict__ vo,
+                                                     const int64_t* __restrict__ eo, int32_t B,
+                                                     const int32_t* u, const int32_t* v,
+                                                     int32_t* out, int32_t max_n, int32_t seg_cap,
+                                                     GraphDesc* __restrict__ descs, Ctrl* ctrl,
+                                                     int32_t* status) {
+    __shared__ int32_t start[256];
+    __shared__ int32_t flags;
+    const int32_t tid = threadIdx.x, nthr = blockDim.x;
+    for (int32_t c = tid; c < 256; c += nthr) start[c] = 0;
+    if (tid == 0) {
+        flags = 0;
+        ctrl->queue_head = 0;
+    }
+    __syncthreads();
+    // pass 1: class histogram; pass 2: scatter.  Offsets of kPrepUnroll
+    // graphs per thread are loaded before any is used (indices clamped to
+    // the last graph, so every load is in bounds).
+    for (int pass = 0; pass < 2; ++pass) {
+        int32_t flag = 0;
+        for (int64_t g0 = 0; g0 < B; g0 += (int64_t)nthr * kPrepUnroll) {
+            int64_t a0[kPrepUnroll], a1[kPrepUnroll], b0[kPrepUnroll], b1[kPrepUnroll];
+#pragma unroll
+            for (int j = 0; j < kPrepUnroll; ++j) {
+                const int64_t g = min(g0 + tid + (int64_t)j * nthr, (int64_t)B - 1);
+                a0[j] = vo[g];
+                a1[j] = vo[g + 1];
+                b0[j] = eo[g];
+                b1[j] = eo[g + 1];
+            }
+#pragma unroll
+            for (int j = 0; j < kPrepUnroll; ++j) {
+                const int64_t g = g0 + tid + (int64_t)j * nthr;
+                if (g >= B) continue;
+                const PrepGraph p = prep_graph(a0[j], a1[j], b0[j], b1[j], g == 0, max_n);
+                if (pass == 0) {
+                    atomicAdd(&start[p.cls], 1);
+                    continue;
+                }
+                flag |= p.flag;
+                const int32_t pos = atomicAdd(&start[p.cls], 1);
+                GraphDesc d;
+                d.u = u + p.e0;
+                d.v = v + p.e0;
+                d.out = out + p.v0;
+                d.m = p.m;
+                d.n = (int32_t)p.n;
+                d.segments = p.n > 0 ? batch_segments(p.m, p.n, seg_cap) : 1;
+                descs[pos] = d;
+            }
+        }
+        if (pass == 1 && flag) atomicOr(&flags, flag);
+        __syncthreads();
+        if (pass == 0 && tid < 64) {
+            // exclusive scan of the 256 counts: 4 per lane, then across the wave
+            const int32_t c0 = start[4 * tid], c1 = start[4 * tid + 1], c2 = start[4 * tid + 2],
+                          c3 = start[4 * tid + 3];
+            const int32_t sum = c0 + c1 + c2 + c3;
+            int32_t inc = sum;
+#pragma unroll
+            for (int d = 1; d < 64; d <<= 1) {
+                const int32_t t = __shfl_up(inc, d, 64);
+                if (tid >= d) inc += t;
+            }
+            const int32_t ex = inc - sum;
+            start[4 * tid] = ex;
+            start[4 * tid + 1] = ex + c0;
+            start[4 * tid + 2] = ex + c0 + c1;
+            start[4 * tid + 3] = ex + c0 + c1 + c2;
+        }
+        __syncthreads();
+    }
+    if (tid == 0 && flags)
+        __hip_atomic_store(status + 1, flags, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_SYSTEM);
+}
+
+hipError_t launch_batch_prep(const int64_t* vo, const int64_t* eo, int32_t B, const int32_t* u,
+                             const int32_t* v, int32_t* out, int32_t max_n, int32_t seg_cap,
+                             GraphDesc* descs, Ctrl* ctrl, int32_t* status, hipStream_t s) {
+    if (B <= 0) return hipSuccess;
+    k_batch_prep<<<1, 1024, 0, s>>>(vo, eo, B, u, v, out, max_n, seg_cap, descs, ctrl, status);
+    return hipGetLastError();
+}
+
 // Window round of the hybrid plan (an atomic-free Hook round, Fig. 2, with
 // the Hook of each workgroup's chunk done in LDS; beyond the paper).
 // Workgroup w takes entries [w * kWinEntries, (w + 1) * kWinEntries) and a

@@ -148,6 +148,23 @@ static void abi_validation() {
     cc_options_init(&o);
     o.block = 100;
     CHECK(cc_labels_batch_ex(1, vo3, eo3, d, d, d, &o, nullptr, nullptr) == CC_ERR_ARG);
+    // batches with device offsets: argument checks made before any launch
+    CHECK(cc_labels_batch_device(-1, d64, d64, d, d, d, 8, nullptr, nullptr, nullptr) == CC_ERR_ARG);
+    CHECK(cc_labels_batch_device(0, nullptr, nullptr, nullptr, nullptr, nullptr, 8, nullptr,
+                                 nullptr, nullptr) == CC_OK);
+    CHECK(cc_labels_batch_device(2, d64, d64, d, d, d, 0, nullptr, nullptr, nullptr) == CC_ERR_ARG);
+    CHECK(cc_labels_batch_device(2, d64, d64, d, d, d, CC_BATCH_LDS_MAX_N + 1, nullptr, nullptr,
+                                 nullptr) == CC_ERR_ARG);
+    CHECK(cc_labels_batch_device(2, nullptr, d64, d, d, d, 8, nullptr, nullptr, nullptr) == CC_ERR_ARG);
+    CHECK(cc_labels_batch_device(2, d64, d64, d, nullptr, d, 8, nullptr, nullptr, nullptr) == CC_ERR_ARG);
+    CHECK(cc_labels_batch_device(INT32_MAX, d64, d64, d, d, nullptr, 8, nullptr, nullptr, nullptr) ==
+          CC_ERR_ARG);
+    cc_options_init(&o);
+    o.block = 96;
+    CHECK(cc_labels_batch_device(2, d64, d64, d, d, d, 8, &o, nullptr, nullptr) == CC_ERR_ARG);
+    cc_options_init(&o);
+    o.no_sync = 1;
+    CHECK(cc_labels_batch_device(2, d64, d64, d, d, d, 8, &o, nullptr, nullptr) == CC_ERR_ARG);
     cc_graph g[2];
     std::memset(g, 0, sizeof g);
     g[0].n = 4;

@@ -83,6 +83,10 @@ def to_dev(x, dev):
     return torch.from_numpy(np.ascontiguousarray(x, dtype=np.int32)).to(dev)
 
 
+def to_dev64(x, dev):
+    return torch.from_numpy(np.ascontiguousarray(x, dtype=np.int64)).to(dev)
+
+
 def solve(u, v, n, dev, options=None, offset=0):
     """GPU labels as numpy.  ``offset`` shifts the edge arrays inside a larger
     allocation so that their base is not 16-byte aligned."""
@@ -326,6 +330,114 @@ def test_batch_range_error(dev):
     assert ei.value.code == cc.CC_ERR_RANGE
 
 
+def _batch_device(u, v, vo, eo, dev, max_n, options=None, stream=None):
+    import torch
+    # as many labels as the largest offset, so that invalid offsets never
+    # make a valid graph's labels land outside the tensor
+    out = torch.full((max(int(np.max(vo)), 1),), -1, dtype=torch.int32, device=dev)
+    dvo, deo = to_dev64(vo, dev), to_dev64(eo, dev)
+    return cc.labels_batch_device(to_dev(u, dev), to_dev(v, dev), dvo, deo, max_n, out,
+                                  options=options, stream=stream)
+
+
+def test_batch_device_offsets_match_oracle(dev):
+    """Offsets in device memory: graphs ordered and described on the device.
+    Empty graphs, single vertices, every slot width (32-bit up to 32,768
+    vertices, 16-bit above) and every segment schedule equal the oracle."""
+    rng = np.random.default_rng(18)
+    sizes = [0, 1, 2, 300, 65536, 7, 40000, 0, 1000, 32768, 32769, 5]
+    us, vs, vo, eo = [], [], [0], [0]
+    for i, n in enumerate(sizes):
+        m = 0 if n == 0 else int(rng.integers(0, 3 * n + 2))
+        uu, vv = graphgen.uniform_pairs(m, max(n, 1), seed=150 + i, stream=0)
+        us.append(uu)
+        vs.append(vv)
+        vo.append(vo[-1] + n)
+        eo.append(eo[-1] + m)
+    u, v = np.concatenate(us), np.concatenate(vs)
+    vo, eo = np.array(vo, np.int64), np.array(eo, np.int64)
+    want = oracle.labels_batch(u, v, vo, eo)
+    for opt in (None, cc.Options(segments=1), cc.Options(segments=5, path_halving="off"),
+                cc.Options(segments=0, path_halving="off"), cc.Options(block=256)):
+        say("batch device offsets", opt)
+        got = _batch_device(u, v, vo, eo, dev, 65536, options=opt).cpu().numpy()
+        assert np.array_equal(got, want), opt
+    # a tight bound on the vertex count (smaller LDS, more workgroups per CU)
+    small = [i for i, n in enumerate(sizes) if n <= 1000]
+    su = np.concatenate([us[i] for i in small])
+    sv = np.concatenate([vs[i] for i in small])
+    svo = np.concatenate([[0], np.cumsum([sizes[i] for i in small])]).astype(np.int64)
+    seo = np.concatenate([[0], np.cumsum([len(us[i]) for i in small])]).astype(np.int64)
+    got = _batch_device(su, sv, svo, seo, dev, 1000).cpu().numpy()
+    assert np.array_equal(got, oracle.labels_batch(su, sv, svo, seo))
+    # exhaustive tiny graphs, the same as the host-offset test
+    graphs = []
+    for n in range(1, 6):
+        pairs = list(itertools.combinations(range(n), 2))
+        for mask in range(1 << len(pairs)):
+            graphs.append((n, [pairs[k] for k in range(len(pairs)) if mask >> k & 1]))
+    tvo = np.concatenate([[0], np.cumsum([n for n, _ in graphs])]).astype(np.int64)
+    teo = np.concatenate([[0], np.cumsum([len(c) for _, c in graphs])]).astype(np.int64)
+    tu = np.array([b for _, c in graphs for _, b in c], np.int32)
+    tv = np.array([a for _, c in graphs for a, _ in c], np.int32)
+    want = np.concatenate([pins.closure_labels(tu[teo[g]:teo[g + 1]], tv[teo[g]:teo[g + 1]], n)
+                           for g, (n, _) in enumerate(graphs)])
+    assert np.array_equal(_batch_device(tu, tv, tvo, teo, dev, 5).cpu().numpy(), want)
+
+
+def test_batch_device_offsets_errors_and_replays(dev):
+    import torch
+    u = np.array([0, 1, 1, 2], np.int32)
+    v = np.array([1, 2, 0, 3], np.int32)
+    vo = np.array([0, 3, 7], np.int64)
+    eo = np.array([0, 2, 4], np.int64)
+    want = oracle.labels_batch(u, v, vo, eo)
+    assert np.array_equal(_batch_device(u, v, vo, eo, dev, 4).cpu().numpy(), want)
+    # a graph above max_n: CC_ERR_ARG, no label written for it, the others solved
+    with pytest.raises(cc.CCError) as ei:
+        _batch_device(u, v, vo, eo, dev, 3)
+    assert ei.value.code == cc.CC_ERR_ARG
+    out = torch.full((7,), -1, dtype=torch.int32, device=dev)
+    dvo, deo = to_dev64(vo, dev), to_dev64(eo, dev)
+    with pytest.raises(cc.CCError):
+        cc.labels_batch_device(to_dev(u, dev), to_dev(v, dev), dvo, deo, 3, out)
+    got = out.cpu().numpy()
+    assert np.array_equal(got[:3], want[:3]) and (got[3:] == -1).all()
+    # offsets that decrease or do not start at 0
+    for bad_vo, bad_eo in (([0, 5, 4], [0, 2, 4]), ([1, 3, 7], [0, 2, 4]), ([0, 3, 7], [0, 3, 2])):
+        with pytest.raises(cc.CCError) as ei:
+            _batch_device(u, v, np.array(bad_vo, np.int64), np.array(bad_eo, np.int64), dev, 8)
+        assert ei.value.code == cc.CC_ERR_ARG, (bad_vo, bad_eo)
+    # an endpoint outside its graph, and entries in a graph without vertices
+    with pytest.raises(cc.CCError) as ei:
+        _batch_device(np.array([0, 5], np.int32), np.array([1, 0], np.int32),
+                      np.array([0, 3, 7], np.int64), np.array([0, 1, 2], np.int64), dev, 4)
+    assert ei.value.code == cc.CC_ERR_RANGE
+    with pytest.raises(cc.CCError) as ei:
+        _batch_device(u, v, np.array([0, 0, 7], np.int64), eo, dev, 8)
+    assert ei.value.code == cc.CC_ERR_RANGE
+    # host-side argument checks
+    for mx in (0, 65537):
+        with pytest.raises(cc.CCError) as ei:
+            _batch_device(u, v, vo, eo, dev, mx)
+        assert ei.value.code == cc.CC_ERR_ARG
+    # a captured launch sequence replayed, with eager calls in between
+    bu, bv, bvo, beo = graphgen.batch_er(300, seed=85, lo_exp=6, hi_exp=16)
+    bwant = oracle.labels_batch(bu, bv, bvo, beo)
+    s = torch.cuda.Stream()
+    dbu, dbv, dbvo, dbeo = to_dev(bu, dev), to_dev(bv, dev), to_dev64(bvo, dev), to_dev64(beo, dev)
+    bout = torch.empty(int(bvo[-1]), dtype=torch.int32, device=dev)
+    for rep in range(4):
+        with torch.cuda.stream(s):
+            bout.fill_(-1)
+            cc.labels_batch_device(dbu, dbv, dbvo, dbeo, 65536, bout,
+                                   options=cc.Options(graph=True), stream=s)
+            got = bout.cpu().numpy()
+        assert np.array_equal(got, bwant), rep
+        assert np.array_equal(_batch_device(bu, bv, bvo, beo, dev, 65536).cpu().numpy(), bwant)
+        torch.cuda.synchronize()
+
+
 # ----------------------------------------------------------------------------- full size
 def _golden():
     with open(GOLDEN) as f:
@@ -428,6 +540,14 @@ def test_full_size_batch_matches_oracle_digest(dev):
                               options=cc.Options(segments=cap, path_halving=halve,
                                                  block=block)).cpu().numpy()
         assert digest(lab) == rec["sha256"], (cap, halve, block)
+    # the same batch with its offsets in device memory
+    dvo, deo = to_dev64(vo, dev), to_dev64(eo, dev)
+    out = torch.empty(int(vo[-1]), dtype=torch.int32, device=dev)
+    max_n = int(np.diff(vo).max())
+    for opt in (cc.Options(), cc.Options(segments=3, path_halving="off")):
+        out.fill_(-1)
+        lab = cc.labels_batch_device(du, dv, dvo, deo, max_n, out, options=opt).cpu().numpy()
+        assert digest(lab) == rec["sha256"], ("device offsets", opt)
 
 
 # ----------------------------------------------------------------------------- streamed (host edges)

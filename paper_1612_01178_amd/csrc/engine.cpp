@@ -1448,7 +1448,8 @@ int32_t batch_device_impl(int32_t B, const int64_t* vo, const int64_t* eo, const
     if (!vo || !eo || !u || !v || !out) return fail(CC_ERR_ARG, "null offsets, edges or labels");
     if ((size_t)B > (SIZE_MAX - sizeof(Ctrl)) / sizeof(GraphDesc)) return fail(CC_ERR_ARG, "too many graphs");
     const size_t desc_off = sizeof(Ctrl);
-    const size_t total = desc_off + align256((size_t)B * sizeof(GraphDesc));
+    const size_t rows_off = desc_off + align256((size_t)B * sizeof(GraphDesc));
+    const size_t total = rows_off + align256(((size_t)B + 1023) / 1024 * 256 * 4);
     HIPCHK(prepare_batch_lds());
     PoolEntry* pe = pool_entry(s);
     std::lock_guard<std::mutex> lk(pe->mu);
@@ -1456,12 +1457,13 @@ int32_t batch_device_impl(int32_t B, const int64_t* vo, const int64_t* eo, const
     if (rc != CC_OK) return rc;
     if (!pe->batch_status)
         HIPCHK(hipHostMalloc((void**)&pe->batch_status, 256, hipHostMallocDefault));
-    pe->batch_status[0] = pe->batch_status[1] = 0;
+    pe->batch_status[0] = pe->batch_status[1] = pe->batch_status[2] = 0;
     char* ws = static_cast<char*>(pe->dev);
     Ctrl* ctrl = reinterpret_cast<Ctrl*>(ws);
     GraphDesc* descs = reinterpret_cast<GraphDesc*>(ws + desc_off);
+    int32_t* rows = reinterpret_cast<int32_t*>(ws + rows_off);
     auto enqueue = [&]() -> int32_t {
-        HIPCHK(launch_batch_prep(vo, eo, B, u, v, out, max_n, seg_cap, descs, ctrl,
+        HIPCHK(launch_batch_prep(vo, eo, B, u, v, out, max_n, seg_cap, descs, rows, ctrl,
                                  pe->batch_status, s));
         HIPCHK(launch_batch_lds(descs, B, max_n, &ctrl->queue_head, pe->batch_status, lds_halve,
                                 device_cu_count(), s, lds_block));
@@ -1479,7 +1481,8 @@ int32_t batch_device_impl(int32_t B, const int64_t* vo, const int64_t* eo, const
     if (st) st->hook_launches += 1;
     HIPCHK(hipStreamSynchronize(s));
     if (st) st->host_syncs += 1;
-    const int32_t prep = *(volatile int32_t*)(pe->batch_status + 1);
+    const int32_t prep = *(volatile int32_t*)(pe->batch_status + 1) |
+                         *(volatile int32_t*)(pe->batch_status + 2);
     const int32_t solve = *(volatile int32_t*)pe->batch_status;
     if (prep & kStatusBadGraph)
         return fail(CC_ERR_ARG, "batch offsets must start at 0, be non-decreasing and give "

@@ -165,12 +165,14 @@ hipError_t launch_batch_lds(const GraphDesc* descs, int32_t count, int32_t max_n
                             int32_t* queue_head, int32_t* status, bool halve, int grid,
                             hipStream_t s, int block = 1024);
 
-// Descriptors of a batch with device offsets, largest first, in one
-// workgroup; clears ctrl->queue_head; status[1] gets kStatusBadGraph /
+// Descriptors of a batch with device offsets, largest first (two launches,
+// one thread per graph); `rows` is scratch of ceil(B / 1024) x 256 int32.
+// Clears ctrl->queue_head; status[1] / status[2] get kStatusBadGraph /
 // kStatusRange for invalid graphs (status may be pinned host memory).
 hipError_t launch_batch_prep(const int64_t* vo, const int64_t* eo, int32_t B, const int32_t* u,
                              const int32_t* v, int32_t* out, int32_t max_n, int32_t seg_cap,
-                             GraphDesc* descs, Ctrl* ctrl, int32_t* status, hipStream_t s);
+                             GraphDesc* descs, int32_t* rows, Ctrl* ctrl, int32_t* status,
+                             hipStream_t s);
 
 // Zeroes `words` 32-bit words with a kernel (graph-capture friendly).
 hipError_t launch_zero(void* p, int64_t words, hipStream_t s);

@@ -234,15 +234,16 @@ __global__ __launch_bounds__(1024) void k_batch_lds(const GraphDesc* __restrict_
 }
 
 // ---------------------------------------------------------------------------
-// Preparation of a batch whose offsets are in device memory (one workgroup):
-// checks every graph, orders the graphs largest first by a counting sort on
-// the size class of m + n (four classes per power of two, the order the
-// host-offset call builds), and writes their descriptors for k_batch_lds.
-// A graph whose offsets are invalid (not starting at 0, decreasing, more
-// than max_n vertices) or that has entries but no vertex gets an empty
-// descriptor (nothing is read or written for it) and its status bit goes to
-// status[1] (host memory: a plain store, visible once the launch is done).
-// Then k_batch_lds takes its queue from ctrl->queue_head, cleared here.
+// Preparation of a batch whose offsets are in device memory, in two launches
+// of one thread per graph: every graph is checked and given its size class
+// of m + n (four classes per power of two, the order the host-offset call
+// builds); the graphs are placed largest class first (a counting sort) and
+// their descriptors written for k_batch_lds.  A graph whose offsets are
+// invalid (not starting at 0, decreasing, more than max_n vertices) or that
+// has entries but no vertex gets an empty descriptor (nothing is read or
+// written for it); status[1] / status[2] (host memory) then receive
+// kStatusBadGraph / kStatusRange.  ctrl->queue_head is cleared for the
+// solve.
 
 __device__ __forceinline__ int batch_size_class(uint64_t w) {
     w |= 1;
@@ -263,7 +264,7 @@ __device__ __forceinline__ int32_t batch_segments(int64_t m, int64_t n, int32_t 
     return cap > 0 && r > cap ? cap : (int32_t)r;
 }
 
-constexpr int kPrepUnroll = 8;  // graphs per thread whose offsets are loaded together
+constexpr int kPrepGraphs = 1024;  // graphs per preparation workgroup, one per thread
 
 struct PrepGraph {
     int64_t v0, n, e0, m;
@@ -271,15 +272,15 @@ struct PrepGraph {
     int32_t flag;  // 0, kStatusBadGraph or kStatusRange
 };
 
-__device__ __forceinline__ PrepGraph prep_graph(int64_t v0, int64_t v1, int64_t e0, int64_t e1,
-                                                bool first, int32_t max_n) {
+__device__ __forceinline__ PrepGraph prep_graph(const int64_t* vo, const int64_t* eo, int32_t g,
+                                                int32_t max_n) {
     PrepGraph p;
-    p.v0 = v0;
-    p.e0 = e0;
-    p.n = v1 - v0;
-    p.m = e1 - e0;
+    p.v0 = vo[g];
+    p.e0 = eo[g];
+    p.n = vo[g + 1] - p.v0;
+    p.m = eo[g + 1] - p.e0;
     p.flag = 0;
-    if ((first && (v0 != 0 || e0 != 0)) || p.n < 0 || p.m < 0 || p.n > max_n)
+    if ((g == 0 && (p.v0 != 0 || p.e0 != 0)) || p.n < 0 || p.m < 0 || p.n > max_n)
         p.flag = kStatusBadGraph;
     else if (p.n == 0 && p.m > 0)
         p.flag = kStatusRange;
@@ -288,87 +289,99 @@ __device__ __forceinline__ PrepGraph prep_graph(int64_t v0, int64_t v1, int64_t 
     return p;
 }
 
-__global__ __launch_bounds__(1024) void k_batch_prep(const int64_t* __restrict__ vo,
-                                                     const int64_t* __restrict__ eo, int32_t B,
-                                                     const int32_t* u, const int32_t* v,
-                                                     int32_t* out, int32_t max_n, int32_t seg_cap,
-                                                     GraphDesc* __restrict__ descs, Ctrl* ctrl,
-                                                     int32_t* status) {
-    __shared__ int32_t start[256];
+// Step 1 (one thread per graph, kPrepGraphs per workgroup): each workgroup
+// counts its graphs per class into its row of `rows` (W x 256).
+__global__ __launch_bounds__(1024) void k_batch_prep_count(const int64_t* __restrict__ vo,
+                                                           const int64_t* __restrict__ eo,
+                                                           int32_t B, int32_t max_n,
+                                                           int32_t* __restrict__ rows, Ctrl* ctrl) {
+    __shared__ int32_t hist[256];
+    const int32_t tid = threadIdx.x;
+    if (tid < 256) hist[tid] = 0;
+    __syncthreads();
+    const int32_t g = blockIdx.x * kPrepGraphs + tid;
+    if (g < B) atomicAdd(&hist[prep_graph(vo, eo, g, max_n).cls], 1);
+    __syncthreads();
+    if (tid < 256) rows[blockIdx.x * 256 + tid] = hist[tid];
+    if (blockIdx.x == 0 && tid == 0) ctrl->queue_head = 0;
+}
+
+// Step 2: each workgroup finds where its graphs of each class go (all
+// earlier classes of every workgroup, then this class of the earlier
+// workgroups) and writes their descriptors there.
+__global__ __launch_bounds__(1024) void k_batch_prep_place(
+    const int64_t* __restrict__ vo, const int64_t* __restrict__ eo, int32_t B, const int32_t* u,
+    const int32_t* v, int32_t* out, int32_t max_n, int32_t seg_cap,
+    const int32_t* __restrict__ rows, int32_t W, GraphDesc* __restrict__ descs, int32_t* status) {
+    __shared__ int32_t base[256];
     __shared__ int32_t flags;
-    const int32_t tid = threadIdx.x, nthr = blockDim.x;
-    for (int32_t c = tid; c < 256; c += nthr) start[c] = 0;
-    if (tid == 0) {
-        flags = 0;
-        ctrl->queue_head = 0;
+    const int32_t tid = threadIdx.x;
+    int32_t total = 0, before = 0;
+    if (tid < 256) {
+        for (int32_t w = 0; w < W; ++w) {
+            const int32_t r = rows[w * 256 + tid];
+            total += r;
+            before += w < (int32_t)blockIdx.x ? r : 0;
+        }
+    }
+    if (tid == 0) flags = 0;
+    __shared__ int32_t tot[256];
+    if (tid < 256) tot[tid] = total;
+    __syncthreads();
+    if (tid < 64) {
+        // exclusive scan of the 256 class totals: 4 per lane, then across the wave
+        const int32_t c0 = tot[4 * tid], c1 = tot[4 * tid + 1], c2 = tot[4 * tid + 2],
+                      c3 = tot[4 * tid + 3];
+        const int32_t sum = c0 + c1 + c2 + c3;
+        int32_t inc = sum;
+#pragma unroll
+        for (int d = 1; d < 64; d <<= 1) {
+            const int32_t t = __shfl_up(inc, d, 64);
+            if (tid >= d) inc += t;
+        }
+        const int32_t ex = inc - sum;
+        tot[4 * tid] = ex;
+        tot[4 * tid + 1] = ex + c0;
+        tot[4 * tid + 2] = ex + c0 + c1;
+        tot[4 * tid + 3] = ex + c0 + c1 + c2;
     }
     __syncthreads();
-    // pass 1: class histogram; pass 2: scatter.  Offsets of kPrepUnroll
-    // graphs per thread are loaded before any is used (indices clamped to
-    // the last graph, so every load is in bounds).
-    for (int pass = 0; pass < 2; ++pass) {
-        int32_t flag = 0;
-        for (int64_t g0 = 0; g0 < B; g0 += (int64_t)nthr * kPrepUnroll) {
-            int64_t a0[kPrepUnroll], a1[kPrepUnroll], b0[kPrepUnroll], b1[kPrepUnroll];
-#pragma unroll
-            for (int j = 0; j < kPrepUnroll; ++j) {
-                const int64_t g = min(g0 + tid + (int64_t)j * nthr, (int64_t)B - 1);
-                a0[j] = vo[g];
-                a1[j] = vo[g + 1];
-                b0[j] = eo[g];
-                b1[j] = eo[g + 1];
-            }
-#pragma unroll
-            for (int j = 0; j < kPrepUnroll; ++j) {
-                const int64_t g = g0 + tid + (int64_t)j * nthr;
-                if (g >= B) continue;
-                const PrepGraph p = prep_graph(a0[j], a1[j], b0[j], b1[j], g == 0, max_n);
-                if (pass == 0) {
-                    atomicAdd(&start[p.cls], 1);
-                    continue;
-                }
-                flag |= p.flag;
-                const int32_t pos = atomicAdd(&start[p.cls], 1);
-                GraphDesc d;
-                d.u = u + p.e0;
-                d.v = v + p.e0;
-                d.out = out + p.v0;
-                d.m = p.m;
-                d.n = (int32_t)p.n;
-                d.segments = p.n > 0 ? batch_segments(p.m, p.n, seg_cap) : 1;
-                descs[pos] = d;
-            }
-        }
-        if (pass == 1 && flag) atomicOr(&flags, flag);
-        __syncthreads();
-        if (pass == 0 && tid < 64) {
-            // exclusive scan of the 256 counts: 4 per lane, then across the wave
-            const int32_t c0 = start[4 * tid], c1 = start[4 * tid + 1], c2 = start[4 * tid + 2],
-                          c3 = start[4 * tid + 3];
-            const int32_t sum = c0 + c1 + c2 + c3;
-            int32_t inc = sum;
-#pragma unroll
-            for (int d = 1; d < 64; d <<= 1) {
-                const int32_t t = __shfl_up(inc, d, 64);
-                if (tid >= d) inc += t;
-            }
-            const int32_t ex = inc - sum;
-            start[4 * tid] = ex;
-            start[4 * tid + 1] = ex + c0;
-            start[4 * tid + 2] = ex + c0 + c1;
-            start[4 * tid + 3] = ex + c0 + c1 + c2;
-        }
-        __syncthreads();
+    if (tid < 256) base[tid] = tot[tid] + before;
+    __syncthreads();
+    const int32_t g = blockIdx.x * kPrepGraphs + tid;
+    if (g < B) {
+        const PrepGraph p = prep_graph(vo, eo, g, max_n);
+        const int32_t pos = atomicAdd(&base[p.cls], 1);
+        GraphDesc d;
+        d.u = u + p.e0;
+        d.v = v + p.e0;
+        d.out = out + p.v0;
+        d.m = p.m;
+        d.n = (int32_t)p.n;
+        d.segments = p.n > 0 ? batch_segments(p.m, p.n, seg_cap) : 1;
+        descs[pos] = d;
+        if (p.flag) atomicOr(&flags, p.flag);
     }
-    if (tid == 0 && flags)
-        __hip_atomic_store(status + 1, flags, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_SYSTEM);
+    __syncthreads();
+    // one word per kind of fault, so that plain stores of different
+    // workgroups never overwrite each other's bits
+    if (tid == 0 && (flags & kStatusBadGraph))
+        __hip_atomic_store(status + 1, kStatusBadGraph, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_SYSTEM);
+    if (tid == 0 && (flags & kStatusRange))
+        __hip_atomic_store(status + 2, kStatusRange, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_SYSTEM);
 }
 
 hipError_t launch_batch_prep(const int64_t* vo, const int64_t* eo, int32_t B, const int32_t* u,
                              const int32_t* v, int32_t* out, int32_t max_n, int32_t seg_cap,
-                             GraphDesc* descs, Ctrl* ctrl, int32_t* status, hipStream_t s) {
+                             GraphDesc* descs, int32_t* rows, Ctrl* ctrl, int32_t* status,
+                             hipStream_t s) {
     if (B <= 0) return hipSuccess;
-    k_batch_prep<<<1, 1024, 0, s>>>(vo, eo, B, u, v, out, max_n, seg_cap, descs, ctrl, status);
+    const int32_t W = (int32_t)(((int64_t)B + kPrepGraphs - 1) / kPrepGraphs);
+    k_batch_prep_count<<<W, kPrepGraphs, 0, s>>>(vo, eo, B, max_n, rows, ctrl);
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return e;
+    k_batch_prep_place<<<W, kPrepGraphs, 0, s>>>(vo, eo, B, u, v, out, max_n, seg_cap, rows, W,
+                                                 descs, status);
     return hipGetLastError();
 }
 

@@ -114,6 +114,7 @@ __device__ __forceinline__ void lds_atomic_hook(T* spi, uint32_t pu, uint32_t pv
 // `end`).  Each array is read through a raw buffer resource whose size is
 // the step's entries inside [base, end), so no load is issued past `end`;
 // the byte offsets are per lane and the same at every step.
+template <int EPT = kBatchEPT>
 __device__ __forceinline__ void edge_step_loads(g_cint* du, g_cint* dv, int64_t base, int64_t end,
                                                 int64_t step, int32_t* a, int32_t* b) {
     const int64_t rem = end - base < step ? end - base : step;
@@ -123,7 +124,7 @@ __device__ __forceinline__ void edge_step_loads(g_cint* du, g_cint* dv, int64_t 
     const __amdgpu_buffer_rsrc_t rv =
         __builtin_amdgcn_make_buffer_rsrc((void*)(dv + base), 0, bytes, kBufferRsrcWord3);
 #pragma unroll
-    for (int j = 0; j < kBatchEPT; ++j) {
+    for (int j = 0; j < EPT; ++j) {
         const int32_t off = (int32_t)((threadIdx.x + j * blockDim.x) * 4);
         a[j] = __builtin_amdgcn_raw_buffer_load_b32(ru, off, 0, kBufferNonTemporal);
         b[j] = __builtin_amdgcn_raw_buffer_load_b32(rv, off, 0, kBufferNonTemporal);
@@ -414,6 +415,7 @@ hipError_t launch_batch_prep(const int64_t* vo, const int64_t* eo, int32_t B, co
 constexpr int64_t kWinEntries = 49152;  // 1024 threads x 48 entries
 constexpr uint32_t kWinSlots = 40960;   // 16-bit local ids: 80 KiB of LDS
 constexpr int kWinSegments = 2;
+constexpr int kWinEPT = 4;  // entries per thread per step (registers: two workgroups per CU)
 
 __global__ __launch_bounds__(1024) void k_hook_window(const int32_t* __restrict__ eu,
                                                       const int32_t* __restrict__ ev, int64_t m,
@@ -445,66 +447,60 @@ __global__ __launch_bounds__(1024) void k_hook_window(const int32_t* __restrict_
     uint32_t far = 0;  // entries hooked outside the window
     // The chunk in kWinSegments segments, each followed by a Multi-Jump over
     // the window (the schedule of Fig. 4 inside the chunk) so that later
-    // climbs start from stars.  kBatchEPT entries per thread per step,
-    // consecutive threads on consecutive entries (coalesced), the next
-    // step's loads issued before this step's hooks.
+    // climbs start from stars.  kWinEPT entries per thread per step,
+    // consecutive threads on consecutive entries (coalesced, through buffer
+    // resources as in the batched solver), the next step's loads issued
+    // before this step's hooks.  An entry past the segment's end reads as
+    // (0, 0); no branch surrounds the LDS hook, which is given (0, 0) -- a
+    // no-op -- for every entry that is not inside the window.
     for (int seg = 0; seg < kWinSegments; ++seg) {
         const int64_t s0 = c0 + (c1 - c0) * seg / kWinSegments;
         const int64_t s1 = c0 + (c1 - c0) * (seg + 1) / kWinSegments;
-        const int64_t step = (int64_t)nthr * kBatchEPT;
-        int32_t a[kBatchEPT], b[kBatchEPT], na[kBatchEPT], nb[kBatchEPT];
-        int64_t e0 = s0 + tid;
+        const int64_t step = (int64_t)nthr * kWinEPT;
+        int32_t a[kWinEPT], b[kWinEPT], na[kWinEPT], nb[kWinEPT];
+        g_cint* gu = (g_cint*)eu;
+        g_cint* gv = (g_cint*)ev;
+        edge_step_loads<kWinEPT>(gu, gv, s0, s1, step, a, b);
+        for (int64_t sb = s0; sb < s1; sb += step) {
+            edge_step_loads<kWinEPT>(gu, gv, sb + step, s1, step, na, nb);
+            const uint32_t rem = (uint32_t)min<int64_t>(s1 - sb, step);
 #pragma unroll
-        for (int j = 0; j < kBatchEPT; ++j) {
-            const int64_t e = e0 + (int64_t)j * nthr;
-            a[j] = e < s1 ? __builtin_nontemporal_load(eu + e) : 0;
-            b[j] = e < s1 ? __builtin_nontemporal_load(ev + e) : 0;
-        }
-        for (; e0 < s1; e0 += step) {
-            const int64_t e1 = e0 + step;
-#pragma unroll
-            for (int j = 0; j < kBatchEPT; ++j) {
-                const int64_t e = e1 + (int64_t)j * nthr;
-                na[j] = e < s1 ? __builtin_nontemporal_load(eu + e) : 0;
-                nb[j] = e < s1 ? __builtin_nontemporal_load(ev + e) : 0;
-            }
-#pragma unroll
-            for (int j = 0; j < kBatchEPT; ++j) {
-                if (e0 + (int64_t)j * nthr >= s1) continue;
-                if ((uint32_t)a[j] >= (uint32_t)n || (uint32_t)b[j] >= (uint32_t)n) {
-                    bad = true;
-                    continue;
-                }
-                if (a[j] == b[j]) continue;
-                const uint32_t la = (uint32_t)(a[j] - base), lb = (uint32_t)(b[j] - base);
-                if (la < span && lb < span) {
-                    lds_atomic_hook(spi, lds_ld(spi, la), lds_ld(spi, lb), true);
-                } else {
+            for (int j = 0; j < kWinEPT; ++j) {
+                const bool in = tid + j * nthr < rem;
+                const uint32_t x = (uint32_t)a[j], y = (uint32_t)b[j];
+                const bool ok = max(x, y) < (uint32_t)n;
+                bad |= in && !ok;
+                const uint32_t la = x - (uint32_t)base, lb = y - (uint32_t)base;
+                const bool win = ok && la < span && lb < span;
+                lds_atomic_hook(spi, lds_ld(spi, win ? la : 0u), lds_ld(spi, win ? lb : 0u), true);
+                if (in && ok && !win) {
                     ++far;
-                    const int32_t pa = ld_rlx(pi + a[j]), pb = ld_rlx(pi + b[j]);
+                    const int32_t pa = ld_rlx(pi + x), pb = ld_rlx(pi + y);
                     if (pa != pb) st_rlx(pi + max(pa, pb), min(pa, pb));
                 }
             }
 #pragma unroll
-            for (int j = 0; j < kBatchEPT; ++j) {
+            for (int j = 0; j < kWinEPT; ++j) {
                 a[j] = na[j];
                 b[j] = nb[j];
             }
         }
         __syncthreads();
-        // Multi-Jump over the window; after the last segment the local roots
-        // go to pi
+        // Multi-Jump over the window: each vertex climbs to its local root
+        // and stores it once; after the last segment the local roots of the
+        // non-roots go to pi
         const bool last = seg + 1 == kWinSegments;
         for (uint32_t x = tid; x < span; x += nthr) {
             uint32_t p = lds_ld(spi, x);
-            if (p == x) continue;
             uint32_t g = lds_ld(spi, p);
             while (g != p) {
-                lds_st(spi, x, g);
                 p = g;
                 g = lds_ld(spi, p);
             }
-            if (last) st_rlx(pi + base + (int32_t)x, base + (int32_t)p);
+            if (!last)
+                lds_st(spi, x, p);
+            else if (p != x)
+                st_rlx(pi + base + (int32_t)x, base + (int32_t)p);
         }
         __syncthreads();
     }

@@ -1174,10 +1174,6 @@ size_t workspace_bytes_impl(int32_t n, int64_t m, const cc_options* opts) {
 }
 
 // ---------------------------------------------------------------------- graph lists
-// Small graphs (n <= CC_BATCH_LDS_MAX_N) go to one persistent LDS launch whose
-// workgroups take them largest first; every larger graph gets the device-memory
-// Atomic-Hook solve with its own control block.  Everything is enqueued on `s`
-// and the call ends with one synchronisation and one read of all control blocks.
 // Segments of an LDS-solved graph: min(cap, round(m / n)) (at least 1), or
 // round(m / n) for cap 0; small caps by comparison, without a division.
 int32_t lds_segments(int64_t m, int64_t n, int32_t cap) {
@@ -1192,7 +1188,12 @@ int32_t lds_segments(int64_t m, int64_t n, int32_t cap) {
 
 // The graph-list solve over any graph accessor: graph_at(g) returns graph g
 // as a cc_graph (the caller's array, or one computed from batch offsets, so a
-// batch never materialises a list).
+// batch never materialises a list).  Small graphs (n <= CC_BATCH_LDS_MAX_N)
+// go to one persistent LDS launch whose workgroups take them largest first;
+// every larger graph gets the device-memory Atomic-Hook solve with its own
+// control block.  Everything is enqueued on `s`; the call ends with one
+// synchronisation, after which the LDS launch's pinned status word and the
+// large graphs' control blocks (copied back) are read.
 template <class GraphAt>
 int32_t list_core(int32_t count, GraphAt&& graph_at, const cc_options* opts, hipStream_t s,
                   cc_stats* st, void* workspace, size_t ws_bytes, size_t* ws_needed) {

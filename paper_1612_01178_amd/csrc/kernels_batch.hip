@@ -2,8 +2,9 @@
 //
 // Persistent workgroups (1024 threads, 16 waves, by default; as many per CU as
 // the LDS of the launch's largest graph allows) take graphs from a device
-// work queue (an atomic counter over a host-sorted order, largest first) and
-// solves each one entirely in LDS: the graph's tree array pi lives in LDS as
+// work queue (an atomic counter over descriptors ordered largest first, by
+// the host or, for offsets in device memory, by the preparation launches
+// below) and solve each one entirely in LDS: the graph's tree array pi lives in LDS as
 // local ids, 32-bit for n <= 32768 and 16-bit up to 65536 (at most 128 KiB of
 // the 160 KiB LDS), the edge entries are streamed once from HBM, and the
 // labels are written once.

@@ -313,13 +313,15 @@ int32_t cc_labels_batch_ex(int32_t num_graphs, const int64_t* vtx_off, const int
  * then the persistent LDS launch solves them.  A call is two launches and
  * one synchronisation on `stream`, whatever the number of graphs.
  *   vtx_off, edge_off  [device] int64[B+1], as for cc_labels_batch
- *   edges_u/v          [device] int32[edge_off[B]], local ids
- *   out_label          [device] int32[vtx_off[B]]
+ *   edges_u/v          [device] int32[edge_off[B]], local ids (NULL only if no graph
+ *                      has entries)
+ *   out_label          [device] int32[vtx_off[B]] (NULL only if no graph has vertices)
  *   max_n              an upper bound of every graph's vertex count, in
  *                      [1, CC_BATCH_LDS_MAX_N]: it sizes the launch's LDS (a
  *                      tight bound lets several workgroups share a CU)
  * Every graph is LDS-solved: offsets that do not start at 0, decrease, or
- * give a graph more than max_n vertices are found on the device; then no
+ * give a graph more than max_n vertices, and a NULL array that a graph
+ * needs, are found on the device; then no
  * label is written for the offending graphs and the call returns
  * CC_ERR_ARG after the synchronisation.  `opts` (nullable) takes
  * `segments`, `path_halving`, `block` and `graph` as for cc_labels_batch_ex;

@@ -1446,7 +1446,9 @@ int32_t batch_device_impl(int32_t B, const int64_t* vo, const int64_t* eo, const
         st->giant_label = -1;
     }
     if (B == 0) return CC_OK;
-    if (!vo || !eo || !u || !v || !out) return fail(CC_ERR_ARG, "null offsets, edges or labels");
+    // null edge or label arrays are allowed for graphs without entries /
+    // vertices; the preparation launch checks that on the device
+    if (!vo || !eo) return fail(CC_ERR_ARG, "null offsets");
     if ((size_t)B > (SIZE_MAX - sizeof(Ctrl)) / sizeof(GraphDesc)) return fail(CC_ERR_ARG, "too many graphs");
     const size_t desc_off = sizeof(Ctrl);
     const size_t rows_off = desc_off + align256((size_t)B * sizeof(GraphDesc));

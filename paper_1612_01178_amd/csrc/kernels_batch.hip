@@ -275,14 +275,17 @@ struct PrepGraph {
 };
 
 __device__ __forceinline__ PrepGraph prep_graph(const int64_t* vo, const int64_t* eo, int32_t g,
-                                                int32_t max_n) {
+                                                int32_t max_n, bool edges, bool labels) {
     PrepGraph p;
     p.v0 = vo[g];
     p.e0 = eo[g];
     p.n = vo[g + 1] - p.v0;
     p.m = eo[g + 1] - p.e0;
     p.flag = 0;
-    if ((g == 0 && (p.v0 != 0 || p.e0 != 0)) || p.n < 0 || p.m < 0 || p.n > max_n)
+    // (edges / labels: whether those arrays were given; a null one may only
+    // belong to graphs that have no entries / no vertices)
+    if ((g == 0 && (p.v0 != 0 || p.e0 != 0)) || p.n < 0 || p.m < 0 || p.n > max_n ||
+        (p.m > 0 && !edges) || (p.n > 0 && !labels))
         p.flag = kStatusBadGraph;
     else if (p.n == 0 && p.m > 0)
         p.flag = kStatusRange;
@@ -295,14 +298,15 @@ __device__ __forceinline__ PrepGraph prep_graph(const int64_t* vo, const int64_t
 // counts its graphs per class into its row of `rows` (W x 256).
 __global__ __launch_bounds__(1024) void k_batch_prep_count(const int64_t* __restrict__ vo,
                                                            const int64_t* __restrict__ eo,
-                                                           int32_t B, int32_t max_n,
-                                                           int32_t* __restrict__ rows, Ctrl* ctrl) {
+                                                           int32_t B, int32_t max_n, bool edges,
+                                                           bool labels, int32_t* __restrict__ rows,
+                                                           Ctrl* ctrl) {
     __shared__ int32_t hist[256];
     const int32_t tid = threadIdx.x;
     if (tid < 256) hist[tid] = 0;
     __syncthreads();
     const int32_t g = blockIdx.x * kPrepGraphs + tid;
-    if (g < B) atomicAdd(&hist[prep_graph(vo, eo, g, max_n).cls], 1);
+    if (g < B) atomicAdd(&hist[prep_graph(vo, eo, g, max_n, edges, labels).cls], 1);
     __syncthreads();
     if (tid < 256) rows[blockIdx.x * 256 + tid] = hist[tid];
     if (blockIdx.x == 0 && tid == 0) ctrl->queue_head = 0;
@@ -352,7 +356,7 @@ __global__ __launch_bounds__(1024) void k_batch_prep_place(
     __syncthreads();
     const int32_t g = blockIdx.x * kPrepGraphs + tid;
     if (g < B) {
-        const PrepGraph p = prep_graph(vo, eo, g, max_n);
+        const PrepGraph p = prep_graph(vo, eo, g, max_n, u && v, out != nullptr);
         const int32_t pos = atomicAdd(&base[p.cls], 1);
         GraphDesc d;
         d.u = u + p.e0;
@@ -379,7 +383,8 @@ hipError_t launch_batch_prep(const int64_t* vo, const int64_t* eo, int32_t B, co
                              hipStream_t s) {
     if (B <= 0) return hipSuccess;
     const int32_t W = (int32_t)(((int64_t)B + kPrepGraphs - 1) / kPrepGraphs);
-    k_batch_prep_count<<<W, kPrepGraphs, 0, s>>>(vo, eo, B, max_n, rows, ctrl);
+    k_batch_prep_count<<<W, kPrepGraphs, 0, s>>>(vo, eo, B, max_n, u && v, out != nullptr, rows,
+                                                 ctrl);
     hipError_t e = hipGetLastError();
     if (e != hipSuccess) return e;
     k_batch_prep_place<<<W, kPrepGraphs, 0, s>>>(vo, eo, B, u, v, out, max_n, seg_cap, rows, W,

@@ -383,6 +383,23 @@ def test_batch_device_offsets_match_oracle(dev):
     want = np.concatenate([pins.closure_labels(tu[teo[g]:teo[g + 1]], tv[teo[g]:teo[g + 1]], n)
                            for g, (n, _) in enumerate(graphs)])
     assert np.array_equal(_batch_device(tu, tv, tvo, teo, dev, 5).cpu().numpy(), want)
+    # one graph; graphs without vertices only; more graphs than one preparation
+    # workgroup takes (1,024), most of them empty
+    one_u, one_v = np.array([3, 1], np.int32), np.array([1, 0], np.int32)
+    got = _batch_device(one_u, one_v, np.array([0, 5], np.int64), np.array([0, 2], np.int64), dev, 5)
+    assert np.array_equal(got.cpu().numpy(), [0, 0, 2, 0, 4])
+    empty = np.zeros(4, np.int64)
+    got = _batch_device(np.zeros(0, np.int32), np.zeros(0, np.int32), empty, empty, dev, 1)
+    assert (got.cpu().numpy() == -1).all()  # nothing written
+    B = 2500
+    nv = np.where(np.arange(B) % 7 == 3, 3, 0).astype(np.int64)
+    me = np.where(nv > 0, 1, 0).astype(np.int64)
+    bvo = np.concatenate([[0], np.cumsum(nv)]).astype(np.int64)
+    beo = np.concatenate([[0], np.cumsum(me)]).astype(np.int64)
+    bu = np.full(int(beo[-1]), 2, np.int32)
+    bv = np.zeros(int(beo[-1]), np.int32)
+    got = _batch_device(bu, bv, bvo, beo, dev, 3).cpu().numpy()
+    assert np.array_equal(got, oracle.labels_batch(bu, bv, bvo, beo))
 
 
 def test_batch_device_offsets_errors_and_replays(dev):

@@ -1384,6 +1384,10 @@ int32_t list_impl(int32_t count, const cc_graph* graphs, const cc_options* opts,
                      ws_bytes, ws_needed);
 }
 
+int32_t batch_lds_impl(int32_t B, const int64_t* vo, const int64_t* eo, const int64_t* hvo,
+                       const int64_t* heo, const int32_t* u, const int32_t* v, int32_t* out,
+                       int32_t max_n, const cc_options* opts, hipStream_t s, cc_stats* st);
+
 int32_t batch_impl(int32_t B, const int64_t* vo, const int64_t* eo, const int32_t* u,
                    const int32_t* v, int32_t* out, const cc_options* opts, hipStream_t s,
                    cc_stats* st) {
@@ -1399,13 +1403,21 @@ int32_t batch_impl(int32_t B, const int64_t* vo, const int64_t* eo, const int32_
     }
     if (!vo || !eo) return fail(CC_ERR_ARG, "null offsets");
     if (vo[0] != 0 || eo[0] != 0) return fail(CC_ERR_ARG, "offsets must start at 0");
+    int64_t max_n = 0;
     for (int32_t g = 0; g < B; ++g) {
         const int64_t nv = vo[g + 1] - vo[g], ne = eo[g + 1] - eo[g];
         if (nv < 0 || ne < 0) return fail(CC_ERR_ARG, "offsets must be non-decreasing");
         if (nv > INT32_MAX) return fail(CC_ERR_ARG, "graph with 2^31 or more vertices");
+        max_n = std::max(max_n, nv);
     }
     if (eo[B] > 0 && (!u || !v)) return fail(CC_ERR_ARG, "null edge array");
     if (vo[B] > 0 && !out) return fail(CC_ERR_ARG, "null out_label");
+    // Every graph LDS-sized: the offsets are copied to the device as they are
+    // and the graphs ordered and described there (the device-offset path),
+    // which costs less host time than building the descriptors here.
+    if (max_n <= CC_BATCH_LDS_MAX_N)
+        return batch_lds_impl(B, nullptr, nullptr, vo, eo, u, v, out,
+                              (int32_t)std::max<int64_t>(1, max_n), opts, s, st);
     // graph g straight from the offsets: no list of B graphs is built
     auto graph_at = [=](int32_t g) {
         cc_graph G;
@@ -1424,9 +1436,12 @@ int32_t batch_impl(int32_t B, const int64_t* vo, const int64_t* eo, const int32_
 // Device offsets: the preparation workgroup builds the descriptors and the
 // largest-first order on the device (no host pass over the graphs), then the
 // persistent LDS launch solves them; one synchronisation.
-int32_t batch_device_impl(int32_t B, const int64_t* vo, const int64_t* eo, const int32_t* u,
-                          const int32_t* v, int32_t* out, int32_t max_n, const cc_options* opts,
-                          hipStream_t s, cc_stats* st) {
+// The LDS batch with offsets in device memory (vo, eo), or in host memory
+// (hvo, heo non-null: copied through the pinned staging buffer into the
+// workspace first, one copy per call).
+int32_t batch_lds_impl(int32_t B, const int64_t* vo, const int64_t* eo, const int64_t* hvo,
+                       const int64_t* heo, const int32_t* u, const int32_t* v, int32_t* out,
+                       int32_t max_n, const cc_options* opts, hipStream_t s, cc_stats* st) {
     if (B < 0) return fail(CC_ERR_ARG, "num_graphs < 0");
     if (opts && opts->no_sync)
         return fail(CC_ERR_ARG, "cc_options.no_sync is for cc_labels_ex and cc_labels_csr only");
@@ -1448,24 +1463,40 @@ int32_t batch_device_impl(int32_t B, const int64_t* vo, const int64_t* eo, const
     if (B == 0) return CC_OK;
     // null edge or label arrays are allowed for graphs without entries /
     // vertices; the preparation launch checks that on the device
-    if (!vo || !eo) return fail(CC_ERR_ARG, "null offsets");
+    const bool staged = hvo && heo;
+    if (!staged && (!vo || !eo)) return fail(CC_ERR_ARG, "null offsets");
     if ((size_t)B > (SIZE_MAX - sizeof(Ctrl)) / sizeof(GraphDesc)) return fail(CC_ERR_ARG, "too many graphs");
     const size_t desc_off = sizeof(Ctrl);
     const size_t rows_off = desc_off + align256((size_t)B * sizeof(GraphDesc));
-    const size_t total = rows_off + align256(((size_t)B + 1023) / 1024 * 256 * 4);
+    const size_t off_bytes = align256(((size_t)B + 1) * 8);  // one offset array
+    const size_t offs_off = rows_off + align256(((size_t)B + 1023) / 1024 * 256 * 4);
+    const size_t total = offs_off + (staged ? 2 * off_bytes : 0);
     HIPCHK(prepare_batch_lds());
     PoolEntry* pe = pool_entry(s);
     std::lock_guard<std::mutex> lk(pe->mu);
     int32_t rc = ensure_dev(pe, total);
     if (rc != CC_OK) return rc;
+    if (staged) {
+        rc = ensure_stage(pe, 2 * off_bytes);
+        if (rc != CC_OK) return rc;
+        std::memcpy(pe->host_stage, hvo, ((size_t)B + 1) * 8);
+        std::memcpy(static_cast<char*>(pe->host_stage) + off_bytes, heo, ((size_t)B + 1) * 8);
+    }
     if (!pe->batch_status)
         HIPCHK(hipHostMalloc((void**)&pe->batch_status, 256, hipHostMallocDefault));
     pe->batch_status[0] = pe->batch_status[1] = pe->batch_status[2] = 0;
     char* ws = static_cast<char*>(pe->dev);
+    if (staged) {
+        vo = reinterpret_cast<const int64_t*>(ws + offs_off);
+        eo = reinterpret_cast<const int64_t*>(ws + offs_off + off_bytes);
+    }
     Ctrl* ctrl = reinterpret_cast<Ctrl*>(ws);
     GraphDesc* descs = reinterpret_cast<GraphDesc*>(ws + desc_off);
     int32_t* rows = reinterpret_cast<int32_t*>(ws + rows_off);
     auto enqueue = [&]() -> int32_t {
+        if (staged)
+            HIPCHK(hipMemcpyAsync(ws + offs_off, pe->host_stage, 2 * off_bytes,
+                                  hipMemcpyHostToDevice, s));
         HIPCHK(launch_batch_prep(vo, eo, B, u, v, out, max_n, seg_cap, descs, rows, ctrl,
                                  pe->batch_status, s));
         HIPCHK(launch_batch_lds(descs, B, max_n, &ctrl->queue_head, pe->batch_status, lds_halve,
@@ -1474,8 +1505,11 @@ int32_t batch_device_impl(int32_t B, const int64_t* vo, const int64_t* eo, const
     };
     if (opts && opts->graph == 1 && s != nullptr) {
         KeyHash k;
+        // staged offsets: the captured copy re-reads the staging buffer,
+        // rewritten above, at every replay
         k.add(uint64_t(0xba7c4de71ce)).add(B).add(vo).add(eo).add(u).add(v).add(out).add(max_n)
-            .add(seg_cap).add(lds_halve).add(lds_block).add(ws).add(s);
+            .add(seg_cap).add(lds_halve).add(lds_block).add(ws).add(s).add(staged)
+            .add(pe->host_stage);
         rc = run_graph(pe, k.h, s, enqueue);
     } else {
         rc = enqueue();
@@ -1492,6 +1526,12 @@ int32_t batch_device_impl(int32_t B, const int64_t* vo, const int64_t* eo, const
                                 "every graph at most max_n vertices");
     if ((prep | solve) & kStatusRange) return fail(CC_ERR_RANGE, "edge endpoint outside [0, n_g)");
     return CC_OK;
+}
+
+int32_t batch_device_impl(int32_t B, const int64_t* vo, const int64_t* eo, const int32_t* u,
+                          const int32_t* v, int32_t* out, int32_t max_n, const cc_options* opts,
+                          hipStream_t s, cc_stats* st) {
+    return batch_lds_impl(B, vo, eo, nullptr, nullptr, u, v, out, max_n, opts, s, st);
 }
 
 // ---------------------------------------------------------------------- probes, release

@@ -145,9 +145,14 @@ __device__ __forceinline__ void solve_graph(T* spi, const GraphDesc& d, bool hal
     g_cint* du = (g_cint*)d.u;
     g_cint* dv = (g_cint*)d.v;
     g_int* dout = (g_int*)d.out;
+    const int32_t s = d.segments > 0 ? d.segments : 1;
+    const int64_t step = (int64_t)nthr * kBatchEPT;
+    int32_t a[kBatchEPT], b[kBatchEPT], na[kBatchEPT], nb[kBatchEPT];
+    // the first segment's first loads go out before the init, so that their
+    // latency overlaps it and its barrier
+    edge_step_loads(du, dv, 0, d.m / s, step, a, b);
     for (uint32_t x = tid; x < n; x += nthr) lds_st(spi, x, x);
     __syncthreads();
-    const int32_t s = d.segments > 0 ? d.segments : 1;
     for (int32_t seg = 0; seg < s; ++seg) {
         const int64_t b0 = d.m * seg / s, b1 = d.m * (seg + 1) / s;
         // kBatchEPT entries per thread per step, all loads issued before
@@ -161,10 +166,8 @@ __device__ __forceinline__ void solve_graph(T* spi, const GraphDesc& d, bool hal
         // (0, 0), whose hook does nothing -- divergent branches would cost
         // more scalar exec-mask instructions than the work they skip.
         if (b1 > b0) {
-            const int64_t step = (int64_t)nthr * kBatchEPT;
-            int32_t a[kBatchEPT], b[kBatchEPT], na[kBatchEPT], nb[kBatchEPT];
             int64_t base = b0;
-            edge_step_loads(du, dv, base, b1, step, a, b);
+            if (seg > 0) edge_step_loads(du, dv, base, b1, step, a, b);
             for (; base < b1; base += step) {
                 edge_step_loads(du, dv, base + step, b1, step, na, nb);
 #pragma unroll

@@ -435,17 +435,25 @@ __global__ __launch_bounds__(1024) void k_hook_window(const int32_t* __restrict_
     const uint32_t lane = tid & 63, wave = tid >> 6, waves = nthr >> 6;
     const int64_t c0 = (int64_t)blockIdx.x * kWinEntries;
     const int64_t c1 = min(m, c0 + kWinEntries);
+    const int64_t step = (int64_t)nthr * kWinEPT;
+    g_cint* gu = (g_cint*)eu;
+    g_cint* gv = (g_cint*)ev;
+    int32_t a[kWinEPT], b[kWinEPT], na[kWinEPT], nb[kWinEPT];
+    // the first segment's first entries are loaded before the LDS init, so
+    // that their latency overlaps it; the window starts at the smallest
+    // endpoint among the first blockDim.x of them
+    const int64_t first_end = c0 + (c1 - c0) / kWinSegments;
+    edge_step_loads<kWinEPT>(gu, gv, c0, first_end, step, a, b);
+    uint32_t* w32 = reinterpret_cast<uint32_t*>(spi);
+    for (uint32_t w = tid; w < kWinSlots / 2; w += nthr) w32[w] = ((2 * w + 1) << 16) | (2 * w);
     int32_t lo = INT32_MAX;
-    if (c0 + tid < c1) {
-        const int32_t a = eu[c0 + tid], b = ev[c0 + tid];
-        if ((uint32_t)a < (uint32_t)n) lo = min(lo, a);
-        if ((uint32_t)b < (uint32_t)n) lo = min(lo, b);
+    if (c0 + tid < first_end) {
+        if ((uint32_t)a[0] < (uint32_t)n) lo = min(lo, a[0]);
+        if ((uint32_t)b[0] < (uint32_t)n) lo = min(lo, b[0]);
     }
 #pragma unroll
     for (int d = 32; d >= 1; d >>= 1) lo = min(lo, __shfl_xor(lo, d, 64));
     if (lane == 0) wave_min[wave] = lo;
-    uint32_t* w32 = reinterpret_cast<uint32_t*>(spi);
-    for (uint32_t w = tid; w < kWinSlots / 2; w += nthr) w32[w] = ((2 * w + 1) << 16) | (2 * w);
     __syncthreads();
     int32_t base = wave_min[0];
     for (uint32_t i = 1; i < waves; ++i) base = min(base, wave_min[i]);
@@ -465,11 +473,7 @@ __global__ __launch_bounds__(1024) void k_hook_window(const int32_t* __restrict_
     for (int seg = 0; seg < kWinSegments; ++seg) {
         const int64_t s0 = c0 + (c1 - c0) * seg / kWinSegments;
         const int64_t s1 = c0 + (c1 - c0) * (seg + 1) / kWinSegments;
-        const int64_t step = (int64_t)nthr * kWinEPT;
-        int32_t a[kWinEPT], b[kWinEPT], na[kWinEPT], nb[kWinEPT];
-        g_cint* gu = (g_cint*)eu;
-        g_cint* gv = (g_cint*)ev;
-        edge_step_loads<kWinEPT>(gu, gv, s0, s1, step, a, b);
+        if (seg > 0) edge_step_loads<kWinEPT>(gu, gv, s0, s1, step, a, b);
         for (int64_t sb = s0; sb < s1; sb += step) {
             edge_step_loads<kWinEPT>(gu, gv, sb + step, s1, step, na, nb);
             const uint32_t rem = (uint32_t)min<int64_t>(s1 - sb, step);

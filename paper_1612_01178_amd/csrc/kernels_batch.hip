@@ -208,9 +208,11 @@ __device__ __forceinline__ void solve_graph(T* spi, const GraphDesc& d, bool hal
     }
 }
 
+template <bool HALVE>
 __global__ __launch_bounds__(1024) void k_batch_lds(const GraphDesc* __restrict__ descs,
                                                     int32_t count, int32_t* queue_head,
-                                                    int32_t* status, bool halve) {
+                                                    int32_t* status) {
+    constexpr bool halve = HALVE;  // a compile-time constant: no branch in the hook loop
     extern __shared__ uint16_t spi[];
     __shared__ int32_t next;
     bool bad = false;
@@ -539,9 +541,13 @@ hipError_t launch_hook_window(const int32_t* u, const int32_t* v, int64_t m, int
 
 hipError_t prepare_batch_lds() {
     // Allows up to 128 KiB of dynamic LDS; set once, outside any capture.
-    static hipError_t once = hipFuncSetAttribute(reinterpret_cast<const void*>(&k_batch_lds),
-                                                 hipFuncAttributeMaxDynamicSharedMemorySize,
-                                                 65536 * 2);
+    static hipError_t once = [] {
+        hipError_t e = hipFuncSetAttribute(reinterpret_cast<const void*>(&k_batch_lds<true>),
+                                           hipFuncAttributeMaxDynamicSharedMemorySize, 65536 * 2);
+        if (e != hipSuccess) return e;
+        return hipFuncSetAttribute(reinterpret_cast<const void*>(&k_batch_lds<false>),
+                                   hipFuncAttributeMaxDynamicSharedMemorySize, 65536 * 2);
+    }();
     return once;
 }
 
@@ -557,7 +563,10 @@ hipError_t launch_batch_lds(const GraphDesc* descs, int32_t count, int32_t max_n
     // thread limits), at most 32 waves per CU
     const int per_cu = (int)std::max<size_t>(1, std::min<size_t>((size_t)(160 * 1024) / lds,
                                                                  (size_t)(2048 / block)));
-    k_batch_lds<<<grid * per_cu, block, lds, s>>>(descs, count, queue_head, status, halve);
+    if (halve)
+        k_batch_lds<true><<<grid * per_cu, block, lds, s>>>(descs, count, queue_head, status);
+    else
+        k_batch_lds<false><<<grid * per_cu, block, lds, s>>>(descs, count, queue_head, status);
     return hipGetLastError();
 }
 

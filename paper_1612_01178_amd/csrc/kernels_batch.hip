@@ -191,18 +191,27 @@ __device__ __forceinline__ void solve_graph(T* spi, const GraphDesc& d, bool hal
         // itself); no hook runs in this phase, so only the stores of other
         // climbers race with it, and each stores an ancestor.  After the last
         // segment the root is the label: it goes to global memory only.
+        // Two vertices per thread and pass, their climbs interleaved (a
+        // finished climb stays on its root, whose parent is itself).
         const bool last = seg + 1 == s;
-        for (uint32_t x = tid; x < n; x += nthr) {
-            uint32_t p = lds_ld(spi, x);
-            uint32_t g = lds_ld(spi, p);
-            while (g != p) {
-                p = g;
-                g = lds_ld(spi, p);
+        for (uint32_t x = tid; x < n; x += 2 * nthr) {
+            const uint32_t y = x + nthr;
+            const bool has_y = y < n;
+            uint32_t p1 = lds_ld(spi, x), p2 = lds_ld(spi, has_y ? y : x);
+            uint32_t g1 = lds_ld(spi, p1), g2 = lds_ld(spi, p2);
+            while (g1 != p1 || g2 != p2) {
+                p1 = g1;
+                p2 = g2;
+                g1 = lds_ld(spi, p1);
+                g2 = lds_ld(spi, p2);
             }
-            if (last)
-                dout[x] = (int32_t)p;
-            else
-                lds_st(spi, x, p);
+            if (last) {
+                dout[x] = (int32_t)p1;
+                if (has_y) dout[y] = (int32_t)p2;
+            } else {
+                lds_st(spi, x, p1);
+                if (has_y) lds_st(spi, y, p2);
+            }
         }
         if (!last) __syncthreads();
     }

@@ -513,18 +513,26 @@ __global__ __launch_bounds__(1024) void k_hook_window(const int32_t* __restrict_
         // Multi-Jump over the window: each vertex climbs to its local root
         // and stores it once; after the last segment the local roots of the
         // non-roots go to pi
+        // (two vertices per thread and pass, their climbs interleaved)
         const bool last = seg + 1 == kWinSegments;
-        for (uint32_t x = tid; x < span; x += nthr) {
-            uint32_t p = lds_ld(spi, x);
-            uint32_t g = lds_ld(spi, p);
-            while (g != p) {
-                p = g;
-                g = lds_ld(spi, p);
+        for (uint32_t x = tid; x < span; x += 2 * nthr) {
+            const uint32_t y = x + nthr;
+            const bool has_y = y < span;
+            uint32_t p1 = lds_ld(spi, x), p2 = lds_ld(spi, has_y ? y : x);
+            uint32_t g1 = lds_ld(spi, p1), g2 = lds_ld(spi, p2);
+            while (g1 != p1 || g2 != p2) {
+                p1 = g1;
+                p2 = g2;
+                g1 = lds_ld(spi, p1);
+                g2 = lds_ld(spi, p2);
             }
-            if (!last)
-                lds_st(spi, x, p);
-            else if (p != x)
-                st_rlx(pi + base + (int32_t)x, base + (int32_t)p);
+            if (!last) {
+                lds_st(spi, x, p1);
+                if (has_y) lds_st(spi, y, p2);
+            } else {
+                if (p1 != x) st_rlx(pi + base + (int32_t)x, base + (int32_t)p1);
+                if (has_y && p2 != y) st_rlx(pi + base + (int32_t)y, base + (int32_t)p2);
+            }
         }
         __syncthreads();
     }

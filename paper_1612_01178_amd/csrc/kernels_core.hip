@@ -349,16 +349,27 @@ __global__ __launch_bounds__(1024, 8) void k_mj_local(int32_t* pi, int32_t n) {
 __global__ __launch_bounds__(256) void k_mj1(int32_t* pi, int32_t n, const uint32_t* gate,
                                              uint32_t limit) {
     if (gate != nullptr && *gate <= limit) return;
-    for (int64_t v = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; v < n;
-         v += (int64_t)gridDim.x * blockDim.x) {
-        int32_t q = ld_tree<false>(pi + v);
-        if (q == v) continue;
-        int32_t g = ld_tree<false>(pi + q);
-        while (g != q) {
-            st_tree<false>(pi + v, g);
-            q = g;
-            g = ld_tree<false>(pi + q);
+    // Two vertices per thread and pass (v and v + blockDim.x: both loads
+    // coalesced), their climbs interleaved so that each thread keeps two
+    // dependent loads in flight; a finished climb stays on its root, whose
+    // parent is itself.  Each vertex's root is stored once, if it is not
+    // already its parent.
+    const int64_t step = (int64_t)gridDim.x * blockDim.x * 2;
+    for (int64_t v = (int64_t)blockIdx.x * blockDim.x * 2 + threadIdx.x; v < n; v += step) {
+        const int64_t w = v + blockDim.x;
+        const bool has_w = w < n;
+        const int32_t q1 = ld_tree<false>(pi + v);
+        const int32_t q2 = has_w ? ld_tree<false>(pi + w) : q1;
+        int32_t r1 = q1, r2 = q2;
+        int32_t g1 = ld_tree<false>(pi + r1), g2 = ld_tree<false>(pi + r2);
+        while (g1 != r1 || g2 != r2) {
+            r1 = g1;
+            r2 = g2;
+            g1 = ld_tree<false>(pi + r1);
+            g2 = ld_tree<false>(pi + r2);
         }
+        if (r1 != q1) st_tree<false>(pi + v, r1);
+        if (has_w && r2 != q2) st_tree<false>(pi + w, r2);
     }
 }
 
@@ -368,7 +379,7 @@ hipError_t launch_mj_deep(int32_t* pi, int32_t n, hipStream_t s) {
     if (n < (1 << 22)) return launch_mj1(pi, n, nullptr, s);
     const int grid = (int)(((int64_t)n + kMjBlock - 1) / kMjBlock);
     k_mj_local<<<grid, 1024, 0, s>>>(pi, n);
-    k_mj1<<<(int)(((int64_t)n + 255) / 256), 256, 0, s>>>(pi, n, nullptr, 0);
+    k_mj1<<<(int)(((int64_t)n + 511) / 512), 256, 0, s>>>(pi, n, nullptr, 0);
     return hipGetLastError();
 }
 
@@ -377,7 +388,7 @@ hipError_t launch_mj1(int32_t* pi, int32_t n, const uint32_t* gate, hipStream_t 
     if (n <= 0) return hipSuccess;
     // a gated launch may find nothing to do: a grid of at most 32 workgroups
     // per CU, each thread striding over vertices, exits in a few microseconds
-    int64_t grid = ((int64_t)n + 255) / 256;
+    int64_t grid = ((int64_t)n + 511) / 512;  // two vertices per thread
     if (gate != nullptr) grid = std::min<int64_t>(grid, (int64_t)device_cu_count() * 32);
     k_mj1<<<(int)grid, 256, 0, s>>>(pi, n, gate, limit);
     return hipGetLastError();

@@ -351,6 +351,46 @@ __device__ __forceinline__ void hot_climb(int32_t* pi, int32_t pu, int32_t pv, b
     }
 }
 
+// K climbs of hot_climb advanced together (a finished one has pu == pv):
+// each step issues all their loads, then all their compare-and-swaps, then
+// all their reloads, so a thread keeps K dependent chains of tree accesses in
+// flight instead of one.  Every step of each climb is the step hot_climb
+// takes.
+template <int K>
+__device__ __forceinline__ void hot_climb_k(int32_t* pi, int32_t* pu, int32_t* pv, bool halve) {
+    uint32_t step[K];
+#pragma unroll
+    for (int k = 0; k < K; ++k) step[k] = 0;
+    while (true) {
+        bool any = false;
+#pragma unroll
+        for (int k = 0; k < K; ++k) any |= pu[k] != pv[k];
+        if (!any) break;
+        int32_t H[K], L[K], f[K];
+#pragma unroll
+        for (int k = 0; k < K; ++k) {
+            H[k] = pu[k] > pv[k] ? pu[k] : pv[k];
+            L[k] = pu[k] > pv[k] ? pv[k] : pu[k];
+            f[k] = pu[k] != pv[k] ? ld_tree<false>(pi + H[k]) : H[k];
+        }
+#pragma unroll
+        for (int k = 0; k < K; ++k)
+            if (pu[k] != pv[k] && f[k] == H[k]) f[k] = cas_root(pi + H[k], H[k], L[k]);
+#pragma unroll
+        for (int k = 0; k < K; ++k) {
+            if (pu[k] == pv[k]) continue;
+            if (f[k] == H[k]) {
+                pu[k] = pv[k] = L[k];  // hooked
+            } else {
+                pu[k] = ld_tree<false>(pi + f[k]);
+                pv[k] = ld_tree<false>(pi + L[k]);
+                if (halve && pu[k] != f[k] && step[k]++ % kHalveEveryFiltered == 0)
+                    halve_to(pi + H[k], pu[k]);
+            }
+        }
+    }
+}
+
 // SLOTS slots with tags of type TagT (16384 x uint16 = 96 KiB of LDS with the
 // words, or 32768 x uint8 = 160 KiB); a tag equal to TagT's maximum marks an
 // empty slot (also used for a word index too large for the tag type).
@@ -519,9 +559,23 @@ __global__ __launch_bounds__(1024) void k_ahook_hotv(const int32_t* __restrict__
                 pb[j] = bb ? g : ld_tree<false>(pi + b[j]);
             }
         }
+        // the kept entries' climbs, kClimbs at a time (entries j, j + EPT /
+        // kClimbs, ...; an entry not kept takes part as a finished climb)
+        constexpr int kClimbs = 2;
 #pragma unroll
-        for (int j = 0; j < EPT; ++j)
-            if (act >> j & 1) hot_climb(pi, pa[j], pb[j], halve);
+        for (int j = 0; j < EPT / kClimbs; ++j) {
+            int32_t cu[kClimbs], cv[kClimbs];
+            bool anyk = false;
+#pragma unroll
+            for (int k = 0; k < kClimbs; ++k) {
+                const int e = j + k * (EPT / kClimbs);
+                const bool a = act >> e & 1;
+                cu[k] = a ? pa[e] : 0;
+                cv[k] = a ? pb[e] : 0;
+                anyk |= a;
+            }
+            if (anyk) hot_climb_k<kClimbs>(pi, cu, cv, halve);
+        }
     }
     if (bad) atomicOr(&ctrl->status, kStatusRange);
 }

@@ -191,8 +191,8 @@ def main():
                 args.segments or args.ept or args.block or args.coherent or args.symmetric):
             traffic = measured_traffic(args.workload, "atomic")
     elif st.get("hook") == 3:
-        alg_bytes = 8.0 * m  # the atomic-free round's pass over the input entries
-        kernel = "k_hook_plain + k_compact + k_ahook_pairs (all edge passes of one solve)"
+        alg_bytes = 8.0 * m  # the window round's pass over the input entries
+        kernel = "k_hook_window + k_compact + k_ahook_pairs (all edge passes of one solve)"
     else:
         alg_bytes = 8.0 * m  # first Hook pass over the input entries
         kernel = "k_hook_plain + k_compact (all edge passes of one solve)"

@@ -282,7 +282,7 @@ def main():
 
 
 ABLATION = [
-    # Fig. 5 progression, then this build's additions
+    # Fig. 5 progression, then the variants beyond the paper
     ("fig1_hostloop_jump", dict(hook="plain", host_loop="jump")),
     ("fig1_hostloop_multijump", dict(hook="plain", host_loop="multijump")),
     ("atomic_hook_s1", dict(hook="atomic", segments=1, filter="off", path_halving="off")),

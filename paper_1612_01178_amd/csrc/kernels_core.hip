@@ -231,6 +231,10 @@ hipError_t launch_ahook(const int32_t* u, const int32_t* v, int64_t begin, int64
 }
 
 // ----------------------------------------------------------------------------- K-MJ
+// 256-vertex chunks per wave in k_mj and k_mj_bitmap (two measured the same as
+// one on R-MAT 24: the hoisted loads were what paid)
+constexpr int kMjChunks = 1;
+
 // Multi-Jump (Fig. 3, bottom): for every vertex, while its grandparent
 // differs from its parent, replace the parent by the grandparent.  The new
 // parent is stored on every step, not once at the end, so that other threads
@@ -238,41 +242,56 @@ hipError_t launch_ahook(const int32_t* u, const int32_t* v, int64_t begin, int64
 // the two optimisations of Section 3.A).  Workgroups cover the vertex range in
 // increasing id order, so the low ids near the roots are flattened first (the
 // second optimisation; the hardware dispatches workgroups in index order).
-// Each thread handles 4 consecutive vertices from one 16-byte load; roots are
-// skipped at once; the 4 grandparent gathers are issued together.
+// Each lane handles 4 consecutive vertices from one 16-byte load in each of CH
+// chunks of 256 vertices per wave (wave w covers vertices [256 CH w,
+// 256 CH (w + 1))); roots are skipped at once; the chunks' loads and their
+// grandparent gathers are issued together (the pass is bound by the latency
+// of these dependent loads, not by bandwidth).
 //
 // During a Multi-Jump no root changes (only non-roots are written, and only
 // with ancestors), so "grandparent == parent" holds exactly when the parent is
 // a root: on exit every vertex points at its tree's root, i.e. at the minimum
 // id of its tree.
-template <bool VEC, bool COH>
+template <bool VEC, bool COH, int CH>
 __global__ __launch_bounds__(256) void k_mj(int32_t* pi, int32_t n, const uint32_t* gate) {
     if (gate != nullptr && *gate == 0) return;
-    const int64_t base = ((int64_t)blockIdx.x * blockDim.x + threadIdx.x) * 4;
-    int32_t p[4];
-    if (VEC && base + 3 < n) {
-        v4i q = *reinterpret_cast<const v4i*>(pi + base);
-        p[0] = q.x;
-        p[1] = q.y;
-        p[2] = q.z;
-        p[3] = q.w;
-    } else {
+    const int64_t wave = ((int64_t)blockIdx.x * blockDim.x + threadIdx.x) >> 6;
+    const int lane = threadIdx.x & 63;
+    int64_t base[CH];
 #pragma unroll
-        for (int j = 0; j < 4; ++j)
-            p[j] = (base + j < n) ? ld_tree<COH>(pi + base + j) : (int32_t)(base + j);
-    }
-    int32_t gp[4];
+    for (int c = 0; c < CH; ++c) base[c] = (wave * CH + c) * 256 + 4 * lane;
+    int32_t p[CH][4];
 #pragma unroll
-    for (int j = 0; j < 4; ++j) gp[j] = (p[j] != base + j) ? ld_tree<COH>(pi + p[j]) : p[j];
+    for (int c = 0; c < CH; ++c) {
+        if (VEC && base[c] + 3 < n) {
+            v4i q = *reinterpret_cast<const v4i*>(pi + base[c]);
+            p[c][0] = q.x;
+            p[c][1] = q.y;
+            p[c][2] = q.z;
+            p[c][3] = q.w;
+        } else {
 #pragma unroll
-    for (int j = 0; j < 4; ++j) {
-        int32_t q = p[j], g = gp[j];
-        while (g != q) {
-            st_tree<COH>(pi + base + j, g);
-            q = g;
-            g = ld_tree<COH>(pi + q);
+            for (int j = 0; j < 4; ++j)
+                p[c][j] = (base[c] + j < n) ? ld_tree<COH>(pi + base[c] + j) : (int32_t)(base[c] + j);
         }
     }
+    int32_t gp[CH][4];
+#pragma unroll
+    for (int c = 0; c < CH; ++c)
+#pragma unroll
+        for (int j = 0; j < 4; ++j)
+            gp[c][j] = (p[c][j] != base[c] + j) ? ld_tree<COH>(pi + p[c][j]) : p[c][j];
+#pragma unroll
+    for (int c = 0; c < CH; ++c)
+#pragma unroll
+        for (int j = 0; j < 4; ++j) {
+            int32_t q = p[c][j], g = gp[c][j];
+            while (g != q) {
+                st_tree<COH>(pi + base[c] + j, g);
+                q = g;
+                g = ld_tree<COH>(pi + q);
+            }
+        }
 }
 
 // Multi-Jump for deep trees (after an atomic-free Hook round every vertex
@@ -396,13 +415,13 @@ hipError_t launch_mj1(int32_t* pi, int32_t n, const uint32_t* gate, hipStream_t 
 
 hipError_t launch_mj(int32_t* pi, int32_t n, const uint32_t* gate, bool coherent, hipStream_t s) {
     if (n <= 0) return hipSuccess;
-    const int64_t groups = ((int64_t)n + 3) / 4;
-    const int grid = (int)((groups + 255) / 256);
+    const int64_t waves = ((int64_t)n + 256 * kMjChunks - 1) / (256 * kMjChunks);
+    const int grid = (int)((waves + 3) / 4);
     const bool vec = ((uintptr_t)pi & 15) == 0;
-    if (vec && coherent) k_mj<true, true><<<grid, 256, 0, s>>>(pi, n, gate);
-    else if (vec) k_mj<true, false><<<grid, 256, 0, s>>>(pi, n, gate);
-    else if (coherent) k_mj<false, true><<<grid, 256, 0, s>>>(pi, n, gate);
-    else k_mj<false, false><<<grid, 256, 0, s>>>(pi, n, gate);
+    if (vec && coherent) k_mj<true, true, kMjChunks><<<grid, 256, 0, s>>>(pi, n, gate);
+    else if (vec) k_mj<true, false, kMjChunks><<<grid, 256, 0, s>>>(pi, n, gate);
+    else if (coherent) k_mj<false, true, kMjChunks><<<grid, 256, 0, s>>>(pi, n, gate);
+    else k_mj<false, false, kMjChunks><<<grid, 256, 0, s>>>(pi, n, gate);
     return hipGetLastError();
 }
 
@@ -534,79 +553,107 @@ __device__ __forceinline__ uint32_t spread4(uint32_t x) {
 
 // Multi-Jump (as k_mj) and, when the filter is on, the giant bitmap rebuilt
 // in the same pass (as k_bitmap) and the cached words of the hot-word table
-// refreshed (as k_hot_values), instead of three passes over pi.  Each thread
-// jumps its 4 vertices to their roots; the giant's current root is found by
-// climbing from the last giant label (other threads' jumps only move values
-// up, and no hook runs, so the climb ends at the root); a vertex's bit is
-// (its root == that root).  A wave covers 256 consecutive vertices: one
-// ballot per slot j (bit l = vertex 4l + j), and lane w < 8 assembles word w
-// (vertices 32w .. 32w + 31) from byte w of the four ballots.
-template <bool VEC>
+// refreshed (as k_hot_values), instead of three passes over pi.  Each lane
+// jumps 4 consecutive vertices in each of CH chunks of 256 vertices per wave
+// (wave w covers vertices [256 CH w, 256 CH (w + 1))) to their roots; the
+// giant's current root is found by climbing from the last giant label (other
+// threads' jumps only move values up, and no hook runs, so the climb ends at
+// the root); a vertex's bit is (its root == that root).  Per chunk, one
+// ballot per slot j (bit l = vertex 4l + j of the chunk), and lane w < 8
+// assembles word w of the chunk (its vertices 32w .. 32w + 31) from byte w of
+// the four ballots.  The pass is bound by the latency of its dependent loads,
+// so every load that does not depend on pi (the filter switch, the giant
+// label and its parent, the vertex-table tags) is issued with the first pi
+// load, and the CH chunks' loads and gathers are issued together.
+template <bool VEC, int CH>
 __global__ __launch_bounds__(256) void k_mj_bitmap(int32_t* pi, int32_t n, Ctrl* ctrl,
                                                    uint32_t* __restrict__ bits,
                                                    const uint32_t* __restrict__ hot_tags,
                                                    uint32_t* __restrict__ hot_vals, int slots,
                                                    uint8_t* vtab) {
-    const int64_t base = ((int64_t)blockIdx.x * blockDim.x + threadIdx.x) * 4;
-    int32_t p[4];
-    if (VEC && base + 3 < n) {
-        v4i q = *reinterpret_cast<const v4i*>(pi + base);
-        p[0] = q.x;
-        p[1] = q.y;
-        p[2] = q.z;
-        p[3] = q.w;
-    } else {
-#pragma unroll
-        for (int j = 0; j < 4; ++j)
-            p[j] = (base + j < n) ? ld_tree<false>(pi + base + j) : (int32_t)(base + j);
-    }
-    int32_t gp[4];
-#pragma unroll
-    for (int j = 0; j < 4; ++j) gp[j] = (p[j] != base + j) ? ld_tree<false>(pi + p[j]) : p[j];
-#pragma unroll
-    for (int j = 0; j < 4; ++j) {
-        int32_t q = p[j], g = gp[j];
-        while (g != q) {
-            st_tree<false>(pi + base + j, g);
-            q = g;
-            g = ld_tree<false>(pi + q);
-        }
-        p[j] = q;  // the root
-    }
-    if (!ctrl->filter_on) return;
-    int32_t groot = ctrl->giant;
-    for (int32_t up = ld_tree<false>(pi + groot); up != groot; up = ld_tree<false>(pi + groot))
-        groot = up;
     const int lane = threadIdx.x & 63;
-    uint64_t m4[4];
+    const int64_t wave = ((int64_t)blockIdx.x * blockDim.x + threadIdx.x) >> 6;
+    int64_t base[CH];
 #pragma unroll
-    for (int j = 0; j < 4; ++j) m4[j] = __ballot(base + j < n && p[j] == groot);
-    if (vtab && base < n && (uint32_t)base / kVertSets < kVertTagNone) {
+    for (int c = 0; c < CH; ++c) base[c] = (wave * CH + c) * 256 + 4 * lane;
+    const int32_t fon = ctrl->filter_on;
+    int32_t groot = ctrl->giant;
+    int32_t up = fon ? ld_tree<false>(pi + groot) : groot;
+    uint64_t tags[CH];
+    bool has_tags[CH];
+#pragma unroll
+    for (int c = 0; c < CH; ++c) {
         // the sets of base .. base + 3 (same tag: kVertSets is a multiple of
-        // 4) and their 8 tag bytes; a member flag is written only by the
-        // vertex its slot holds
-        const uint32_t k = (uint32_t)base / kVertSets;
-        const uint32_t s0 = (uint32_t)base % kVertSets;
-        const uint64_t tags = *reinterpret_cast<const uint64_t*>(vtab + 2 * s0);
-        uint8_t* mem = vtab + kVertSlots + 2 * s0;
+        // 4) and their 8 tag bytes
+        has_tags[c] = fon && vtab && base[c] < n && (uint32_t)base[c] / kVertSets < kVertTagNone;
+        tags[c] = has_tags[c] ? *reinterpret_cast<const uint64_t*>(vtab + 2 * ((uint32_t)base[c] % kVertSets))
+                              : 0;
+    }
+    int32_t p[CH][4];
+#pragma unroll
+    for (int c = 0; c < CH; ++c) {
+        if (VEC && base[c] + 3 < n) {
+            v4i q = *reinterpret_cast<const v4i*>(pi + base[c]);
+            p[c][0] = q.x;
+            p[c][1] = q.y;
+            p[c][2] = q.z;
+            p[c][3] = q.w;
+        } else {
+#pragma unroll
+            for (int j = 0; j < 4; ++j)
+                p[c][j] = (base[c] + j < n) ? ld_tree<false>(pi + base[c] + j) : (int32_t)(base[c] + j);
+        }
+    }
+    int32_t gp[CH][4];
+#pragma unroll
+    for (int c = 0; c < CH; ++c)
 #pragma unroll
         for (int j = 0; j < 4; ++j)
+            gp[c][j] = (p[c][j] != base[c] + j) ? ld_tree<false>(pi + p[c][j]) : p[c][j];
 #pragma unroll
-            for (int w = 0; w < kVertWays; ++w)
-                if (base + j < n && (uint32_t)(tags >> (8 * (2 * j + w)) & 0xffu) == k)
-                    mem[2 * j + w] = p[j] == groot ? 1 : 0;
+    for (int c = 0; c < CH; ++c)
+#pragma unroll
+        for (int j = 0; j < 4; ++j) {
+            int32_t q = p[c][j], g = gp[c][j];
+            while (g != q) {
+                st_tree<false>(pi + base[c] + j, g);
+                q = g;
+                g = ld_tree<false>(pi + q);
+            }
+            p[c][j] = q;  // the root
+        }
+    if (!fon) return;
+    while (up != groot) {
+        groot = up;
+        up = ld_tree<false>(pi + groot);
     }
-    if (lane < 8) {
-        const int64_t wave_base = base - 4 * lane;  // vertex of lane 0
-        const int64_t w = wave_base / 32 + lane;
-        if (w * 32 < n) {
-            uint32_t word = 0;
 #pragma unroll
-            for (int j = 0; j < 4; ++j) word |= spread4((uint32_t)(m4[j] >> (8 * lane)) & 0xffu) << j;
-            bits[w] = word;
-            if (hot_tags) {
-                const uint32_t slot = (uint32_t)w & (uint32_t)(slots - 1);
-                if (hot_tags[slot] == (uint32_t)(w / slots)) hot_vals[slot] = word;
+    for (int c = 0; c < CH; ++c) {
+        uint64_t m4[4];
+#pragma unroll
+        for (int j = 0; j < 4; ++j) m4[j] = __ballot(base[c] + j < n && p[c][j] == groot);
+        if (has_tags[c]) {
+            // a member flag is written only by the vertex its slot holds
+            const uint32_t k = (uint32_t)base[c] / kVertSets;
+            uint8_t* mem = vtab + kVertSlots + 2 * ((uint32_t)base[c] % kVertSets);
+#pragma unroll
+            for (int j = 0; j < 4; ++j)
+#pragma unroll
+                for (int w = 0; w < kVertWays; ++w)
+                    if (base[c] + j < n && (uint32_t)(tags[c] >> (8 * (2 * j + w)) & 0xffu) == k)
+                        mem[2 * j + w] = p[c][j] == groot ? 1 : 0;
+        }
+        if (lane < 8) {
+            const int64_t w = (wave * CH + c) * 8 + lane;  // word of vertices 32w .. 32w + 31
+            if (w * 32 < n) {
+                uint32_t word = 0;
+#pragma unroll
+                for (int j = 0; j < 4; ++j) word |= spread4((uint32_t)(m4[j] >> (8 * lane)) & 0xffu) << j;
+                bits[w] = word;
+                if (hot_tags) {
+                    const uint32_t slot = (uint32_t)w & (uint32_t)(slots - 1);
+                    if (hot_tags[slot] == (uint32_t)(w / slots)) hot_vals[slot] = word;
+                }
             }
         }
     }
@@ -618,12 +665,12 @@ hipError_t launch_mj_bitmap(int32_t* pi, int32_t n, Ctrl* ctrl, uint32_t* bits,
                             hipStream_t s) {
     if (n <= 0) return hipSuccess;
     if (hot_tags && slots != 16384 && slots != 32768) return hipErrorInvalidValue;
-    const int64_t groups = ((int64_t)n + 3) / 4;
-    const int grid = (int)((groups + 255) / 256);
+    const int64_t waves = ((int64_t)n + 256 * kMjChunks - 1) / (256 * kMjChunks);
+    const int grid = (int)((waves + 3) / 4);
     if (((uintptr_t)pi & 15) == 0)
-        k_mj_bitmap<true><<<grid, 256, 0, s>>>(pi, n, ctrl, bits, hot_tags, hot_vals, slots, vtab);
+        k_mj_bitmap<true, kMjChunks><<<grid, 256, 0, s>>>(pi, n, ctrl, bits, hot_tags, hot_vals, slots, vtab);
     else
-        k_mj_bitmap<false><<<grid, 256, 0, s>>>(pi, n, ctrl, bits, hot_tags, hot_vals, slots, vtab);
+        k_mj_bitmap<false, kMjChunks><<<grid, 256, 0, s>>>(pi, n, ctrl, bits, hot_tags, hot_vals, slots, vtab);
     return hipGetLastError();
 }
 

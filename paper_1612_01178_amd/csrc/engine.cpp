@@ -1469,7 +1469,7 @@ int32_t batch_lds_impl(int32_t B, const int64_t* vo, const int64_t* eo, const in
     const size_t desc_off = sizeof(Ctrl);
     const size_t rows_off = desc_off + align256((size_t)B * sizeof(GraphDesc));
     const size_t off_bytes = align256(((size_t)B + 1) * 8);  // one offset array
-    const size_t offs_off = rows_off + align256(((size_t)B + 1023) / 1024 * 256 * 4);
+    const size_t offs_off = rows_off + align256((((size_t)B + 1023) / 1024 + 1) * 256 * 4);
     const size_t total = offs_off + (staged ? 2 * off_bytes : 0);
     HIPCHK(prepare_batch_lds());
     PoolEntry* pe = pool_entry(s);

@@ -166,7 +166,8 @@ hipError_t launch_batch_lds(const GraphDesc* descs, int32_t count, int32_t max_n
                             hipStream_t s, int block = 1024);
 
 // Descriptors of a batch with device offsets, largest first (two launches,
-// one thread per graph); `rows` is scratch of ceil(B / 1024) x 256 int32.
+// one thread per graph, with a scan launch between them above 32,768
+// graphs); `rows` is scratch of (ceil(B / 1024) + 1) x 256 int32.
 // Clears ctrl->queue_head; status[1] / status[2] get kStatusBadGraph /
 // kStatusRange for invalid graphs (status may be pinned host memory).
 hipError_t launch_batch_prep(const int64_t* vo, const int64_t* eo, int32_t B, const int32_t* u,

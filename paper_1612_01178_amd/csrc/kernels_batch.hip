@@ -326,18 +326,62 @@ __global__ __launch_bounds__(1024) void k_batch_prep_count(const int64_t* __rest
     if (blockIdx.x == 0 && tid == 0) ctrl->queue_head = 0;
 }
 
+// Up to this many preparation workgroups, each placing workgroup sums the
+// rows of all of them itself (W x 256 loads each); above it a scan launch
+// turns the rows into prefix sums first, so that the work stays linear in B.
+constexpr int32_t kPrepLoopMaxW = 32;
+
+// Step 1b (only when W > kPrepLoopMaxW; one workgroup per class c): column c
+// of `rows` becomes the exclusive prefix sums over the workgroups (row w: the
+// graphs of class c in workgroups before w), and totals[c] its sum.  Thread t
+// takes a run of consecutive rows.
+__global__ __launch_bounds__(1024) void k_batch_prep_scan(int32_t* __restrict__ rows, int32_t W,
+                                                          int32_t* __restrict__ totals) {
+    __shared__ int32_t wsum[16];
+    const int32_t c = blockIdx.x, tid = threadIdx.x;
+    const int32_t lane = tid & 63, wave = tid >> 6;
+    const int32_t per = (W + 1023) / 1024;
+    const int32_t w0 = min(W, tid * per), w1 = min(W, w0 + per);
+    int32_t sum = 0;
+    for (int32_t w = w0; w < w1; ++w) sum += rows[(int64_t)w * 256 + c];
+    int32_t incl = sum;
+#pragma unroll
+    for (int d = 1; d < 64; d <<= 1) {
+        const int32_t t = __shfl_up(incl, d, 64);
+        if (lane >= d) incl += t;
+    }
+    if (lane == 63) wsum[wave] = incl;
+    __syncthreads();
+    int32_t at = incl - sum, all = 0;
+    for (int32_t i = 0; i < 16; ++i) {
+        at += i < wave ? wsum[i] : 0;
+        all += wsum[i];
+    }
+    for (int32_t w = w0; w < w1; ++w) {
+        const int32_t r = rows[(int64_t)w * 256 + c];
+        rows[(int64_t)w * 256 + c] = at;
+        at += r;
+    }
+    if (tid == 0) totals[c] = all;
+}
+
 // Step 2: each workgroup finds where its graphs of each class go (all
 // earlier classes of every workgroup, then this class of the earlier
-// workgroups) and writes their descriptors there.
+// workgroups) and writes their descriptors there.  `totals` null: `rows`
+// holds the per-workgroup counts; else the scanned rows and the totals.
 __global__ __launch_bounds__(1024) void k_batch_prep_place(
     const int64_t* __restrict__ vo, const int64_t* __restrict__ eo, int32_t B, const int32_t* u,
     const int32_t* v, int32_t* out, int32_t max_n, int32_t seg_cap,
-    const int32_t* __restrict__ rows, int32_t W, GraphDesc* __restrict__ descs, int32_t* status) {
+    const int32_t* __restrict__ rows, const int32_t* __restrict__ totals, int32_t W,
+    GraphDesc* __restrict__ descs, int32_t* status) {
     __shared__ int32_t base[256];
     __shared__ int32_t flags;
     const int32_t tid = threadIdx.x;
     int32_t total = 0, before = 0;
-    if (tid < 256) {
+    if (tid < 256 && totals) {
+        total = totals[tid];
+        before = rows[(int64_t)blockIdx.x * 256 + tid];
+    } else if (tid < 256) {
         for (int32_t w = 0; w < W; ++w) {
             const int32_t r = rows[w * 256 + tid];
             total += r;
@@ -401,8 +445,15 @@ hipError_t launch_batch_prep(const int64_t* vo, const int64_t* eo, int32_t B, co
                                                  ctrl);
     hipError_t e = hipGetLastError();
     if (e != hipSuccess) return e;
-    k_batch_prep_place<<<W, kPrepGraphs, 0, s>>>(vo, eo, B, u, v, out, max_n, seg_cap, rows, W,
-                                                 descs, status);
+    int32_t* totals = nullptr;
+    if (W > kPrepLoopMaxW) {
+        totals = rows + (int64_t)W * 256;
+        k_batch_prep_scan<<<256, 1024, 0, s>>>(rows, W, totals);
+        e = hipGetLastError();
+        if (e != hipSuccess) return e;
+    }
+    k_batch_prep_place<<<W, kPrepGraphs, 0, s>>>(vo, eo, B, u, v, out, max_n, seg_cap, rows, totals,
+                                                 W, descs, status);
     return hipGetLastError();
 }
 

@@ -402,6 +402,44 @@ def test_batch_device_offsets_match_oracle(dev):
     assert np.array_equal(got, oracle.labels_batch(bu, bv, bvo, beo))
 
 
+def test_batch_preparation_scan_path(dev):
+    """More than 32 preparation workgroups (32,768 graphs): a scan launch
+    turns the per-workgroup class counts into prefix sums before the
+    descriptors are placed.  Sizes spread over many classes, with empty
+    graphs; offsets on the device and on the host; an invalid graph among
+    them is reported and the valid ones are still solved."""
+    import torch
+    rs = np.random.default_rng(19)
+    B = 40000
+    nv = rs.integers(0, 40, B).astype(np.int64)
+    nv[rs.integers(0, B, 25)] = rs.integers(1000, 5000, 25)
+    me = (nv * rs.uniform(0.0, 1.5, B)).astype(np.int64)
+    me[nv == 0] = 0
+    vo = np.concatenate([[0], np.cumsum(nv)]).astype(np.int64)
+    eo = np.concatenate([[0], np.cumsum(me)]).astype(np.int64)
+    gid = np.repeat(np.arange(B), me)
+    u = (rs.random(len(gid)) * nv[gid]).astype(np.int32)
+    v = (rs.random(len(gid)) * nv[gid]).astype(np.int32)
+    want = oracle.labels_batch(u, v, vo, eo)
+    say("batch scan path", B, int(vo[-1]), int(eo[-1]))
+    got = _batch_device(u, v, vo, eo, dev, 5000).cpu().numpy()
+    assert np.array_equal(got, want)
+    got = cc.labels_batch(to_dev(u, dev), to_dev(v, dev), vo, eo).cpu().numpy()
+    assert np.array_equal(got, want)
+    # the largest graph above max_n: CC_ERR_ARG, the other graphs' labels written
+    big = int(np.argmax(nv))
+    out = torch.full((int(vo[-1]),), -1, dtype=torch.int32, device=dev)
+    with pytest.raises(cc.CCError) as ei:
+        cc.labels_batch_device(to_dev(u, dev), to_dev(v, dev), to_dev64(vo, dev),
+                               to_dev64(eo, dev), int(nv[big]) - 1, out)
+    assert ei.value.code == cc.CC_ERR_ARG
+    got = out.cpu().numpy()
+    keep = np.ones(int(vo[-1]), bool)
+    keep[vo[big]:vo[big + 1]] = False
+    assert np.array_equal(got[keep], want[keep])
+    assert (got[~keep] == -1).all()
+
+
 def test_batch_device_offsets_errors_and_replays(dev):
     import torch
     u = np.array([0, 1, 1, 2], np.int32)

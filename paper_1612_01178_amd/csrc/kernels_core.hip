@@ -359,37 +359,69 @@ __global__ __launch_bounds__(1024, 8) void k_mj_local(int32_t* pi, int32_t n) {
         }
 }
 
-// Multi-Jump with one vertex per thread, for the atomic-free path: after
-// k_mj_local, or after a round that hooked roots, most climbs are a
-// dependent load or two, and a thread holding four vertices would run their
-// climbs one after the other (a 4096^2 grid: 0.575 -> 0.537 ms; ER 2^16
-// rounds: 0.100 -> 0.090 ms).  The Atomic-Hook path keeps k_mj, whose
-// 16-byte loads win on its shallow trees (R-MAT 24: 3.75 against 3.78 ms).
+// Multi-Jump with one-word loads, for the atomic-free and hybrid paths:
+// after k_mj_local, or after a round that hooked roots, most climbs are a
+// dependent load or two, and k_mj's four consecutive vertices per thread
+// would run their climbs one after the other (a 4096^2 grid: 0.575 -> 0.537
+// ms; ER 2^16 rounds: 0.100 -> 0.090 ms); here a thread's V vertices climb
+// interleaved.  The Atomic-Hook path keeps k_mj, whose 16-byte loads win on
+// its shallow trees (R-MAT 24: 3.75 against 3.78 ms).
+template <int V>
 __global__ __launch_bounds__(256) void k_mj1(int32_t* pi, int32_t n, const uint32_t* gate,
                                              uint32_t limit) {
     if (gate != nullptr && *gate <= limit) return;
-    // Two vertices per thread and pass (v and v + blockDim.x: both loads
-    // coalesced), their climbs interleaved so that each thread keeps two
+    // V vertices per thread and pass (v, v + blockDim.x, ...: every load
+    // coalesced), their climbs interleaved so that each thread keeps V
     // dependent loads in flight; a finished climb stays on its root, whose
     // parent is itself.  Each vertex's root is stored once, if it is not
     // already its parent.
-    const int64_t step = (int64_t)gridDim.x * blockDim.x * 2;
-    for (int64_t v = (int64_t)blockIdx.x * blockDim.x * 2 + threadIdx.x; v < n; v += step) {
-        const int64_t w = v + blockDim.x;
-        const bool has_w = w < n;
-        const int32_t q1 = ld_tree<false>(pi + v);
-        const int32_t q2 = has_w ? ld_tree<false>(pi + w) : q1;
-        int32_t r1 = q1, r2 = q2;
-        int32_t g1 = ld_tree<false>(pi + r1), g2 = ld_tree<false>(pi + r2);
-        while (g1 != r1 || g2 != r2) {
-            r1 = g1;
-            r2 = g2;
-            g1 = ld_tree<false>(pi + r1);
-            g2 = ld_tree<false>(pi + r2);
+    const int64_t step = (int64_t)gridDim.x * blockDim.x * V;
+    for (int64_t v = (int64_t)blockIdx.x * blockDim.x * V + threadIdx.x; v < n; v += step) {
+        int32_t q[V], r[V], g[V];
+#pragma unroll
+        for (int k = 0; k < V; ++k) {
+            const int64_t w = v + (int64_t)k * blockDim.x;
+            q[k] = w < n ? ld_tree<false>(pi + w) : 0;  // vertex 0 stands in past n
         }
-        if (r1 != q1) st_tree<false>(pi + v, r1);
-        if (has_w && r2 != q2) st_tree<false>(pi + w, r2);
+#pragma unroll
+        for (int k = 0; k < V; ++k) {
+            r[k] = q[k];
+            g[k] = ld_tree<false>(pi + r[k]);
+        }
+        bool more = false;
+#pragma unroll
+        for (int k = 0; k < V; ++k) more |= g[k] != r[k];
+        while (more) {
+            more = false;
+#pragma unroll
+            for (int k = 0; k < V; ++k) {
+                r[k] = g[k];
+                g[k] = ld_tree<false>(pi + r[k]);
+                more |= g[k] != r[k];
+            }
+        }
+#pragma unroll
+        for (int k = 0; k < V; ++k) {
+            const int64_t w = v + (int64_t)k * blockDim.x;
+            if (w < n && r[k] != q[k]) st_tree<false>(pi + w, r[k]);
+        }
     }
+}
+
+// k_mj1 with V vertices per thread: four where that still gives every CU at
+// least 8 workgroups (a 4096^2 grid's final Multi-Jump: 42 -> 35 us; eight
+// per thread no better), else two (ER 2^16: four leaves 64 workgroups).
+static hipError_t mj1_launch(int32_t* pi, int32_t n, const uint32_t* gate, uint32_t limit,
+                             bool capped, hipStream_t s) {
+    const int64_t cus = device_cu_count();
+    const int V = (int64_t)n >= 256 * 4 * 8 * cus ? 4 : 2;
+    int64_t grid = ((int64_t)n + 256 * V - 1) / (256 * V);
+    if (capped) grid = std::min<int64_t>(grid, cus * 32);
+    if (V == 4)
+        k_mj1<4><<<(int)grid, 256, 0, s>>>(pi, n, gate, limit);
+    else
+        k_mj1<2><<<(int)grid, 256, 0, s>>>(pi, n, gate, limit);
+    return hipGetLastError();
 }
 
 hipError_t launch_mj_deep(int32_t* pi, int32_t n, hipStream_t s) {
@@ -398,8 +430,7 @@ hipError_t launch_mj_deep(int32_t* pi, int32_t n, hipStream_t s) {
     if (n < (1 << 22)) return launch_mj1(pi, n, nullptr, s);
     const int grid = (int)(((int64_t)n + kMjBlock - 1) / kMjBlock);
     k_mj_local<<<grid, 1024, 0, s>>>(pi, n);
-    k_mj1<<<(int)(((int64_t)n + 511) / 512), 256, 0, s>>>(pi, n, nullptr, 0);
-    return hipGetLastError();
+    return mj1_launch(pi, n, nullptr, 0, false, s);
 }
 
 hipError_t launch_mj1(int32_t* pi, int32_t n, const uint32_t* gate, hipStream_t s,
@@ -407,10 +438,7 @@ hipError_t launch_mj1(int32_t* pi, int32_t n, const uint32_t* gate, hipStream_t 
     if (n <= 0) return hipSuccess;
     // a gated launch may find nothing to do: a grid of at most 32 workgroups
     // per CU, each thread striding over vertices, exits in a few microseconds
-    int64_t grid = ((int64_t)n + 511) / 512;  // two vertices per thread
-    if (gate != nullptr) grid = std::min<int64_t>(grid, (int64_t)device_cu_count() * 32);
-    k_mj1<<<(int)grid, 256, 0, s>>>(pi, n, gate, limit);
-    return hipGetLastError();
+    return mj1_launch(pi, n, gate, limit, gate != nullptr, s);
 }
 
 hipError_t launch_mj(int32_t* pi, int32_t n, const uint32_t* gate, bool coherent, hipStream_t s) {

@@ -355,9 +355,15 @@ __device__ __forceinline__ void hot_climb(int32_t* pi, int32_t pu, int32_t pv, b
 // each step issues all their loads, then all their compare-and-swaps, then
 // all their reloads, so a thread keeps K dependent chains of tree accesses in
 // flight instead of one.  Every step of each climb is the step hot_climb
-// takes.
+// takes, except that a climb whose bit is set in `root` starts at the
+// compare-and-swap: the larger of its two starting values is an endpoint
+// that was its own parent when its parent was gathered, so the load that
+// would check that it is a root is skipped (if it no longer is one, the
+// compare-and-swap fails and returns its parent, the value the load would
+// have read, and the climb goes on from there as after that load).
 template <int K>
-__device__ __forceinline__ void hot_climb_k(int32_t* pi, int32_t* pu, int32_t* pv, bool halve) {
+__device__ __forceinline__ void hot_climb_k(int32_t* pi, int32_t* pu, int32_t* pv, bool halve,
+                                            uint32_t root) {
     uint32_t step[K];
 #pragma unroll
     for (int k = 0; k < K; ++k) step[k] = 0;
@@ -371,8 +377,9 @@ __device__ __forceinline__ void hot_climb_k(int32_t* pi, int32_t* pu, int32_t* p
         for (int k = 0; k < K; ++k) {
             H[k] = pu[k] > pv[k] ? pu[k] : pv[k];
             L[k] = pu[k] > pv[k] ? pv[k] : pu[k];
-            f[k] = pu[k] != pv[k] ? ld_tree<false>(pi + H[k]) : H[k];
+            f[k] = pu[k] != pv[k] && !(root >> k & 1) ? ld_tree<false>(pi + H[k]) : H[k];
         }
+        root = 0;
 #pragma unroll
         for (int k = 0; k < K; ++k)
             if (pu[k] != pv[k] && f[k] == H[k]) f[k] = cas_root(pi + H[k], H[k], L[k]);
@@ -566,15 +573,21 @@ __global__ __launch_bounds__(1024) void k_ahook_hotv(const int32_t* __restrict__
         for (int j = 0; j < EPT / kClimbs; ++j) {
             int32_t cu[kClimbs], cv[kClimbs];
             bool anyk = false;
+            // bit k of root: the larger start of climb k is an endpoint that
+            // was its own parent (a wrong bit would only cost a failed CAS)
+            uint32_t root = 0;
 #pragma unroll
             for (int k = 0; k < kClimbs; ++k) {
                 const int e = j + k * (EPT / kClimbs);
-                const bool a = act >> e & 1;
-                cu[k] = a ? pa[e] : 0;
-                cv[k] = a ? pb[e] : 0;
-                anyk |= a;
+                const bool on = act >> e & 1;
+                cu[k] = on ? pa[e] : 0;
+                cv[k] = on ? pb[e] : 0;
+                anyk |= on;
+                const bool ra = cu[k] > cv[k] && cu[k] == a[e];
+                const bool rb = cv[k] > cu[k] && cv[k] == b[e];
+                root |= (uint32_t)(ra || rb) << k;
             }
-            if (anyk) hot_climb_k<kClimbs>(pi, cu, cv, halve);
+            if (anyk) hot_climb_k<kClimbs>(pi, cu, cv, halve, root);
         }
     }
     if (bad) atomicOr(&ctrl->status, kStatusRange);

@@ -381,7 +381,8 @@ __global__ __launch_bounds__(256) void k_mj1(int32_t* pi, int32_t n, const uint3
 #pragma unroll
         for (int k = 0; k < V; ++k) {
             const int64_t w = v + (int64_t)k * blockDim.x;
-            q[k] = w < n ? ld_tree<false>(pi + w) : 0;  // vertex 0 stands in past n
+            // past n: vertex 0, always a root (pi[x] <= x), so that climb ends at once
+            q[k] = w < n ? ld_tree<false>(pi + w) : 0;
         }
 #pragma unroll
         for (int k = 0; k < V; ++k) {

@@ -523,10 +523,16 @@ FilterBufs filter_bufs(char* base, const Layout& L) {
 
 // Growth factor of the super-segments hooked after the giant filter is on:
 // with the filter, later segments hook few edges, so they are taken in
-// launches of 1, 4, 16, ... segments (each followed by a Multi-Jump and a
-// bitmap refresh).  Measured on R-MAT 24 (s = 512): x2 3.81 ms, x4 3.76 ms,
+// launches of 2, 8, 32, ... segments (from kSuperStart times the unfiltered
+// prefix; each launch followed by a Multi-Jump and a bitmap refresh).
+// Measured on R-MAT 24 (s = 512, from 1 segment): x2 3.81 ms, x4 3.76 ms,
 // x8 3.88 ms -- fewer refreshes against a staler bitmap.
 constexpr int64_t kSuperGrowth = 4;
+// Segments of the first filtered launch, as a multiple of the unfiltered
+// prefix (filter_after segments): R-MAT 24 (s = 512, launches of 2, 8, 32,
+// 128 and 341 segments) 3.58 ms against 3.63 ms for 1, 3.64 for 4 and 3.61
+// for 8; the same graph as CSR 4.74 against 4.76 ms for 1.
+constexpr int64_t kSuperStart = 2;
 
 int32_t enqueue_atomic(int32_t n, const int32_t* u, const int32_t* v, int64_t m, int32_t* pi,
                        const Plan& p, Ctrl* ctrl, const FilterBufs& fb, hipStream_t s, Timer& tm,
@@ -573,7 +579,7 @@ int32_t enqueue_atomic(int32_t n, const int32_t* u, const int32_t* v, int64_t m,
         }
         // The rest of the list in super-segments that grow by kSuperGrowth,
         // each followed by a Compress and a bitmap refresh.
-        int64_t g = fa, step = fa;
+        int64_t g = fa, step = kSuperStart * fa;
         while (g < S) {
             const int64_t h = std::min<int64_t>(S, g + step);
             if (hot)
@@ -1132,7 +1138,7 @@ int32_t csr_impl(int32_t n, const int64_t* row_ptr, const int32_t* col, int64_t 
         // endpoints sampled from col[] (the second endpoints of the entries)
         TIMED(kPhaseOther, launch_sample_giant(col, m, out, n, ctrl, 2048, s));
         TIMED(kPhaseOther, launch_bitmap(out, n, ctrl, bits, s));
-        int64_t g = fa, step = fa;
+        int64_t g = fa, step = kSuperStart * fa;
         while (g < S) {
             const int64_t h = std::min<int64_t>(S, g + step);
             TIMED(kPhaseHook, launch_ahook_csr(row_ptr, col, n, bound(g), bound(h), out, ctrl, bits,

@@ -627,9 +627,10 @@ hipError_t launch_batch_lds(const GraphDesc* descs, int32_t count, int32_t max_n
     if (block < 64 || block > 1024 || block % 64) return hipErrorInvalidValue;
     // 32-bit slots for graphs of at most kWideMaxN vertices, 16-bit above
     const size_t lds = (uint32_t)max_n <= kWideMaxN ? (size_t)max_n * 4 : (size_t)kWideMaxN * 4;
-    // persistent: as many workgroups as fit on the CUs at once (LDS and
-    // thread limits), at most 32 waves per CU
-    const int per_cu = (int)std::max<size_t>(1, std::min<size_t>((size_t)(160 * 1024) / lds,
+    // persistent: as many workgroups as fit on the CUs at once (LDS, with a
+    // margin for the kernel's own static LDS, and thread limits), at most 32
+    // waves per CU
+    const int per_cu = (int)std::max<size_t>(1, std::min<size_t>((size_t)(160 * 1024) / (lds + 256),
                                                                  (size_t)(2048 / block)));
     if (halve)
         k_batch_lds<true><<<grid * per_cu, block, lds, s>>>(descs, count, queue_head, status);

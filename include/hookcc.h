@@ -307,11 +307,12 @@ int32_t cc_labels_batch_ex(int32_t num_graphs, const int64_t* vtx_off, const int
                            const cc_options* opts, void* stream, cc_stats* stats);
 
 /* As cc_labels_batch_ex with the offsets in DEVICE memory: the batch needs
- * no host pass at all.  One preparation workgroup reads the offsets, checks
- * them, orders the graphs largest first (a counting sort on the size class
- * of m_g + n_g, as the host-offset call does) and writes their descriptors;
- * then the persistent LDS launch solves them.  A call is two launches and
- * one synchronisation on `stream`, whatever the number of graphs.
+ * no host pass at all.  Preparation launches of one thread per graph read
+ * the offsets, check them, order the graphs largest first (a counting sort
+ * on the size class of m_g + n_g, as the host-offset call does) and write
+ * their descriptors; then the persistent LDS launch solves them.  A call is
+ * three launches (four above 32,768 graphs, where a scan launch keeps the
+ * ordering linear in the graph count) and one synchronisation on `stream`.
  *   vtx_off, edge_off  [device] int64[B+1], as for cc_labels_batch
  *   edges_u/v          [device] int32[edge_off[B]], local ids (NULL only if no graph
  *                      has entries)
@@ -325,8 +326,8 @@ int32_t cc_labels_batch_ex(int32_t num_graphs, const int64_t* vtx_off, const int
  * label is written for the offending graphs and the call returns
  * CC_ERR_ARG after the synchronisation.  `opts` (nullable) takes
  * `segments`, `path_halving`, `block` and `graph` as for cc_labels_batch_ex;
- * the device memory it needs (256 + 40 B per graph) comes from the stream's
- * pool.  Returns CC_OK, CC_ERR_ARG, CC_ERR_RANGE, CC_ERR_NOMEM or CC_ERR_HIP. */
+ * the device memory it needs (256 B, plus 40 B per graph, plus 1 KiB per
+ * 1,024 graphs and 1 KiB) comes from the stream's pool.  Returns CC_OK, CC_ERR_ARG, CC_ERR_RANGE, CC_ERR_NOMEM or CC_ERR_HIP. */
 int32_t cc_labels_batch_device(int32_t num_graphs, const int64_t* vtx_off,
                                const int64_t* edge_off, const int32_t* edges_u,
                                const int32_t* edges_v, int32_t* out_label, int32_t max_n,
